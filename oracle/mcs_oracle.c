@@ -1,0 +1,750 @@
+/*
+ * FP64 CPU oracle for the gradient-guided Monte Carlo SLAM particle update.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the HIP library is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it.  It shares no
+ * code, header, table or constant with the HIP library; both are fed from the
+ * seeded generators in the `synth` package.
+ *
+ * Paper: T. Nakao et al., "Range-based 6-DoF Monte Carlo SLAM with
+ * Gradient-guided Particle Filter on GPU" (arXiv 2504.18056).
+ *
+ * What it computes, per particle i and pose T_i = (t_i, q_i):
+ *   prediction   T_i <- T_i * dT * Exp(delta_i)                     (Sec. III-B, Eq. 1)
+ *   likelihood   l_i = sum_j ln(G(u_ij) + eps), G trilinear in a
+ *                likelihood grid exp(-d^2 / 2 sigma^2) sampled at voxel
+ *                centres; u = (R p_j + t - o)/h - 1/2 in index units.
+ *                The paper's likelihood is the GICP registration error of
+ *                Eq. 2-4 (Sec. III-C.1); the grid likelihood replaces it here
+ *                and keeps its structure: a sum of per-point log terms of the
+ *                scan transformed by the particle pose, summed over neighbour
+ *                keyframes (Eq. 2) when several keyframe grids are used.
+ *   gradient     g = d l(T Exp(xi)) / d xi at xi = 0, xi = [rho; phi]
+ *                (right perturbation, translation first, as in Eq. 7).
+ *   pose step    psi = [a_t g_rho; a_r g_phi], each block clamped in norm,
+ *                T <- T Exp(psi)                                    (Sec. III-C.2, Eq. 7)
+ *   weighting    logw_i += beta * l_i                               (Sec. III-D, Eq. 11)
+ *   normalising  L = logsumexp(logw), logw -= L, ESS = 1 / sum w^2
+ *   resampling   systematic: a_k = min{i : CDF_i > (u + k)/N}; compare the
+ *                paper's dead-particle pruning (Sec. III-F), which respawns
+ *                particles from the weights of the remaining ones.
+ *
+ * Conventions: quaternions are Hamilton (w, x, y, z), active body-to-world;
+ * poses are rows [tx ty tz qw qx qy qz]; grids are x-fastest with samples at
+ * origin + (i + 1/2) h; a point is inside the grid when 0 <= u_a < n_a - 1 on
+ * every axis (a NaN coordinate is outside).  Every quantity is FP64; FP32
+ * inputs (scan, poses, grid values) are promoted exactly and the quaternion is
+ * renormalised in FP64.  Sums run in ascending index order.
+ *
+ * Built with gcc -O2 -fopenmp -ffp-contract=off (no fast-math); OpenMP runs
+ * over particles only, so results do not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* SO(3) / SE(3)                                                             */
+/* ------------------------------------------------------------------------ */
+
+static void quat_normalize(double q[4])
+{
+    double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    q[0] /= n; q[1] /= n; q[2] /= n; q[3] /= n;
+}
+
+/* Rotation matrix (row-major) of a unit quaternion. */
+static void quat_to_rot(const double q[4], double R[9])
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);       R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+/* Hamilton product a (x) b. */
+static void quat_mul(const double a[4], const double b[4], double o[4])
+{
+    double r[4];
+    r[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    r[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    r[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    r[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    memcpy(o, r, sizeof r);
+}
+
+/* sin(x)/x, exact at 0. */
+static double sinc(double x)
+{
+    if (fabs(x) < 1e-6) return 1.0 - x * x / 6.0;
+    return sin(x) / x;
+}
+
+/* Unit quaternion of exp([phi]x): [cos(th/2), sin(th/2) phi/th]. */
+static void so3_exp_quat(const double phi[3], double q[4])
+{
+    double th = sqrt(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
+    double s = 0.5 * sinc(0.5 * th);          /* sin(th/2)/th */
+    q[0] = cos(0.5 * th);
+    q[1] = s * phi[0]; q[2] = s * phi[1]; q[3] = s * phi[2];
+}
+
+/* Left Jacobian V(phi) = I + a [phi]x + b [phi]x^2 with
+ * a = (1 - cos th)/th^2 = (1/2) sinc(th/2)^2 and b = (th - sin th)/th^3. */
+static void so3_V(const double phi[3], double V[9])
+{
+    double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+    double th = sqrt(th2);
+    double sh = sinc(0.5 * th);
+    double a = 0.5 * sh * sh;
+    double b;
+    if (th < 0.1) {
+        /* Taylor series of (th - sin th)/th^3; the next term is below 2e-20. */
+        b = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0 - th2 * th2 * th2 / 362880.0
+            + th2 * th2 * th2 * th2 / 39916800.0;
+    } else {
+        b = (th - sin(th)) / (th2 * th);
+    }
+    double K[9] = {0.0, -phi[2], phi[1], phi[2], 0.0, -phi[0], -phi[1], phi[0], 0.0};
+    double K2[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int m = 0; m < 3; ++m) s += K[3 * r + m] * K[3 * m + c];
+            K2[3 * r + c] = s;
+        }
+    for (int e = 0; e < 9; ++e) V[e] = (e % 4 == 0 ? 1.0 : 0.0) + a * K[e] + b * K2[e];
+}
+
+static void mat3_vec(const double M[9], const double v[3], double o[3])
+{
+    double r0 = M[0] * v[0] + M[1] * v[1] + M[2] * v[2];
+    double r1 = M[3] * v[0] + M[4] * v[1] + M[5] * v[2];
+    double r2 = M[6] * v[0] + M[7] * v[1] + M[8] * v[2];
+    o[0] = r0; o[1] = r1; o[2] = r2;
+}
+
+static void mat3T_vec(const double M[9], const double v[3], double o[3])
+{
+    double r0 = M[0] * v[0] + M[3] * v[1] + M[6] * v[2];
+    double r1 = M[1] * v[0] + M[4] * v[1] + M[7] * v[2];
+    double r2 = M[2] * v[0] + M[5] * v[1] + M[8] * v[2];
+    o[0] = r0; o[1] = r1; o[2] = r2;
+}
+
+static void cross3(const double a[3], const double b[3], double o[3])
+{
+    double r0 = a[1] * b[2] - a[2] * b[1];
+    double r1 = a[2] * b[0] - a[0] * b[2];
+    double r2 = a[0] * b[1] - a[1] * b[0];
+    o[0] = r0; o[1] = r1; o[2] = r2;
+}
+
+/* T * Exp(psi) for a pose row (t, q): t' = t + R V(phi) rho, q' = q (x) q(phi). */
+static void pose_right_exp(const double pose[7], const double psi[6], double out[7])
+{
+    double q[4] = {pose[3], pose[4], pose[5], pose[6]};
+    double R[9], V[9], Vr[3], dt[3], dq[4], qn[4];
+    quat_normalize(q);
+    quat_to_rot(q, R);
+    so3_V(psi + 3, V);
+    mat3_vec(V, psi, Vr);
+    mat3_vec(R, Vr, dt);
+    so3_exp_quat(psi + 3, dq);
+    quat_mul(q, dq, qn);
+    quat_normalize(qn);
+    out[0] = pose[0] + dt[0]; out[1] = pose[1] + dt[1]; out[2] = pose[2] + dt[2];
+    out[3] = qn[0]; out[4] = qn[1]; out[5] = qn[2]; out[6] = qn[3];
+}
+
+/* A * B for poses (composition of rigid transforms). */
+static void pose_mul(const double A[7], const double B[7], double out[7])
+{
+    double qa[4] = {A[3], A[4], A[5], A[6]}, qb[4] = {B[3], B[4], B[5], B[6]}, R[9], tb[3], q[4];
+    quat_normalize(qa); quat_normalize(qb);
+    quat_to_rot(qa, R);
+    mat3_vec(R, B, tb);
+    quat_mul(qa, qb, q);
+    quat_normalize(q);
+    out[0] = A[0] + tb[0]; out[1] = A[1] + tb[1]; out[2] = A[2] + tb[2];
+    out[3] = q[0]; out[4] = q[1]; out[5] = q[2]; out[6] = q[3];
+}
+
+static void pose_from_float(const float *p, double o[7])
+{
+    for (int c = 0; c < 7; ++c) o[c] = (double)p[c];
+    double q[4] = {o[3], o[4], o[5], o[6]};
+    quat_normalize(q);
+    o[3] = q[0]; o[4] = q[1]; o[5] = q[2]; o[6] = q[3];
+}
+
+/* Exported SE(3) primitives (used by the pins). */
+void oracle_quat_to_rot(const double *q_in, double *R)
+{
+    double q[4] = {q_in[0], q_in[1], q_in[2], q_in[3]};
+    quat_normalize(q);
+    quat_to_rot(q, R);
+}
+
+/* 4x4 row-major matrix of Exp(xi), xi = [rho; phi]. */
+void oracle_se3_exp(const double *xi, double *T)
+{
+    double q[4], R[9], V[9], t[3];
+    so3_exp_quat(xi + 3, q);
+    quat_to_rot(q, R);
+    so3_V(xi + 3, V);
+    mat3_vec(V, xi, t);
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) T[4 * r + c] = R[3 * r + c];
+        T[4 * r + 3] = t[r];
+    }
+    T[12] = T[13] = T[14] = 0.0; T[15] = 1.0;
+}
+
+/* xi = Log(T) for a 4x4 rigid transform with rotation angle below pi. */
+int oracle_se3_log(const double *T, double *xi)
+{
+    double R[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) R[3 * r + c] = T[4 * r + c];
+    /* Quaternion of R (Shepperd), then phi = 2 atan2(|v|, w) v/|v| with w >= 0. */
+    double q[4], tr = R[0] + R[4] + R[8];
+    if (tr > 0.0) {
+        double s = 2.0 * sqrt(tr + 1.0);
+        q[0] = 0.25 * s; q[1] = (R[7] - R[5]) / s; q[2] = (R[2] - R[6]) / s; q[3] = (R[3] - R[1]) / s;
+    } else if (R[0] > R[4] && R[0] > R[8]) {
+        double s = 2.0 * sqrt(1.0 + R[0] - R[4] - R[8]);
+        q[0] = (R[7] - R[5]) / s; q[1] = 0.25 * s; q[2] = (R[1] + R[3]) / s; q[3] = (R[2] + R[6]) / s;
+    } else if (R[4] > R[8]) {
+        double s = 2.0 * sqrt(1.0 + R[4] - R[0] - R[8]);
+        q[0] = (R[2] - R[6]) / s; q[1] = (R[1] + R[3]) / s; q[2] = 0.25 * s; q[3] = (R[5] + R[7]) / s;
+    } else {
+        double s = 2.0 * sqrt(1.0 + R[8] - R[0] - R[4]);
+        q[0] = (R[3] - R[1]) / s; q[1] = (R[2] + R[6]) / s; q[2] = (R[5] + R[7]) / s; q[3] = 0.25 * s;
+    }
+    if (q[0] < 0.0) { q[0] = -q[0]; q[1] = -q[1]; q[2] = -q[2]; q[3] = -q[3]; }
+    quat_normalize(q);
+    double vn = sqrt(q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double th = 2.0 * atan2(vn, q[0]);
+    double k = (vn < 1e-300) ? 2.0 : th / vn;
+    double phi[3] = {k * q[1], k * q[2], k * q[3]};
+    /* rho solves V(phi) rho = t: Gaussian elimination with partial pivoting. */
+    double V[9], A[12];
+    so3_V(phi, V);
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) A[4 * r + c] = V[3 * r + c];
+        A[4 * r + 3] = T[4 * r + 3];
+    }
+    for (int c = 0; c < 3; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(A[4 * r + c]) > fabs(A[4 * p + c])) p = r;
+        if (A[4 * p + c] == 0.0) return -1;
+        for (int e = 0; e < 4; ++e) { double tmp = A[4 * c + e]; A[4 * c + e] = A[4 * p + e]; A[4 * p + e] = tmp; }
+        for (int r = c + 1; r < 3; ++r) {
+            double f = A[4 * r + c] / A[4 * c + c];
+            for (int e = c; e < 4; ++e) A[4 * r + e] -= f * A[4 * c + e];
+        }
+    }
+    double rho[3];
+    for (int r = 2; r >= 0; --r) {
+        double s = A[4 * r + 3];
+        for (int e = r + 1; e < 3; ++e) s -= A[4 * r + e] * rho[e];
+        rho[r] = s / A[4 * r + r];
+    }
+    xi[0] = rho[0]; xi[1] = rho[1]; xi[2] = rho[2];
+    xi[3] = phi[0]; xi[4] = phi[1]; xi[5] = phi[2];
+    return 0;
+}
+
+/* Exported pose composition T * Exp(psi) for single poses (pins). */
+void oracle_pose_right_exp(const double *pose, const double *psi, double *out)
+{
+    pose_right_exp(pose, psi, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trilinear likelihood grid                                                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const float *v;
+    int nx, ny, nz;
+    double o[3];
+    double h;
+} grid_t;
+
+/* Per-point log term and its gradient in world units at index-space point u.
+ * Returns 1 when u is inside the grid.  Outside: term ln(eps) (or 0 when
+ * oob_skip), zero gradient. */
+static int point_term(const grid_t *g, double eps, int oob_skip, const double u[3],
+                      double *lj, double d[3])
+{
+    const int n[3] = {g->nx, g->ny, g->nz};
+    for (int a = 0; a < 3; ++a) {
+        if (!(u[a] >= 0.0 && u[a] < (double)(n[a] - 1))) {
+            *lj = oob_skip ? 0.0 : log(eps);
+            d[0] = d[1] = d[2] = 0.0;
+            return 0;
+        }
+    }
+    int i0[3];
+    double w[3][2];
+    for (int a = 0; a < 3; ++a) {
+        double fl = floor(u[a]);
+        double f = u[a] - fl;
+        i0[a] = (int)fl;
+        w[a][0] = 1.0 - f;
+        w[a][1] = f;
+    }
+    double G = 0.0, dG[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+                size_t idx = (size_t)(i0[0] + a) + (size_t)g->nx * ((size_t)(i0[1] + b) + (size_t)g->ny * (size_t)(i0[2] + c));
+                double val = (double)g->v[idx];
+                G += val * w[0][a] * w[1][b] * w[2][c];
+                dG[0] += val * (2 * a - 1) * w[1][b] * w[2][c];
+                dG[1] += val * w[0][a] * (2 * b - 1) * w[2][c];
+                dG[2] += val * w[0][a] * w[1][b] * (2 * c - 1);
+            }
+    double den = G + eps;
+    *lj = log(den);
+    for (int a = 0; a < 3; ++a) d[a] = dG[a] / (g->h * den);
+    return 1;
+}
+
+/* Allowance for a point whose cell (or inside/outside) decision sits within
+ * `delta` index units of a cell face: the largest change of the term and of
+ * its xi-derivative over the cells on either side of each such face.  A
+ * kernel that rounds u differently may legitimately take either cell. */
+static int point_ambiguity(const grid_t *g, double eps, int oob_skip, const double u[3],
+                           const double v[3], const double R[9], double delta,
+                           double lj0, const double d0[3], double *amb_l, double amb_g[6])
+{
+    int axes[3], na = 0;
+    double face[3];
+    for (int a = 0; a < 3; ++a) {
+        if (isnan(u[a])) return 0;
+        double r = floor(u[a] + 0.5);          /* nearest integer = nearest face */
+        if (fabs(u[a] - r) < delta) { axes[na] = a; face[na] = r; ++na; }
+    }
+    if (na == 0) return 0;
+    double g0x[3], g0r[3], vx[3];
+    mat3T_vec(R, d0, g0x);
+    cross3(v, d0, vx);
+    mat3T_vec(R, vx, g0r);
+    for (int m = 0; m < (1 << na); ++m) {
+        double ua[3] = {u[0], u[1], u[2]};
+        for (int s = 0; s < na; ++s)
+            ua[axes[s]] = face[s] + (((m >> s) & 1) ? delta : -delta);
+        double lj, d[3], gx[3], gr[3];
+        point_term(g, eps, oob_skip, ua, &lj, d);
+        mat3T_vec(R, d, gx);
+        cross3(v, d, vx);
+        mat3T_vec(R, vx, gr);
+        double dl = fabs(lj - lj0);
+        if (dl > *amb_l) *amb_l = dl;
+        for (int c = 0; c < 3; ++c) {
+            double e0 = fabs(gx[c] - g0x[c]), e1 = fabs(gr[c] - g0r[c]);
+            if (e0 > amb_g[c]) amb_g[c] = e0;
+            if (e1 > amb_g[3 + c]) amb_g[3 + c] = e1;
+        }
+    }
+    return 1;
+}
+
+typedef struct {
+    double ll;         /* l = sum_j l_j */
+    double g[6];       /* [g_rho; g_phi] */
+    double gabs[6];    /* sum_j |d l_j / d xi_c|: scale of the summation error */
+    double amb_l;      /* sum over ambiguous points of the term allowance */
+    double amb_g[6];   /* same for the gradient components */
+    int n_amb;         /* number of ambiguous points */
+} eval_out;
+
+/* Likelihood and right-perturbation gradient of one relative pose (R, t)
+ * against one grid, accumulated into `o`.  v_j = R p_j, x_j = v_j + t.  The
+ * gradient in xi is g_rho = R^T sum d_j and g_phi = R^T sum (v_j x d_j):
+ * d/dphi of R (p + phi x p) + t is -R [p]x, whose transpose maps d to
+ * p x (R^T d) = R^T ((R p) x d). */
+static void eval_pose_grid(const grid_t *g, double eps, int oob_skip, const float *scan, int M,
+                           const double R[9], const double t[3], double delta, eval_out *o)
+{
+    double L = 0.0, A[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
+    double gabs[6] = {0, 0, 0, 0, 0, 0}, amb_g[6] = {0, 0, 0, 0, 0, 0}, amb_l = 0.0;
+    int n_amb = 0;
+    for (int j = 0; j < M; ++j) {
+        double p[3] = {(double)scan[3 * j], (double)scan[3 * j + 1], (double)scan[3 * j + 2]};
+        double v[3], u[3], lj, d[3], vxd[3], tx[3], tr[3];
+        mat3_vec(R, p, v);
+        for (int a = 0; a < 3; ++a) u[a] = (v[a] + t[a] - g->o[a]) / g->h - 0.5;
+        if (point_term(g, eps, oob_skip, u, &lj, d)) {
+            cross3(v, d, vxd);
+        } else {
+            /* Outside the grid the whole gradient contribution is zero (also
+             * for non-finite points, where v x 0 would not be). */
+            vxd[0] = vxd[1] = vxd[2] = 0.0;
+        }
+        L += lj;
+        for (int a = 0; a < 3; ++a) { A[a] += d[a]; B[a] += vxd[a]; }
+        mat3T_vec(R, d, tx);
+        mat3T_vec(R, vxd, tr);
+        for (int c = 0; c < 3; ++c) { gabs[c] += fabs(tx[c]); gabs[3 + c] += fabs(tr[c]); }
+        if (delta > 0.0) {
+            double al = 0.0, ag[6] = {0, 0, 0, 0, 0, 0};
+            if (point_ambiguity(g, eps, oob_skip, u, v, R, delta, lj, d, &al, ag)) {
+                ++n_amb;
+                amb_l += al;
+                for (int c = 0; c < 6; ++c) amb_g[c] += ag[c];
+            }
+        }
+    }
+    double gr[3], gp[3];
+    mat3T_vec(R, A, gr);
+    mat3T_vec(R, B, gp);
+    o->ll += L;
+    for (int c = 0; c < 3; ++c) { o->g[c] += gr[c]; o->g[3 + c] += gp[c]; }
+    for (int c = 0; c < 6; ++c) { o->gabs[c] += gabs[c]; o->amb_g[c] += amb_g[c]; }
+    o->amb_l += amb_l;
+    o->n_amb += n_amb;
+}
+
+static void eval_pose(const grid_t *g, double eps, int oob_skip, const float *scan, int M,
+                      const double pose[7], double delta, eval_out *o)
+{
+    double q[4] = {pose[3], pose[4], pose[5], pose[6]}, R[9];
+    quat_normalize(q);
+    quat_to_rot(q, R);
+    memset(o, 0, sizeof *o);
+    eval_pose_grid(g, eps, oob_skip, scan, M, R, pose, delta, o);
+}
+
+/* Gradient-guided step: psi = [a_t g_rho; a_r g_phi], each block scaled down
+ * to its norm bound when longer, then T <- T Exp(psi) (Eq. 7). */
+static void step_pose(const double pose[7], const double g[6], double a_t, double a_r,
+                      double rho_max, double phi_max, double out[7])
+{
+    double psi[6];
+    for (int c = 0; c < 3; ++c) { psi[c] = a_t * g[c]; psi[3 + c] = a_r * g[3 + c]; }
+    double nr = sqrt(psi[0] * psi[0] + psi[1] * psi[1] + psi[2] * psi[2]);
+    double np = sqrt(psi[3] * psi[3] + psi[4] * psi[4] + psi[5] * psi[5]);
+    if (nr > rho_max) for (int c = 0; c < 3; ++c) psi[c] *= rho_max / nr;
+    if (np > phi_max) for (int c = 3; c < 6; ++c) psi[c] *= phi_max / np;
+    pose_right_exp(pose, psi, out);
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+static grid_t make_grid(const float *v, int nx, int ny, int nz, const double *origin, double h)
+{
+    grid_t g;
+    g.v = v; g.nx = nx; g.ny = ny; g.nz = nz;
+    g.o[0] = origin[0]; g.o[1] = origin[1]; g.o[2] = origin[2];
+    g.h = h;
+    return g;
+}
+
+/* l_i and g_i for every pose (FP32 rows, promoted).  Optional outputs may be
+ * NULL: gabs (N*6), amb_l (N), amb_g (N*6), n_amb (N).  delta <= 0 disables
+ * the ambiguity allowance. */
+int oracle_eval(const float *grid, int nx, int ny, int nz, const double *origin, double h,
+                double eps, int oob_skip, const float *scan, int M, const float *poses, int N,
+                double delta, double *loglik, double *grad, double *gabs, double *amb_l,
+                double *amb_g, int *n_amb, int nthreads)
+{
+    if (nx < 2 || ny < 2 || nz < 2 || M < 0 || N < 0 || h <= 0.0) return -1;
+    grid_t g = make_grid(grid, nx, ny, nz, origin, h);
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < N; ++i) {
+        double pose[7];
+        eval_out o;
+        pose_from_float(poses + 7 * (size_t)i, pose);
+        eval_pose(&g, eps, oob_skip, scan, M, pose, delta, &o);
+        loglik[i] = o.ll;
+        for (int c = 0; c < 6; ++c) grad[6 * (size_t)i + c] = o.g[c];
+        if (gabs) for (int c = 0; c < 6; ++c) gabs[6 * (size_t)i + c] = o.gabs[c];
+        if (amb_l) amb_l[i] = o.amb_l;
+        if (amb_g) for (int c = 0; c < 6; ++c) amb_g[6 * (size_t)i + c] = o.amb_g[c];
+        if (n_amb) n_amb[i] = o.n_amb;
+    }
+    return 0;
+}
+
+/* l at FP64 poses (used by the finite-difference pins). */
+int oracle_eval_f64(const float *grid, int nx, int ny, int nz, const double *origin, double h,
+                    double eps, int oob_skip, const float *scan, int M, const double *poses,
+                    int N, double *loglik, double *grad)
+{
+    if (nx < 2 || ny < 2 || nz < 2 || M < 0 || N < 0 || h <= 0.0) return -1;
+    grid_t g = make_grid(grid, nx, ny, nz, origin, h);
+    for (int i = 0; i < N; ++i) {
+        double pose[7];
+        eval_out o;
+        memcpy(pose, poses + 7 * (size_t)i, sizeof pose);
+        double q[4] = {pose[3], pose[4], pose[5], pose[6]};
+        quat_normalize(q);
+        pose[3] = q[0]; pose[4] = q[1]; pose[5] = q[2]; pose[6] = q[3];
+        eval_pose(&g, eps, oob_skip, scan, M, pose, 0.0, &o);
+        loglik[i] = o.ll;
+        if (grad) for (int c = 0; c < 6; ++c) grad[6 * (size_t)i + c] = o.g[c];
+    }
+    return 0;
+}
+
+/* One gradient step per pose from a given gradient (FP32 pose rows in, FP64 rows out). */
+int oracle_step(const float *poses, const double *grad, int N, double a_t, double a_r,
+                double rho_max, double phi_max, double *out)
+{
+    if (N < 0) return -1;
+    for (int i = 0; i < N; ++i) {
+        double pose[7];
+        pose_from_float(poses + 7 * (size_t)i, pose);
+        step_pose(pose, grad + 6 * (size_t)i, a_t, a_r, rho_max, phi_max, out + 7 * (size_t)i);
+    }
+    return 0;
+}
+
+/* Prediction T_i <- T_i * dT * Exp(delta_i) (Eq. 1); delta may be NULL (zero noise). */
+int oracle_predict(const float *poses, int N, const double *dT, const float *delta, double *out)
+{
+    if (N < 0) return -1;
+    for (int i = 0; i < N; ++i) {
+        double pose[7], tmp[7], dTn[7];
+        pose_from_float(poses + 7 * (size_t)i, pose);
+        memcpy(dTn, dT, sizeof dTn);
+        pose_mul(pose, dTn, tmp);
+        if (delta) {
+            double xi[6];
+            for (int c = 0; c < 6; ++c) xi[c] = (double)delta[6 * (size_t)i + c];
+            pose_right_exp(tmp, xi, out + 7 * (size_t)i);
+        } else {
+            memcpy(out + 7 * (size_t)i, tmp, sizeof tmp);
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Weights and resampling                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* logw_i += beta l_i (Eq. 11), then L = m + ln sum exp(logw - m) with
+ * m = max logw, logw -= L, ESS = 1 / sum exp(logw)^2.  Sums run i ascending. */
+int oracle_weights(const double *logw_in, const double *loglik, int N, double beta,
+                   double *logw_out, double *lse, double *ess)
+{
+    if (N <= 0) return -1;
+    double m = -INFINITY;
+    for (int i = 0; i < N; ++i) {
+        double lw = logw_in[i] + (loglik ? beta * loglik[i] : 0.0);
+        logw_out[i] = lw;
+        if (lw > m) m = lw;
+    }
+    double S = 0.0;
+    for (int i = 0; i < N; ++i) S += exp(logw_out[i] - m);
+    double L = m + log(S);
+    double S2 = 0.0;
+    for (int i = 0; i < N; ++i) {
+        logw_out[i] -= L;
+        double w = exp(logw_out[i]);
+        S2 += w * w;
+    }
+    *lse = L;
+    *ess = 1.0 / S2;
+    return 0;
+}
+
+/* Systematic resampling on normalised log-weights: w_i = exp(logw_i),
+ * CDF_i = sum_{m <= i} w_m (sequential, not renormalised),
+ * u_k = (u + k)/N, a_k = min{i : CDF_i > u_k} or N - 1 when there is none.
+ * margin (optional, N): min over the CDF values of |CDF_i - u_k|, i.e. how
+ * close the decision for k was to a tie. */
+int oracle_resample(const double *logw, int N, double u, int *ancestors, double *margin)
+{
+    if (N <= 0) return -1;
+    double *cdf = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!cdf) return -2;
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) { s += exp(logw[i]); cdf[i] = s; }
+    int i = 0;
+    for (int k = 0; k < N; ++k) {
+        double uk = (u + (double)k) / (double)N;
+        while (i < N && !(cdf[i] > uk)) ++i;      /* u_k is non-decreasing in k */
+        int a = (i < N) ? i : N - 1;
+        ancestors[k] = a;
+        if (margin) {
+            double mg = INFINITY;
+            if (i < N) mg = fabs(cdf[i] - uk);
+            if (i > 0 && fabs(cdf[i - 1] - uk) < mg) mg = fabs(cdf[i - 1] - uk);
+            margin[k] = mg;
+        }
+    }
+    free(cdf);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Keyframe map: sum over neighbour keyframes (Eq. 2)                        */
+/* ------------------------------------------------------------------------ */
+
+/* Neighbour keyframes of one particle: the n_nb smallest translation
+ * distances |t - t_k| (ties to the smaller k), selected in ascending order. */
+static void select_neighbors(const double t[3], const float *kf, int K, int n_nb, int *nb)
+{
+    int used_cap = K;
+    char *used = (char *)calloc((size_t)used_cap, 1);
+    for (int s = 0; s < n_nb; ++s) {
+        int best = -1;
+        double bd = INFINITY;
+        for (int k = 0; k < K; ++k) {
+            if (used[k]) continue;
+            double dx = t[0] - (double)kf[7 * k], dy = t[1] - (double)kf[7 * k + 1], dz = t[2] - (double)kf[7 * k + 2];
+            double d = sqrt(dx * dx + dy * dy + dz * dz);
+            if (d < bd) { bd = d; best = k; }
+        }
+        nb[s] = best;
+        if (best >= 0) used[best] = 1;
+    }
+    free(used);
+}
+
+/* Sum over the n_nb neighbour keyframes of particle i of the grid
+ * log-likelihood of the scan under the relative pose kT = T_k^-1 T
+ * (Eq. 2 and 4): R' = R_k^T R, t' = R_k^T (t - t_k).  The keyframe grids
+ * share dims; grid k starts at grids + k*nx*ny*nz, origin at origins + 3k,
+ * both in the keyframe's own frame.  kf_poses is (N, K, 7). */
+int oracle_kf_eval(const float *grids, int K, int nx, int ny, int nz, const double *origins,
+                   double h, double eps, int oob_skip, const float *scan, int M,
+                   const float *poses, const float *kf_poses, int N, int n_nb, double delta,
+                   double *loglik, double *grad, double *gabs, double *amb_l, double *amb_g,
+                   int *n_amb, int *neighbors, int nthreads)
+{
+    if (K <= 0 || n_nb <= 0 || n_nb > K || N < 0 || M < 0) return -1;
+    size_t gsz = (size_t)nx * ny * nz;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < N; ++i) {
+        double pose[7], R[9];
+        pose_from_float(poses + 7 * (size_t)i, pose);
+        double q[4] = {pose[3], pose[4], pose[5], pose[6]};
+        quat_to_rot(q, R);
+        const float *kf = kf_poses + (size_t)7 * K * i;
+        int nb[64];
+        int *nbp = (n_nb <= 64) ? nb : (int *)malloc(sizeof(int) * (size_t)n_nb);
+        select_neighbors(pose, kf, K, n_nb, nbp);
+        eval_out o;
+        memset(&o, 0, sizeof o);
+        for (int s = 0; s < n_nb; ++s) {
+            int k = nbp[s];
+            if (neighbors) neighbors[(size_t)n_nb * i + s] = k;
+            double kp[7], Rk[9], Rr[9], dt[3], tr[3];
+            pose_from_float(kf + 7 * (size_t)k, kp);
+            double qk[4] = {kp[3], kp[4], kp[5], kp[6]};
+            quat_to_rot(qk, Rk);
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    double sacc = 0.0;
+                    for (int m = 0; m < 3; ++m) sacc += Rk[3 * m + r] * R[3 * m + c];
+                    Rr[3 * r + c] = sacc;
+                }
+            for (int a = 0; a < 3; ++a) dt[a] = pose[a] - kp[a];
+            mat3T_vec(Rk, dt, tr);
+            grid_t g = make_grid(grids + gsz * (size_t)k, nx, ny, nz, origins + 3 * (size_t)k, h);
+            eval_pose_grid(&g, eps, oob_skip, scan, M, Rr, tr, delta, &o);
+        }
+        loglik[i] = o.ll;
+        for (int c = 0; c < 6; ++c) grad[6 * (size_t)i + c] = o.g[c];
+        if (gabs) for (int c = 0; c < 6; ++c) gabs[6 * (size_t)i + c] = o.gabs[c];
+        if (amb_l) amb_l[i] = o.amb_l;
+        if (amb_g) for (int c = 0; c < 6; ++c) amb_g[6 * (size_t)i + c] = o.amb_g[c];
+        if (n_amb) n_amb[i] = o.n_amb;
+        if (nbp != nb) free(nbp);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole filter step                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* One frame: optional prediction, `iters` passes of (likelihood + gradient,
+ * pose step) per particle, weighting with the likelihood of the last pass
+ * (taken at that pass's pre-step pose; with post_eval != 0 a further
+ * likelihood-only pass at the final pose is used instead), normalisation and,
+ * when the policy fires (1: always; 2: ESS < ess_frac * N strictly), systematic
+ * resampling with logw reset to -ln N.
+ * Outputs: poses_out and logw_out (N*7, N), loglik/grad of the last pass,
+ * ancestors (identity when not resampled), stats = {L, ESS, resampled}. */
+int oracle_filter_step(const float *grid, int nx, int ny, int nz, const double *origin,
+                       double h, const float *scan, int M, const float *poses_in,
+                       const double *logw_in, int N, int iters, double a_t, double a_r,
+                       double rho_max, double phi_max, double eps, double beta, int oob_skip,
+                       int post_eval, int policy, double ess_frac, double u, const double *dT,
+                       const float *delta, double *poses_out, double *logw_out, double *loglik,
+                       double *grad, int *ancestors, double *stats, int nthreads)
+{
+    if (N <= 0 || M < 0 || iters < 1) return -1;
+    grid_t g = make_grid(grid, nx, ny, nz, origin, h);
+    set_threads(nthreads);
+    double *cur = (double *)malloc(sizeof(double) * 7 * (size_t)N);
+    double *lw = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!cur || !lw) { free(cur); free(lw); return -2; }
+    if (dT) {
+        oracle_predict(poses_in, N, dT, delta, cur);
+    } else {
+        for (int i = 0; i < N; ++i) pose_from_float(poses_in + 7 * (size_t)i, cur + 7 * (size_t)i);
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < N; ++i) {
+        double *pose = cur + 7 * (size_t)i;
+        eval_out o;
+        for (int it = 0; it < iters; ++it) {
+            double next[7];
+            eval_pose(&g, eps, oob_skip, scan, M, pose, 0.0, &o);
+            loglik[i] = o.ll;
+            for (int c = 0; c < 6; ++c) grad[6 * (size_t)i + c] = o.g[c];
+            step_pose(pose, o.g, a_t, a_r, rho_max, phi_max, next);
+            memcpy(pose, next, sizeof next);
+        }
+        if (post_eval) {
+            eval_pose(&g, eps, oob_skip, scan, M, pose, 0.0, &o);
+            loglik[i] = o.ll;
+        }
+    }
+    double L, ess;
+    oracle_weights(logw_in, loglik, N, beta, lw, &L, &ess);
+    int resample = (policy == 1) || (policy == 2 && ess < ess_frac * (double)N);
+    if (resample) {
+        oracle_resample(lw, N, u, ancestors, NULL);
+        double lnN = -log((double)N);
+        for (int k = 0; k < N; ++k) {
+            memcpy(poses_out + 7 * (size_t)k, cur + 7 * (size_t)ancestors[k], 7 * sizeof(double));
+            logw_out[k] = lnN;
+        }
+    } else {
+        for (int k = 0; k < N; ++k) {
+            ancestors[k] = k;
+            memcpy(poses_out + 7 * (size_t)k, cur + 7 * (size_t)k, 7 * sizeof(double));
+            logw_out[k] = lw[k];
+        }
+    }
+    stats[0] = L; stats[1] = ess; stats[2] = (double)resample;
+    free(cur);
+    free(lw);
+    return 0;
+}

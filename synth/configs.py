@@ -1,0 +1,327 @@
+"""The synthetic workloads the filter is run, tested and measured on.
+
+Each builder returns a plain dict of numpy arrays and scalars.  Seeds are fixed
+per workload (scene = 1000 + workload number, particles = scene + 1, resampling
+offsets = scene + 2, prediction noise = scene + 3) and every builder takes an
+optional seed override.
+
+Workloads (sizes as named; ``small`` variants keep the same structure at sizes
+the FP64 oracle finishes in seconds):
+
+* ``box_room``   -- N = 1,024 particles, M = 512 points, 128^3 grid at 0.2 m:
+  20 random boxes on a floor plane in a 25.6 m cube.  One gradient-guided step,
+  weight normalisation and an always-on systematic resample.
+* ``corridors``  -- N = 100,000, M = 2,048 (32 rings x 64 azimuths, range <= 60 m),
+  512 x 512 x 128 grid at 0.2 m over a 102.4 x 102.4 x 25.6 m corridor maze with
+  boxes; a 200-frame smooth trajectory, 3 gradient passes per frame, resample
+  when ESS < N/2.
+* ``keyframes``  -- K = 64 keyframes (16,384 points each) voxelised into local
+  128^3 grids; N = 50,000 particles, each with its own pose per keyframe;
+  M = 2,048; 4 nearest keyframes per particle.
+* ``serving``    -- many concurrent sessions with their own maps, particle
+  counts and scan sizes.
+
+Scans are ordered ring by azimuth.  Particles start from a Gaussian around the
+true pose: translation N(0, 0.5^2 I) m per axis and a body-frame rotation
+vector N(0, (5 deg)^2 I).
+"""
+
+import math
+
+import numpy as np
+
+from . import geometry as geo
+from .rng import splitmix64_uniforms
+from .scene import Scene
+
+GRID_FP32, GRID_FP16, GRID_BF16 = 0, 1, 2
+
+
+# ---------------------------------------------------------------------------
+# Scans, particles and step parameters
+# ---------------------------------------------------------------------------
+
+def lidar_scan(scene, t, q, elevations_deg, n_az, rmax, noise_sigma, rng, el_range=None):
+    """Ray-cast a ring-by-azimuth scan from pose (t, q); returns (M, 3) FP32, sensor frame.
+
+    Rays that miss (nothing within ``rmax`` inside the volume) are re-drawn in
+    place from a seeded stream of directions with uniform azimuth and uniform
+    elevation in ``el_range``, so the scan always has exactly
+    len(elevations) * n_az points.
+    """
+    R = geo.quat_to_matrix(q)
+    els = np.radians(np.asarray(elevations_deg, dtype=np.float64))
+    az = 2.0 * np.pi * np.arange(n_az) / n_az
+    E, A = np.meshgrid(els, az, indexing="ij")
+    E, A = E.reshape(-1), A.reshape(-1)
+    if el_range is None:
+        el_range = (els.min(), els.max())
+    else:
+        el_range = tuple(np.radians(el_range))
+    dirs_s = np.stack([np.cos(E) * np.cos(A), np.cos(E) * np.sin(A), np.sin(E)], -1)
+    rng_dist = scene.raycast(t, dirs_s @ R.T, rmax)
+    for _ in range(1000):
+        miss = ~np.isfinite(rng_dist)
+        if not miss.any():
+            break
+        k = int(miss.sum())
+        a = rng.uniform(0.0, 2.0 * np.pi, k)
+        e = rng.uniform(el_range[0], el_range[1], k)
+        d_new = np.stack([np.cos(e) * np.cos(a), np.cos(e) * np.sin(a), np.sin(e)], -1)
+        dirs_s[miss] = d_new
+        rng_dist[miss] = scene.raycast(t, d_new @ R.T, rmax)
+    else:
+        raise RuntimeError("lidar_scan: could not find hits for every ray")
+    noisy = rng_dist + rng.normal(0.0, noise_sigma, rng_dist.shape)
+    pts_sensor = dirs_s * noisy[:, None]
+    return pts_sensor.astype(np.float32)
+
+
+def gaussian_particles(t_true, q_true, n, sigma_t, sigma_r_deg, rng):
+    """(n, 7) FP32 poses [tx ty tz qw qx qy qz] around a true pose (q.w >= 0)."""
+    t = np.asarray(t_true)[None, :] + rng.normal(0.0, sigma_t, (n, 3))
+    phi = rng.normal(0.0, math.radians(sigma_r_deg), (n, 3))
+    q = geo.quat_mul(np.asarray(q_true)[None, :], geo.quat_from_axis_angle(phi))
+    q = q / np.linalg.norm(q, axis=-1, keepdims=True)
+    q = np.where(q[:, :1] < 0, -q, q)
+    return np.concatenate([t, q], axis=1).astype(np.float32)
+
+
+def step_params(scan, grid_h, sigma, eps=1e-3, iters=1):
+    """Gradient-step constants from the diagonal preconditioner reading.
+
+    A Gaussian likelihood of width sigma has curvature ~1/sigma^2 per point, so
+    the translation gain is sigma^2/M; the rotation gain divides by the mean
+    squared lever arm r2 = mean |p_j|^2.  Each block is clamped per pass to
+    half a voxel of motion (rotation: half a voxel at the RMS range).
+    """
+    p = np.asarray(scan, dtype=np.float64)
+    M = p.shape[0]
+    r2 = float(np.mean(np.sum(p * p, axis=1)))
+    r_rms = math.sqrt(r2)
+    return dict(
+        iters=int(iters),
+        alpha_t=float(np.float32(sigma * sigma / M)),
+        alpha_r=float(np.float32(sigma * sigma / (M * r2))),
+        rho_max=float(np.float32(0.5 * grid_h)),
+        phi_max=float(np.float32(0.5 * grid_h / r_rms)),
+        eps=float(np.float32(eps)),
+        beta=1.0,
+    )
+
+
+def random_yaw_pose(rng, lo, hi, z, clearance_fn, min_clear):
+    for _ in range(10000):
+        xy = rng.uniform(lo, hi, 2)
+        t = np.array([xy[0], xy[1], z])
+        if clearance_fn(t) > min_clear:
+            q = geo.quat_yaw(rng.uniform(0.0, 2.0 * np.pi))
+            return t, q
+    raise RuntimeError("no free pose found")
+
+
+# ---------------------------------------------------------------------------
+# box_room: 20 boxes + floor in a 25.6 m cube
+# ---------------------------------------------------------------------------
+
+def box_room_scene(rng, n_boxes=20, size=25.6, floor_z=1.0):
+    sides = rng.uniform(0.5, 4.0, (n_boxes, 3))
+    centres = rng.uniform(2.0, size - 2.0, (n_boxes, 2))
+    lo = np.stack([centres[:, 0] - sides[:, 0] / 2, centres[:, 1] - sides[:, 1] / 2,
+                   np.full(n_boxes, floor_z)], -1)
+    hi = np.stack([centres[:, 0] + sides[:, 0] / 2, centres[:, 1] + sides[:, 1] / 2,
+                   floor_z + sides[:, 2]], -1)
+    return Scene(lo, hi, [floor_z], [0.0, 0.0, 0.0], [size, size, size])
+
+
+def box_room(N=1024, seed=1001, grid_n=128, h=0.2, sigma=0.1, n_rings=8, n_az=64,
+             grid_dtype=GRID_FP32):
+    """The single-step box-room workload (N particles, n_rings x n_az point scan)."""
+    rng = np.random.default_rng(seed)
+    size = grid_n * h
+    scene = box_room_scene(rng, size=size)
+    t_true, q_true = random_yaw_pose(rng, 2.0, size - 2.0, 2.5, scene.distance, 1.0)
+    scan = lidar_scan(scene, t_true, q_true, np.linspace(-20.0, 10.0, n_rings), n_az,
+                      rmax=2.0 * size, noise_sigma=0.02, rng=rng)
+    grid = scene.likelihood_grid((grid_n,) * 3, (0.0, 0.0, 0.0), h, sigma)
+    prng = np.random.default_rng(seed + 1)
+    poses = gaussian_particles(t_true, q_true, N, 0.5, 5.0, prng)
+    params = step_params(scan, h, sigma, iters=1)
+    return dict(
+        name="box_room", grid=grid, dims=(grid_n, grid_n, grid_n), origin=(0.0, 0.0, 0.0),
+        h=h, sigma=sigma, grid_dtype=grid_dtype, scan=scan, poses=poses,
+        logw=np.full(N, -math.log(N)), params=params,
+        u=float(splitmix64_uniforms(seed + 2, 1)[0]), t_true=t_true, q_true=q_true,
+        scene=scene,
+    )
+
+
+# ---------------------------------------------------------------------------
+# corridors: maze of wall slabs + floor/ceiling + boxes, 200-frame trajectory
+# ---------------------------------------------------------------------------
+
+def _maze_edges(rng, n, extra_frac=0.12):
+    """Random spanning tree (iterative DFS) over an n x n cell lattice plus extra loops."""
+    visited = np.zeros((n, n), bool)
+    open_e = set()
+    stack = [(int(rng.integers(n)), int(rng.integers(n)))]
+    visited[stack[0]] = True
+    while stack:
+        i, j = stack[-1]
+        nb = [(i + di, j + dj) for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1))
+              if 0 <= i + di < n and 0 <= j + dj < n and not visited[i + di, j + dj]]
+        if not nb:
+            stack.pop()
+            continue
+        a = nb[int(rng.integers(len(nb)))]
+        visited[a] = True
+        open_e.add(frozenset(((i, j), a)))
+        stack.append(a)
+    all_e = [frozenset(((i, j), (i + 1, j))) for i in range(n - 1) for j in range(n)] + \
+            [frozenset(((i, j), (i, j + 1))) for i in range(n) for j in range(n - 1)]
+    closed = [e for e in all_e if e not in open_e]
+    for k in rng.permutation(len(closed))[: int(extra_frac * len(closed))]:
+        open_e.add(closed[k])
+    return open_e
+
+
+def corridor_scene(rng, cells=19, cell=5.0, size_xy=102.4, size_z=25.6, floor_z=1.0,
+                   ceil_z=4.0, wall=0.3, n_boxes=80):
+    off = 0.5 * (size_xy - cells * cell)
+    open_e = _maze_edges(rng, cells)
+    lo, hi = [], []
+    hw = 0.5 * wall
+    # Walls between lattice neighbours that are not connected.
+    for i in range(cells):
+        for j in range(cells):
+            if i + 1 < cells and frozenset(((i, j), (i + 1, j))) not in open_e:
+                x = off + (i + 1) * cell
+                lo.append([x - hw, off + j * cell - hw, floor_z])
+                hi.append([x + hw, off + (j + 1) * cell + hw, ceil_z])
+            if j + 1 < cells and frozenset(((i, j), (i, j + 1))) not in open_e:
+                y = off + (j + 1) * cell
+                lo.append([off + i * cell - hw, y - hw, floor_z])
+                hi.append([off + (i + 1) * cell + hw, y + hw, ceil_z])
+    # Perimeter.
+    a, b = off, off + cells * cell
+    lo += [[a - hw, a - hw, floor_z], [b - hw, a - hw, floor_z], [a - hw, a - hw, floor_z],
+           [a - hw, b - hw, floor_z]]
+    hi += [[a + hw, b + hw, ceil_z], [b + hw, b + hw, ceil_z], [b + hw, a + hw, ceil_z],
+           [b + hw, b + hw, ceil_z]]
+    n_walls = len(lo)
+    # Boxes against the walls of random cells: offset 1.2-1.9 m from the cell centre.
+    for _ in range(n_boxes):
+        ci, cj = rng.integers(cells, size=2)
+        c = np.array([off + (ci + 0.5) * cell, off + (cj + 0.5) * cell])
+        side = rng.uniform(0.4, 1.2, 3)
+        ang = rng.uniform(0, 2 * np.pi)
+        r = rng.uniform(1.2, 0.5 * cell - 0.6)
+        p = c + r * np.array([math.cos(ang), math.sin(ang)])
+        lo.append([p[0] - side[0] / 2, p[1] - side[1] / 2, floor_z])
+        hi.append([p[0] + side[0] / 2, p[1] + side[1] / 2, floor_z + side[2]])
+    sc = Scene(lo, hi, [floor_z, ceil_z], [0.0, 0.0, 0.0], [size_xy, size_xy, size_z])
+    sc.maze = dict(cells=cells, cell=cell, off=off, open=open_e, n_walls=n_walls)
+    return sc
+
+
+def _catmull_rom(P, samples_per_seg=64):
+    P = np.asarray(P, dtype=np.float64)
+    P = np.vstack([2 * P[0] - P[1], P, 2 * P[-1] - P[-2]])
+    out = []
+    s = np.linspace(0.0, 1.0, samples_per_seg, endpoint=False)[:, None]
+    for k in range(1, len(P) - 2):
+        p0, p1, p2, p3 = P[k - 1], P[k], P[k + 1], P[k + 2]
+        out.append(0.5 * ((2 * p1) + (-p0 + p2) * s + (2 * p0 - 5 * p1 + 4 * p2 - p3) * s ** 2
+                          + (-p0 + 3 * p1 - 3 * p2 + p3) * s ** 3))
+    out.append(P[-2][None, :])
+    return np.vstack(out)
+
+
+def maze_trajectory(scene, rng, n_frames=200, step_lo=0.5, step_hi=1.0, z=2.5):
+    """Smooth seeded path through connected maze cells; returns (n_frames, 3), (n_frames, 4)."""
+    mz = scene.maze
+    n, cell, off, open_e = mz["cells"], mz["cell"], mz["off"], mz["open"]
+    need = n_frames * step_hi * 1.3
+    cur = (int(rng.integers(n)), int(rng.integers(n)))
+    path, prev, length = [cur], None, 0.0
+    while length < need:
+        nb = [(cur[0] + d[0], cur[1] + d[1]) for d in ((1, 0), (-1, 0), (0, 1), (0, -1))]
+        nb = [c for c in nb if 0 <= c[0] < n and 0 <= c[1] < n and frozenset((cur, c)) in open_e]
+        fwd = [c for c in nb if c != prev]
+        nxt = (fwd or nb)[int(rng.integers(len(fwd or nb)))]
+        prev, cur = cur, nxt
+        path.append(cur)
+        length += cell
+    way = np.array([[off + (i + 0.5) * cell, off + (j + 0.5) * cell] for i, j in path])
+    curve = _catmull_rom(way)
+    seg = np.linalg.norm(np.diff(curve, axis=0), axis=1)
+    arc = np.concatenate([[0.0], np.cumsum(seg)])
+    steps = rng.uniform(step_lo, step_hi, n_frames - 1)
+    s = np.concatenate([[0.0], np.cumsum(steps)]) + 0.5 * cell
+    s = np.minimum(s, arc[-1] - 1e-6)
+    xy = np.stack([np.interp(s, arc, curve[:, 0]), np.interp(s, arc, curve[:, 1])], -1)
+    tang = np.stack([np.interp(s + 0.05, arc, curve[:, 0]) - xy[:, 0],
+                     np.interp(s + 0.05, arc, curve[:, 1]) - xy[:, 1]], -1)
+    yaw = np.arctan2(tang[:, 1], tang[:, 0])
+    t = np.concatenate([xy, np.full((n_frames, 1), z)], axis=1)
+    return t, geo.quat_yaw(yaw)
+
+
+def frame_scans(scene, t_traj, q_traj, els, n_az, rmax, noise, seed, workers=8):
+    """One scan per trajectory frame; frame f draws from its own stream (seed, 7, f)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(f):
+        return lidar_scan(scene, t_traj[f], q_traj[f], els, n_az, rmax, noise,
+                          np.random.default_rng([seed, 7, f]))
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return np.stack(list(ex.map(one, range(len(t_traj)))))
+
+
+def relative_motion(t0, q0, t1, q1):
+    """(t, q) of T0^-1 T1."""
+    T0, T1 = geo.pose_matrix(t0, q0), geo.pose_matrix(t1, q1)
+    return geo.matrix_to_pose(np.linalg.inv(T0) @ T1)
+
+
+def corridors(N=100000, M_rings=32, n_az=64, n_frames=200, seed=1002, grid=(512, 512, 128),
+              h=0.2, sigma=0.1, iters=3, ess_frac=0.5, with_noise=True, grid_dtype=GRID_FP32):
+    """The paper-scale corridor workload; per-frame scans, odometry and noise."""
+    rng = np.random.default_rng(seed)
+    size_xy, size_z = grid[0] * h, grid[2] * h
+    scene = corridor_scene(rng, size_xy=size_xy, size_z=size_z)
+    t_traj, q_traj = maze_trajectory(scene, rng, n_frames=n_frames)
+    els = np.linspace(-15.0, 15.0, M_rings)
+    scans = frame_scans(scene, t_traj, q_traj, els, n_az, 60.0, 0.02, seed)
+    G = scene.likelihood_grid(grid, (0.0, 0.0, 0.0), h, sigma)
+    # Odometry: true relative motion composed with (1 cm, 0.2 deg) noise.
+    odo = np.zeros((n_frames, 7), np.float32)
+    odo[0] = [0, 0, 0, 1, 0, 0, 0]
+    for f in range(1, n_frames):
+        dt, dq = relative_motion(t_traj[f - 1], q_traj[f - 1], t_traj[f], q_traj[f])
+        dt = dt + rng.normal(0.0, 0.01, 3)
+        dq = geo.quat_mul(dq, geo.quat_from_axis_angle(rng.normal(0.0, math.radians(0.2), 3)))
+        dq = dq / np.linalg.norm(dq)
+        odo[f] = np.concatenate([dt, dq])
+    prng = np.random.default_rng(seed + 1)
+    poses = gaussian_particles(t_traj[0], q_traj[0], N, 0.5, 5.0, prng)
+    params = step_params(scans[0], h, sigma, iters=iters)
+    params["ess_frac"] = ess_frac
+    out = dict(
+        name="corridors", grid=G, dims=tuple(grid), origin=(0.0, 0.0, 0.0), h=h, sigma=sigma,
+        grid_dtype=grid_dtype, scans=scans, scan=scans[0], poses=poses,
+        logw=np.full(N, -math.log(N)), params=params, odometry=odo,
+        u=splitmix64_uniforms(seed + 2, n_frames), t_traj=t_traj, q_traj=q_traj, scene=scene,
+        noise_sigma=(0.05, math.radians(1.0)), noise_seed=seed + 3,
+    )
+    return out
+
+
+def prediction_noise(N, frame, noise_sigma, seed):
+    """(N, 6) FP32 tangent-space noise [rho; phi] for one frame (seeded per frame)."""
+    rng = np.random.default_rng([seed, frame])
+    d = np.empty((N, 6), np.float32)
+    d[:, :3] = rng.normal(0.0, noise_sigma[0], (N, 3))
+    d[:, 3:] = rng.normal(0.0, noise_sigma[1], (N, 3))
+    return d
