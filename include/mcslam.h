@@ -1,0 +1,230 @@
+/*
+ * mcslam.h -- C ABI of the MI355X (gfx950) gradient-guided Monte Carlo SLAM
+ * particle update.
+ *
+ * Paper: T. Nakao et al., "Range-based 6-DoF Monte Carlo SLAM with
+ * Gradient-guided Particle Filter on GPU" (arXiv 2504.18056).
+ *
+ * The calls follow the paper's statement of the problem (Sec. III-A): a set
+ * of N particles, each holding a current sensor pose T_i (and, with a
+ * keyframe map, one pose per keyframe, Sec. III-A "Particle state"), is
+ * updated from a range scan P_t of points in the sensor frame and the relative
+ * motion dT from odometry (Sec. III-B).  One filter step is, per particle:
+ *
+ *   prediction    T_i <- T_i dT Exp(delta_i)                       Eq. 1
+ *   likelihood    l_i = sum_j ln(G(u_ij) + eps), G the trilinear interpolant
+ *                 of a likelihood grid at the transformed point
+ *                 u_ij = (R_i p_j + t_i - o)/h - 1/2; with a keyframe map,
+ *                 summed over neighbour keyframes under T_k^-1 T_i       Eq. 2-4
+ *   gradient      g_i = d l_i(T_i Exp(xi)) / d xi, xi = [rho; phi]
+ *   pose step     psi = [a_t g_rho; a_r g_phi] (norm-clamped per block),
+ *                 T_i <- T_i Exp(psi)                                  Eq. 7
+ *   weighting     logw_i += beta l_i                                   Eq. 11
+ *   normalising   L = logsumexp(logw), logw -= L, ESS = 1 / sum w^2
+ *   resampling    systematic, a_k = min{i : CDF_i > (u + k)/N}
+ *                 (the library's counterpart of Sec. III-F's respawning of
+ *                 particles from the weights of the remaining ones)
+ *
+ * Conventions
+ *   Poses are rows [tx ty tz qw qx qy qz] of FP32: translation in metres and a
+ *   unit Hamilton quaternion, active body-to-world.  Quaternions returned by
+ *   the library have qw >= 0.
+ *   Grids hold nx*ny*nz samples, x fastest, at world points
+ *   origin + (i + 1/2) * res.  A point is inside when its index coordinate
+ *   u satisfies 0 <= u < n - 1 on every axis.
+ *   Scans are M rows [x y z] of FP32 in the sensor frame.
+ *
+ * Ownership and errors
+ *   Host pointers passed in are read during the call only and copied; the
+ *   caller keeps ownership.  Device pointers (the *_dev calls) are borrowed
+ *   until the work enqueued by the call has completed on its stream.  Every
+ *   call returns MCS_OK (0) or a negative mcs_status; no call aborts or throws
+ *   across the ABI.  mcs_last_error() gives a message for the last failing
+ *   call of the calling thread.
+ *
+ * Threading
+ *   Map and session tables are locked per context.  A session must not be
+ *   driven by two threads at the same time.  mcs_filter_step* only enqueue
+ *   work; mcs_get_particles and mcs_session_sync wait for it.
+ */
+#ifndef MCSLAM_H
+#define MCSLAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mcs_status;
+
+#define MCS_OK         0
+#define MCS_EINVAL    -1   /* bad argument (size, pointer, NaN in host input, ...) */
+#define MCS_ENOMEM    -2   /* device allocation failed */
+#define MCS_EBUDGET   -3   /* admission refused: the HBM budget would be exceeded */
+#define MCS_ENOTFOUND -4   /* unknown context, map or session id */
+#define MCS_EDEVICE   -5   /* HIP runtime error */
+#define MCS_EBUSY     -6   /* object still in use (e.g. a map referenced by a session) */
+
+typedef struct mcs_ctx mcs_ctx;
+
+/* Grid storage types.  FP16 and BF16 grids are rounded from the FP32 values
+ * to nearest, ties to even, when the map is loaded; all arithmetic is FP32. */
+#define MCS_GRID_FP32 0
+#define MCS_GRID_FP16 1
+#define MCS_GRID_BF16 2
+
+typedef struct {
+    int32_t nx, ny, nz;     /* samples per axis, each >= 2 */
+    float origin[3];        /* world position of the corner of voxel (0,0,0) */
+    float res;              /* voxel edge h in metres, > 0 */
+    int32_t dtype;          /* MCS_GRID_* */
+} mcs_grid_desc;
+
+/* Resampling policy. */
+#define MCS_RESAMPLE_NEVER  0
+#define MCS_RESAMPLE_ALWAYS 1
+#define MCS_RESAMPLE_ESS    2   /* when ESS < ess_frac * N (strict) */
+
+/* Points outside the grid: ln(eps) (FLOOR) or no contribution (SKIP). */
+#define MCS_OOB_FLOOR 0
+#define MCS_OOB_SKIP  1
+
+typedef struct {
+    int32_t iters;          /* gradient passes per step, >= 1 */
+    float alpha_t;          /* translation gain a_t (m per unit gradient) */
+    float alpha_r;          /* rotation gain a_r (rad per unit gradient) */
+    float rho_max;          /* clamp of |psi_rho| per pass (m) */
+    float phi_max;          /* clamp of |psi_phi| per pass (rad) */
+    float eps;              /* likelihood floor in ln(G + eps), > 0 */
+    float beta;             /* weight exponent: logw += beta * l */
+    int32_t oob;            /* MCS_OOB_* */
+    int32_t post_eval;      /* 0: weight with l of the last pass (taken before
+                               its step); 1: one more likelihood-only pass at
+                               the final pose supplies l */
+    int32_t resample;       /* MCS_RESAMPLE_* */
+    double ess_frac;        /* threshold for MCS_RESAMPLE_ESS */
+    double u;               /* systematic offset in [0, 1) */
+    int32_t predict;        /* 1: apply Eq. 1 with delta_T (and noise) first */
+    float delta_T[7];       /* odometry dT as a pose row */
+    int32_t n_neighbors;    /* keyframe maps: neighbour keyframes per particle */
+} mcs_step_params;
+
+typedef struct {
+    double lse;             /* L = logsumexp of the updated log-weights */
+    double ess;             /* effective sample size 1 / sum w^2 */
+    int32_t resampled;      /* 1 when this step resampled */
+    int32_t best;           /* index (before resampling) of the largest weight, lowest on ties */
+    float best_pose[7];     /* that particle's pose after the step (the representative) */
+    int32_t degenerate;     /* 1 when no log-weight was finite: weights reset to uniform */
+    int32_t pad;
+} mcs_step_stats;
+
+/* Library version string. */
+const char *mcs_version(void);
+
+/* Message describing the last failing call on this thread ("" if none). */
+const char *mcs_last_error(void);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * memory that maps and sessions of this context may hold (0: no bound). */
+mcs_status mcs_create(int32_t device, uint64_t hbm_budget_bytes, mcs_ctx **out);
+
+/* Destroy a context: waits for all sessions' queued work, then frees
+ * everything it owns.  NULL is accepted. */
+mcs_status mcs_destroy(mcs_ctx *ctx);
+
+/* Bytes of device memory currently held by the context's maps and sessions. */
+mcs_status mcs_memory_in_use(mcs_ctx *ctx, uint64_t *bytes);
+
+/* Load a likelihood grid map (the map M of Sec. III-A, as one grid).
+ * values: host FP32, nx*ny*nz samples, x fastest.  The device keeps the grid
+ * in a cell-major layout holding the 8 corner samples of each cell together,
+ * converted to desc->dtype.  Returns the map id in *map_id. */
+mcs_status mcs_init_map(mcs_ctx *ctx, const mcs_grid_desc *desc, const float *values,
+                        int32_t *map_id);
+
+/* Load a keyframe map: K local grids, one per keyframe, each in its own
+ * keyframe frame (Sec. III-A, "Particle state"; Fig. 2).  All descs must have
+ * the same nx, ny, nz, res and dtype; origins may differ.  values[k] is host
+ * FP32 for keyframe k.  Sessions on such a map hold N*K keyframe poses. */
+mcs_status mcs_load_keyframes(mcs_ctx *ctx, int32_t K, const mcs_grid_desc *descs,
+                              const float *const *values, int32_t *map_id);
+
+/* Release a map.  MCS_EBUSY while a session uses it. */
+mcs_status mcs_release_map(mcs_ctx *ctx, int32_t map_id);
+
+/* Create a filter session of N particles on a map, for scans of up to M_max
+ * points.  poses: host N*7.  kf_poses: host N*K*7 (particle-major: particle
+ * i's pose of keyframe k at (i*K + k)*7) for keyframe maps, else NULL.
+ * Log-weights start at -ln N.  Returns MCS_EBUDGET when the session's device
+ * memory would exceed the context budget. */
+mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M_max,
+                              const float *poses, const float *kf_poses, int32_t *session_id);
+
+/* Destroy a session after its queued work has completed. */
+mcs_status mcs_session_destroy(mcs_ctx *ctx, int32_t session_id);
+
+/* Bytes of device memory a session with these sizes would hold. */
+mcs_status mcs_session_bytes(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M_max,
+                             uint64_t *bytes);
+
+/* Overwrite the particle state (checkpoint restore).  Any pointer may be NULL
+ * to keep that part.  poses N*7, logw N, kf_poses N*K*7. */
+mcs_status mcs_set_particles(mcs_ctx *ctx, int32_t session_id, const float *poses,
+                             const double *logw, const float *kf_poses);
+
+/* One filter step (the sequence at the top of this file) on host inputs.
+ * scan: M*3 host FP32 (1 <= M <= M_max); noise: N*6 host FP32 tangent-space
+ * prediction noise [rho; phi] per particle, or NULL for none (used only when
+ * p->predict).  Non-finite scan values give MCS_EINVAL.  Enqueues on the
+ * session's stream and returns. */
+mcs_status mcs_filter_step(mcs_ctx *ctx, int32_t session_id, const float *scan, int32_t M,
+                           const float *noise, const mcs_step_params *p);
+
+/* As mcs_filter_step with device pointers: scan_dev M*3 FP32, noise_dev N*6
+ * FP32 or NULL.  stream: a hipStream_t to enqueue on, or NULL for the
+ * session's stream.  Points with non-finite coordinates count as outside the
+ * grid. */
+mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t session_id, const float *scan_dev,
+                               int32_t M, const float *noise_dev, const mcs_step_params *p,
+                               void *stream);
+
+/* Wait for the session's queued work, then copy out the state.  Any output
+ * may be NULL.  poses N*7; logw N (FP64, normalised); parents N (ancestor of
+ * each particle in the last step, identity when it did not resample); loglik N
+ * and grad N*6 (l and g of the last gradient pass, indexed before
+ * resampling); kf_poses N*K*7; stats of the last step. */
+mcs_status mcs_get_particles(mcs_ctx *ctx, int32_t session_id, float *poses, double *logw,
+                             int32_t *parents, float *loglik, float *grad, float *kf_poses,
+                             mcs_step_stats *stats);
+
+/* Wait for the session's queued work. */
+mcs_status mcs_session_sync(mcs_ctx *ctx, int32_t session_id);
+
+/* The session's own stream (a hipStream_t), e.g. for event timing. */
+mcs_status mcs_session_stream(mcs_ctx *ctx, int32_t session_id, void **stream);
+
+/* GPU time per stage of the steps enqueued while profiling was on, from HIP
+ * events recorded on the stream each step ran on. */
+typedef struct {
+    double predict_ms;      /* scan packing + prediction */
+    double eval_ms;         /* likelihood, gradient and pose-step passes */
+    double weights_ms;      /* weighting, log-sum-exp, ESS */
+    double resample_ms;     /* normalisation and systematic resampling */
+    int64_t steps;          /* steps measured */
+    int64_t evals;          /* particle x point evaluations in those steps */
+} mcs_profile;
+
+/* Turn per-stage event timing on (1) or off (0) for a session; either way the
+ * accumulated figures are reset. */
+mcs_status mcs_session_profile(mcs_ctx *ctx, int32_t session_id, int32_t enable);
+
+/* Wait for the session's profiled steps and return the accumulated times. */
+mcs_status mcs_session_profile_read(mcs_ctx *ctx, int32_t session_id, mcs_profile *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCSLAM_H */

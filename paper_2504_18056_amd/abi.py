@@ -1,0 +1,277 @@
+"""ctypes binding of include/mcslam.h: same names, argument marshalling only.
+
+Every step of the filter runs in the HIP library libmcslam.so built from
+csrc/ (see build.py).  There is no fallback: if the library is missing or
+cannot be loaded, loading raises McsError.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcslam.so")
+
+MCS_OK, MCS_EINVAL, MCS_ENOMEM, MCS_EBUDGET, MCS_ENOTFOUND, MCS_EDEVICE, MCS_EBUSY = \
+    0, -1, -2, -3, -4, -5, -6
+GRID_FP32, GRID_FP16, GRID_BF16 = 0, 1, 2
+RESAMPLE_NEVER, RESAMPLE_ALWAYS, RESAMPLE_ESS = 0, 1, 2
+OOB_FLOOR, OOB_SKIP = 0, 1
+
+_STATUS_NAMES = {0: "MCS_OK", -1: "MCS_EINVAL", -2: "MCS_ENOMEM", -3: "MCS_EBUDGET",
+                 -4: "MCS_ENOTFOUND", -5: "MCS_EDEVICE", -6: "MCS_EBUSY"}
+
+
+class McsError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (%d): %s" % (_STATUS_NAMES.get(status, "?"), status, message))
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("origin", C.c_float * 3), ("res", C.c_float), ("dtype", C.c_int32)]
+
+
+class StepParams(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("alpha_t", C.c_float), ("alpha_r", C.c_float),
+                ("rho_max", C.c_float), ("phi_max", C.c_float), ("eps", C.c_float),
+                ("beta", C.c_float), ("oob", C.c_int32), ("post_eval", C.c_int32),
+                ("resample", C.c_int32), ("ess_frac", C.c_double), ("u", C.c_double),
+                ("predict", C.c_int32), ("delta_T", C.c_float * 7), ("n_neighbors", C.c_int32)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("lse", C.c_double), ("ess", C.c_double), ("resampled", C.c_int32),
+                ("best", C.c_int32), ("best_pose", C.c_float * 7), ("degenerate", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("predict_ms", C.c_double), ("eval_ms", C.c_double), ("weights_ms", C.c_double),
+                ("resample_ms", C.c_double), ("steps", C.c_int64), ("evals", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libmcslam.so (raises McsError when it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise McsError(MCS_EDEVICE, "HIP library %s is not built; run "
+                           "`python -m paper_2504_18056_amd.build`" % LIB_PATH)
+        try:
+            L = C.CDLL(LIB_PATH)
+        except OSError as e:
+            raise McsError(MCS_EDEVICE, "cannot load %s: %s" % (LIB_PATH, e))
+        vp, i32, u64 = C.c_void_p, C.c_int32, C.c_uint64
+        P = C.POINTER
+        sig = {
+            "mcs_version": (C.c_char_p, []),
+            "mcs_last_error": (C.c_char_p, []),
+            "mcs_create": (i32, [i32, u64, P(vp)]),
+            "mcs_destroy": (i32, [vp]),
+            "mcs_memory_in_use": (i32, [vp, P(u64)]),
+            "mcs_init_map": (i32, [vp, P(GridDesc), vp, P(i32)]),
+            "mcs_load_keyframes": (i32, [vp, i32, P(GridDesc), P(vp), P(i32)]),
+            "mcs_release_map": (i32, [vp, i32]),
+            "mcs_session_create": (i32, [vp, i32, i32, i32, vp, vp, P(i32)]),
+            "mcs_session_destroy": (i32, [vp, i32]),
+            "mcs_session_bytes": (i32, [vp, i32, i32, i32, P(u64)]),
+            "mcs_set_particles": (i32, [vp, i32, vp, vp, vp]),
+            "mcs_filter_step": (i32, [vp, i32, vp, i32, vp, P(StepParams)]),
+            "mcs_filter_step_dev": (i32, [vp, i32, vp, i32, vp, P(StepParams), vp]),
+            "mcs_get_particles": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, P(StepStats)]),
+            "mcs_session_sync": (i32, [vp, i32]),
+            "mcs_session_stream": (i32, [vp, i32, P(vp)]),
+            "mcs_session_profile": (i32, [vp, i32, i32]),
+            "mcs_session_profile_read": (i32, [vp, i32, P(Profile)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != MCS_OK:
+        raise McsError(status, mcs_last_error())
+    return status
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a, shape):
+    return np.ascontiguousarray(a, dtype=np.float32).reshape(shape)
+
+
+# ---------------------------------------------------------------------------
+# The C ABI, one function per entry point
+# ---------------------------------------------------------------------------
+
+def mcs_version():
+    return lib().mcs_version().decode()
+
+
+def mcs_last_error():
+    return lib().mcs_last_error().decode()
+
+
+def mcs_create(device=0, hbm_budget_bytes=0):
+    ctx = C.c_void_p()
+    _check(lib().mcs_create(int(device), int(hbm_budget_bytes), C.byref(ctx)))
+    return ctx
+
+
+def mcs_destroy(ctx):
+    _check(lib().mcs_destroy(ctx))
+
+
+def mcs_memory_in_use(ctx):
+    v = C.c_uint64()
+    _check(lib().mcs_memory_in_use(ctx, C.byref(v)))
+    return v.value
+
+
+def grid_desc(dims, origin, res, dtype=GRID_FP32):
+    d = GridDesc()
+    d.nx, d.ny, d.nz = (int(v) for v in dims)
+    for a in range(3):
+        d.origin[a] = float(origin[a])
+    d.res = float(res)
+    d.dtype = int(dtype)
+    return d
+
+
+def mcs_init_map(ctx, desc, values):
+    """values: (nz, ny, nx) or flat FP32, x fastest."""
+    v = _f32(values, (-1,))
+    mid = C.c_int32()
+    _check(lib().mcs_init_map(ctx, C.byref(desc), _ptr(v), C.byref(mid)))
+    return mid.value
+
+
+def mcs_load_keyframes(ctx, descs, values):
+    K = len(descs)
+    arr = (GridDesc * K)(*descs)
+    keep = [_f32(v, (-1,)) for v in values]
+    ptrs = (C.c_void_p * K)(*[k.ctypes.data for k in keep])
+    mid = C.c_int32()
+    _check(lib().mcs_load_keyframes(ctx, K, arr, ptrs, C.byref(mid)))
+    return mid.value
+
+
+def mcs_release_map(ctx, map_id):
+    _check(lib().mcs_release_map(ctx, int(map_id)))
+
+
+def mcs_session_create(ctx, map_id, poses, M_max, kf_poses=None):
+    p = _f32(poses, (-1, 7))
+    kf = None if kf_poses is None else _f32(kf_poses, (-1,))
+    sid = C.c_int32()
+    _check(lib().mcs_session_create(ctx, int(map_id), p.shape[0], int(M_max), _ptr(p), _ptr(kf),
+                                    C.byref(sid)))
+    return sid.value
+
+
+def mcs_session_destroy(ctx, sid):
+    _check(lib().mcs_session_destroy(ctx, int(sid)))
+
+
+def mcs_session_bytes(ctx, map_id, N, M_max):
+    v = C.c_uint64()
+    _check(lib().mcs_session_bytes(ctx, int(map_id), int(N), int(M_max), C.byref(v)))
+    return v.value
+
+
+def mcs_set_particles(ctx, sid, poses=None, logw=None, kf_poses=None):
+    p = None if poses is None else _f32(poses, (-1, 7))
+    w = None if logw is None else np.ascontiguousarray(logw, dtype=np.float64)
+    kf = None if kf_poses is None else _f32(kf_poses, (-1,))
+    _check(lib().mcs_set_particles(ctx, int(sid), _ptr(p), _ptr(w), _ptr(kf)))
+
+
+def step_params(d):
+    """StepParams from a dict (keys named as the struct fields)."""
+    p = StepParams()
+    p.iters = int(d.get("iters", 1))
+    p.alpha_t = d["alpha_t"]
+    p.alpha_r = d["alpha_r"]
+    p.rho_max = d["rho_max"]
+    p.phi_max = d["phi_max"]
+    p.eps = d["eps"]
+    p.beta = d.get("beta", 1.0)
+    p.oob = int(d.get("oob", OOB_FLOOR))
+    p.post_eval = int(bool(d.get("post_eval", False)))
+    p.resample = int(d.get("resample", RESAMPLE_ALWAYS))
+    p.ess_frac = float(d.get("ess_frac", 0.5))
+    p.u = float(d.get("u", 0.5))
+    dT = d.get("delta_T")
+    p.predict = int(dT is not None)
+    dT = dT if dT is not None else (0, 0, 0, 1, 0, 0, 0)
+    for c in range(7):
+        p.delta_T[c] = float(dT[c])
+    p.n_neighbors = int(d.get("n_neighbors", 4))
+    return p
+
+
+def mcs_filter_step(ctx, sid, scan, params, noise=None):
+    s = _f32(scan, (-1, 3))
+    n = None if noise is None else _f32(noise, (-1, 6))
+    p = params if isinstance(params, StepParams) else step_params(params)
+    _check(lib().mcs_filter_step(ctx, int(sid), _ptr(s), s.shape[0], _ptr(n), C.byref(p)))
+
+
+def mcs_filter_step_dev(ctx, sid, scan_dev_ptr, M, params, noise_dev_ptr=None, stream=None):
+    """Device pointers (ints, e.g. torch tensor .data_ptr()) and an optional hipStream_t."""
+    p = params if isinstance(params, StepParams) else step_params(params)
+    _check(lib().mcs_filter_step_dev(ctx, int(sid), C.c_void_p(int(scan_dev_ptr)), int(M),
+                                     None if noise_dev_ptr is None else C.c_void_p(int(noise_dev_ptr)),
+                                     C.byref(p), None if stream is None else C.c_void_p(int(stream))))
+
+
+def mcs_get_particles(ctx, sid, N, K=0, poses=True, logw=True, parents=True, loglik=True,
+                      grad=True, kf_poses=False, stats=True):
+    out = {}
+    P = np.empty((N, 7), np.float32) if poses else None
+    W = np.empty(N, np.float64) if logw else None
+    A = np.empty(N, np.int32) if parents else None
+    Lk = np.empty(N, np.float32) if loglik else None
+    G = np.empty((N, 6), np.float32) if grad else None
+    KF = np.empty((N, K, 7), np.float32) if (kf_poses and K > 0) else None
+    st = StepStats()
+    _check(lib().mcs_get_particles(ctx, int(sid), _ptr(P), _ptr(W), _ptr(A), _ptr(Lk), _ptr(G),
+                                   _ptr(KF), C.byref(st) if stats else None))
+    out.update(poses=P, logw=W, parents=A, loglik=Lk, grad=G, kf_poses=KF)
+    if stats:
+        out["stats"] = dict(lse=st.lse, ess=st.ess, resampled=bool(st.resampled), best=st.best,
+                            best_pose=np.array(st.best_pose[:], np.float32),
+                            degenerate=bool(st.degenerate))
+    return out
+
+
+def mcs_session_sync(ctx, sid):
+    _check(lib().mcs_session_sync(ctx, int(sid)))
+
+
+def mcs_session_stream(ctx, sid):
+    s = C.c_void_p()
+    _check(lib().mcs_session_stream(ctx, int(sid), C.byref(s)))
+    return s.value
+
+
+def mcs_session_profile(ctx, sid, enable=True):
+    _check(lib().mcs_session_profile(ctx, int(sid), int(bool(enable))))
+
+
+def mcs_session_profile_read(ctx, sid):
+    p = Profile()
+    _check(lib().mcs_session_profile_read(ctx, int(sid), C.byref(p)))
+    return {f: getattr(p, f) for f, _ in Profile._fields_}

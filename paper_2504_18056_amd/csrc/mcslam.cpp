@@ -1,0 +1,870 @@
+// C ABI of the MI355X gradient-guided Monte Carlo SLAM particle update: the
+// context, the map store, sessions, admission by HBM budget and the step
+// sequence enqueued on a session's stream.  Kernels live in kernels.hip.
+#include "../../include/mcslam.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace mcs;
+
+namespace {
+
+thread_local std::string g_err;
+
+mcs_status fail(mcs_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+mcs_status hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory) return fail(MCS_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(MCS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                       \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxNeighbors = 16;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+size_t record_bytes(int dtype) { return dtype == MCS_GRID_FP32 ? 32 : 16; }
+
+struct Map {
+    int id = 0;
+    int K = 0;                       // 0: single grid; >0: keyframe grids
+    mcs_grid_desc desc{};            // dims, res, dtype (origin of grid 0)
+    std::vector<float> origins;      // K x 3 (or 1 x 3)
+    void *cells = nullptr;
+    size_t bytes = 0;
+    int64_t records = 0;             // per grid
+    float *origins_dev = nullptr;
+    int users = 0;
+};
+
+struct Session {
+    int id = 0;
+    Map *map = nullptr;
+    int N = 0, M_max = 0, K = 0;
+    hipStream_t stream = nullptr;
+    void *block = nullptr;           // one device allocation holding every buffer
+    size_t bytes = 0;
+    float *pose = nullptr, *pose_tmp = nullptr, *loglik = nullptr, *grad = nullptr;
+    float *kf_pose = nullptr, *kf_pose_tmp = nullptr, *noise = nullptr, *scan3 = nullptr;
+    float4 *scan4 = nullptr;
+    double *logw = nullptr, *cdf_local = nullptr, *part = nullptr;
+    unsigned int *counters = nullptr;
+    int32_t *parents = nullptr, *neighbors = nullptr;
+    StepStatsDev *stats = nullptr;
+    float *pinned = nullptr;         // host staging for host-pointer steps
+    size_t pinned_floats = 0;
+    hipEvent_t staged = nullptr;     // last upload from `pinned` done
+    bool staged_pending = false;
+    // Stage timing: 5 events per profiled step (start, after predict, after
+    // eval, after weights, after resample).
+    bool profiling = false;
+    std::vector<std::array<hipEvent_t, 5>> prof_events;
+    size_t prof_used = 0;
+    int64_t prof_evals = 0;
+    double prof_ms[4] = {0, 0, 0, 0};
+    int64_t prof_steps = 0;
+};
+
+struct Layout {
+    size_t off[20];
+    size_t total;
+};
+
+Layout session_layout(int N, int M_max, int K)
+{
+    const size_t n = (size_t)N, nb = (size_t)weight_blocks(N);
+    const size_t sizes[] = {
+        7 * n * 4,                  // 0 pose
+        7 * n * 4,                  // 1 pose_tmp
+        n * 4,                      // 2 loglik
+        6 * n * 4,                  // 3 grad
+        (size_t)K * 7 * n * 4,      // 4 kf_pose
+        (size_t)K * 7 * n * 4,      // 5 kf_pose_tmp
+        6 * n * 4,                  // 6 noise
+        (size_t)M_max * 3 * 4,      // 7 scan3
+        (size_t)M_max * 16,         // 8 scan4
+        n * 8,                      // 9 logw
+        n * 8,                      // 10 cdf_local
+        nb * 4 * 8,                 // 11 part
+        2 * sizeof(unsigned int),   // 12 counters
+        n * 4,                      // 13 parents
+        (K > 0 ? (size_t)kMaxNeighbors * n * 4 : 0),  // 14 neighbors
+        sizeof(StepStatsDev),       // 15 stats
+    };
+    Layout L{};
+    size_t o = 0;
+    for (size_t k = 0; k < sizeof sizes / sizeof sizes[0]; ++k) {
+        L.off[k] = o;
+        o += align_up(sizes[k]);
+    }
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct mcs_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    uint64_t in_use = 0;
+    std::mutex mu;
+    std::map<int, Map *> maps;
+    std::map<int, Session *> sessions;
+    int next_id = 1;
+};
+
+namespace {
+
+mcs_status set_device(mcs_ctx *ctx)
+{
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    return MCS_OK;
+}
+
+bool budget_allows(const mcs_ctx *ctx, uint64_t extra)
+{
+    return ctx->budget == 0 || ctx->in_use + extra <= ctx->budget;
+}
+
+mcs_status validate_desc(const mcs_grid_desc *d)
+{
+    if (!d) return fail(MCS_EINVAL, "grid desc is NULL");
+    if (d->nx < 2 || d->ny < 2 || d->nz < 2)
+        return fail(MCS_EINVAL, "grid dims must be >= 2 (got %d x %d x %d)", d->nx, d->ny, d->nz);
+    if (!(d->res > 0.0f) || !std::isfinite(d->res)) return fail(MCS_EINVAL, "grid res must be > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d->origin[a])) return fail(MCS_EINVAL, "grid origin not finite");
+    if (d->dtype < MCS_GRID_FP32 || d->dtype > MCS_GRID_BF16)
+        return fail(MCS_EINVAL, "unknown grid dtype %d", d->dtype);
+    const double cells = (double)(d->nx - 1) * (d->ny - 1) * (d->nz - 1);
+    if (cells >= 2147483647.0) return fail(MCS_EINVAL, "grid has too many cells (%.0f)", cells);
+    if (d->nx > (1 << 24) || d->ny > (1 << 24) || d->nz > (1 << 24))
+        return fail(MCS_EINVAL, "grid axis too long");
+    return MCS_OK;
+}
+
+// Upload K host FP32 grids of one shape and convert them into cell records.
+mcs_status build_map(mcs_ctx *ctx, int K, const mcs_grid_desc *descs, const float *const *values,
+                     int32_t *map_id)
+{
+    const mcs_grid_desc &d0 = descs[0];
+    const size_t samples = (size_t)d0.nx * d0.ny * d0.nz;
+    const int64_t recs = (int64_t)(d0.nx - 1) * (d0.ny - 1) * (d0.nz - 1);
+    const size_t grid_bytes = (size_t)recs * record_bytes(d0.dtype);
+    const int G = K > 0 ? K : 1;
+    const size_t total = align_up(grid_bytes) * G + align_up((size_t)G * 3 * sizeof(float));
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!budget_allows(ctx, total))
+            return fail(MCS_EBUDGET, "map needs %zu bytes; budget %llu, in use %llu", total,
+                        (unsigned long long)ctx->budget, (unsigned long long)ctx->in_use);
+        ctx->in_use += total;
+    }
+    Map *m = new Map;
+    m->K = K;
+    m->desc = d0;
+    m->records = recs;
+    m->bytes = total;
+    for (int k = 0; k < G; ++k)
+        for (int a = 0; a < 3; ++a) m->origins.push_back(descs[k].origin[a]);
+    auto undo = [&](mcs_status s) {
+        if (m->cells) (void)hipFree(m->cells);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->in_use -= total;
+        delete m;
+        return s;
+    };
+    hipError_t e = hipMalloc(&m->cells, total);
+    if (e != hipSuccess) { m->cells = nullptr; return undo(hip_fail(e, "hipMalloc(map)")); }
+    m->origins_dev = reinterpret_cast<float *>((char *)m->cells + align_up(grid_bytes) * G);
+    float *tmp = nullptr;
+    e = hipMalloc(&tmp, samples * sizeof(float));
+    if (e != hipSuccess) return undo(hip_fail(e, "hipMalloc(grid staging)"));
+    for (int k = 0; k < G && e == hipSuccess; ++k) {
+        e = hipMemcpy(tmp, values[k], samples * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_build_cells(tmp, (char *)m->cells + align_up(grid_bytes) * k, d0.nx, d0.ny,
+                                   d0.nz, d0.dtype, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(m->origins_dev, m->origins.data(), (size_t)G * 3 * sizeof(float),
+                      hipMemcpyHostToDevice);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return undo(hip_fail(e, "map upload"));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    m->id = ctx->next_id++;
+    ctx->maps[m->id] = m;
+    *map_id = m->id;
+    return MCS_OK;
+}
+
+Session *find_session(mcs_ctx *ctx, int32_t sid)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->sessions.find(sid);
+    return it == ctx->sessions.end() ? nullptr : it->second;
+}
+
+void aos_to_soa(const float *aos, float *soa, size_t n, int C)
+{
+    for (size_t i = 0; i < n; ++i)
+        for (int c = 0; c < C; ++c) soa[(size_t)c * n + i] = aos[i * C + c];
+}
+
+// Poses: normalise quaternions on the host side of the upload and reject
+// non-finite values.
+mcs_status check_poses(const float *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i) {
+        double qq = 0.0;
+        for (int c = 0; c < 7; ++c) {
+            if (!std::isfinite(p[7 * i + c])) return fail(MCS_EINVAL, "pose %zu not finite", i);
+            if (c >= 3) qq += (double)p[7 * i + c] * p[7 * i + c];
+        }
+        if (!(qq > 1e-20)) return fail(MCS_EINVAL, "pose %zu has a zero quaternion", i);
+    }
+    return MCS_OK;
+}
+
+mcs_status upload_kf(Session *s, const float *kf_poses)
+{
+    // Host layout (i, k, c) -> device rows (k*7 + c) of length N.
+    const size_t N = s->N, K = s->K;
+    std::vector<float> soa(K * 7 * N);
+    for (size_t i = 0; i < N; ++i)
+        for (size_t k = 0; k < K; ++k)
+            for (int c = 0; c < 7; ++c) soa[(k * 7 + c) * N + i] = kf_poses[(i * K + k) * 7 + c];
+    HIP_TRY(hipMemcpyAsync(s->kf_pose, soa.data(), soa.size() * 4, hipMemcpyHostToDevice,
+                           s->stream), "upload kf poses");
+    HIP_TRY(hipStreamSynchronize(s->stream), "sync");
+    return MCS_OK;
+}
+
+mcs_status validate_params(const Session *s, const mcs_step_params *p, int M)
+{
+    if (!p) return fail(MCS_EINVAL, "params is NULL");
+    if (M < 1 || M > s->M_max) return fail(MCS_EINVAL, "M=%d outside [1, %d]", M, s->M_max);
+    if (p->iters < 1 || p->iters > 64) return fail(MCS_EINVAL, "iters=%d outside [1, 64]", p->iters);
+    const float fs[] = {p->alpha_t, p->alpha_r, p->rho_max, p->phi_max, p->eps, p->beta};
+    for (float f : fs)
+        if (!std::isfinite(f)) return fail(MCS_EINVAL, "non-finite step parameter");
+    if (!(p->eps > 0.0f)) return fail(MCS_EINVAL, "eps must be > 0");
+    if (p->rho_max < 0.0f || p->phi_max < 0.0f) return fail(MCS_EINVAL, "clamps must be >= 0");
+    if (p->oob != MCS_OOB_FLOOR && p->oob != MCS_OOB_SKIP) return fail(MCS_EINVAL, "bad oob mode");
+    if (p->resample < MCS_RESAMPLE_NEVER || p->resample > MCS_RESAMPLE_ESS)
+        return fail(MCS_EINVAL, "bad resample policy");
+    if (!(p->u >= 0.0 && p->u < 1.0)) return fail(MCS_EINVAL, "u must be in [0, 1)");
+    if (p->resample == MCS_RESAMPLE_ESS && !std::isfinite(p->ess_frac))
+        return fail(MCS_EINVAL, "ess_frac not finite");
+    if (p->predict) {
+        double qq = 0.0;
+        for (int c = 0; c < 7; ++c) {
+            if (!std::isfinite(p->delta_T[c])) return fail(MCS_EINVAL, "delta_T not finite");
+            if (c >= 3) qq += (double)p->delta_T[c] * p->delta_T[c];
+        }
+        if (!(qq > 1e-20)) return fail(MCS_EINVAL, "delta_T has a zero quaternion");
+    }
+    if (s->K > 0 && (p->n_neighbors < 1 || p->n_neighbors > std::min(s->K, kMaxNeighbors)))
+        return fail(MCS_EINVAL, "n_neighbors=%d outside [1, %d]", p->n_neighbors,
+                    std::min(s->K, kMaxNeighbors));
+    return MCS_OK;
+}
+
+// The step sequence on `st` with the scan already in s->scan3 (or scan_dev).
+// Events of the next profiled step (nullptr entries when not profiling).
+mcs_status prof_begin(Session *s, std::array<hipEvent_t, 5> *&ev)
+{
+    ev = nullptr;
+    if (!s->profiling) return MCS_OK;
+    if (s->prof_used == s->prof_events.size()) {
+        std::array<hipEvent_t, 5> a{};
+        for (auto &e : a) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+        s->prof_events.push_back(a);
+    }
+    ev = &s->prof_events[s->prof_used++];
+    return MCS_OK;
+}
+
+#define PROF_MARK(k)                                                     \
+    do {                                                                 \
+        if (ev) HIP_TRY(hipEventRecord((*ev)[k], st), "hipEventRecord"); \
+    } while (0)
+
+mcs_status enqueue_step(Session *s, const float *scan3_dev, int M, const float *noise_dev,
+                        const mcs_step_params *p, hipStream_t st)
+{
+    std::array<hipEvent_t, 5> *ev = nullptr;
+    mcs_status ps = prof_begin(s, ev);
+    if (ps != MCS_OK) return ps;
+    if (ev) s->prof_evals += (int64_t)s->N * M * (p->iters + (p->post_eval ? 1 : 0)) *
+                             (s->K > 0 ? p->n_neighbors : 1);
+    PROF_MARK(0);
+    HIP_TRY(launch_pack_scan(scan3_dev, s->scan4, M, st), "pack scan");
+    if (p->predict) HIP_TRY(launch_predict(s->pose, s->N, p->delta_T, noise_dev, st), "predict");
+    PROF_MARK(1);
+    const Map *m = s->map;
+    if (s->K == 0) {
+        EvalArgs a{};
+        a.scan = s->scan4;
+        a.M = M;
+        a.grid.cells = m->cells;
+        a.grid.nx = m->desc.nx; a.grid.ny = m->desc.ny; a.grid.nz = m->desc.nz;
+        a.grid.dtype = m->desc.dtype;
+        a.grid.ox = m->desc.origin[0]; a.grid.oy = m->desc.origin[1]; a.grid.oz = m->desc.origin[2];
+        a.grid.inv_h = 1.0f / m->desc.res;
+        a.pose = s->pose;
+        a.loglik = s->loglik;
+        a.grad = s->grad;
+        a.N = s->N;
+        a.iters = p->iters;
+        a.post_eval = p->post_eval ? 1 : 0;
+        a.oob_skip = p->oob == MCS_OOB_SKIP;
+        a.alpha_t = p->alpha_t; a.alpha_r = p->alpha_r;
+        a.rho_max = p->rho_max; a.phi_max = p->phi_max;
+        a.eps = p->eps;
+        HIP_TRY(launch_eval_step(a, st), "eval_step");
+    } else {
+        KfEvalArgs a{};
+        a.scan = s->scan4;
+        a.M = M;
+        a.cells = m->cells;
+        a.grid_records = (int64_t)(align_up((size_t)m->records * record_bytes(m->desc.dtype)) /
+                                   record_bytes(m->desc.dtype));
+        a.origins = m->origins_dev;
+        a.nx = m->desc.nx; a.ny = m->desc.ny; a.nz = m->desc.nz; a.dtype = m->desc.dtype;
+        a.inv_h = 1.0f / m->desc.res;
+        a.K = s->K;
+        a.n_nb = p->n_neighbors;
+        a.pose = s->pose;
+        a.kf_pose = s->kf_pose;
+        a.loglik = s->loglik;
+        a.grad = s->grad;
+        a.neighbors = s->neighbors;
+        a.N = s->N;
+        a.iters = p->iters;
+        a.post_eval = p->post_eval ? 1 : 0;
+        a.oob_skip = p->oob == MCS_OOB_SKIP;
+        a.alpha_t = p->alpha_t; a.alpha_r = p->alpha_r;
+        a.rho_max = p->rho_max; a.phi_max = p->phi_max;
+        a.eps = p->eps;
+        HIP_TRY(launch_kf_eval_step(a, st), "kf_eval_step");
+    }
+    PROF_MARK(2);
+    WeightArgs w{};
+    w.logw = s->logw;
+    w.loglik = s->loglik;
+    w.N = s->N;
+    w.beta = (double)p->beta;
+    w.part = s->part;
+    w.counter = s->counters;
+    w.stats = s->stats;
+    w.policy = p->resample;
+    w.ess_frac = p->ess_frac;
+    w.pose = s->pose;
+    HIP_TRY(launch_weights(w, st), "weights");
+    PROF_MARK(3);
+    ResampleArgs r{};
+    r.logw = s->logw;
+    r.cdf_local = s->cdf_local;
+    r.part = s->part;
+    r.counter = s->counters + 1;
+    r.stats = s->stats;
+    r.N = s->N;
+    r.u = p->u;
+    r.parents = s->parents;
+    r.pose = s->pose;
+    r.pose_tmp = s->pose_tmp;
+    r.kf_pose = s->kf_pose;
+    r.kf_pose_tmp = s->kf_pose_tmp;
+    r.K = s->K;
+    HIP_TRY(launch_resample(r, st), "resample");
+    PROF_MARK(4);
+    return MCS_OK;
+}
+
+// Fold the recorded events into the accumulated stage times.
+mcs_status prof_collect(Session *s)
+{
+    for (size_t k = 0; k < s->prof_used; ++k) {
+        auto &e = s->prof_events[k];
+        HIP_TRY(hipEventSynchronize(e[4]), "hipEventSynchronize");
+        for (int j = 0; j < 4; ++j) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, e[j], e[j + 1]), "hipEventElapsedTime");
+            s->prof_ms[j] += ms;
+        }
+        s->prof_steps++;
+    }
+    s->prof_used = 0;
+    return MCS_OK;
+}
+
+void prof_release(Session *s)
+{
+    for (auto &a : s->prof_events)
+        for (auto e : a) (void)hipEventDestroy(e);
+    s->prof_events.clear();
+    s->prof_used = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mcs_version(void) { return "mcslam-gfx950 0.1"; }
+
+const char *mcs_last_error(void) { return g_err.c_str(); }
+
+mcs_status mcs_create(int32_t device, uint64_t hbm_budget_bytes, mcs_ctx **out)
+{
+    if (!out) return fail(MCS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n), "hipGetDeviceCount");
+    if (device < 0 || device >= n) return fail(MCS_EINVAL, "device %d not in [0, %d)", device, n);
+    HIP_TRY(hipSetDevice(device), "hipSetDevice");
+    mcs_ctx *c = new mcs_ctx;
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return MCS_OK;
+}
+
+mcs_status mcs_session_destroy(mcs_ctx *ctx, int32_t sid);
+
+mcs_status mcs_destroy(mcs_ctx *ctx)
+{
+    if (!ctx) return MCS_OK;
+    std::vector<int> ids;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto &kv : ctx->sessions) ids.push_back(kv.first);
+    }
+    for (int id : ids) mcs_session_destroy(ctx, id);
+    for (auto &kv : ctx->maps) {
+        (void)hipFree(kv.second->cells);
+        delete kv.second;
+    }
+    delete ctx;
+    return MCS_OK;
+}
+
+mcs_status mcs_memory_in_use(mcs_ctx *ctx, uint64_t *bytes)
+{
+    if (!ctx || !bytes) return fail(MCS_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *bytes = ctx->in_use;
+    return MCS_OK;
+}
+
+mcs_status mcs_init_map(mcs_ctx *ctx, const mcs_grid_desc *desc, const float *values,
+                        int32_t *map_id)
+{
+    if (!ctx || !values || !map_id) return fail(MCS_EINVAL, "NULL argument");
+    mcs_status s = validate_desc(desc);
+    if (s != MCS_OK) return s;
+    if ((s = set_device(ctx)) != MCS_OK) return s;
+    const float *v[1] = {values};
+    return build_map(ctx, 0, desc, v, map_id);
+}
+
+mcs_status mcs_load_keyframes(mcs_ctx *ctx, int32_t K, const mcs_grid_desc *descs,
+                              const float *const *values, int32_t *map_id)
+{
+    if (!ctx || !descs || !values || !map_id) return fail(MCS_EINVAL, "NULL argument");
+    if (K < 1) return fail(MCS_EINVAL, "K must be >= 1");
+    for (int k = 0; k < K; ++k) {
+        mcs_status s = validate_desc(&descs[k]);
+        if (s != MCS_OK) return s;
+        if (!values[k]) return fail(MCS_EINVAL, "keyframe grid %d is NULL", k);
+        if (descs[k].nx != descs[0].nx || descs[k].ny != descs[0].ny || descs[k].nz != descs[0].nz ||
+            descs[k].res != descs[0].res || descs[k].dtype != descs[0].dtype)
+            return fail(MCS_EINVAL, "keyframe grid %d differs in shape, res or dtype", k);
+    }
+    mcs_status s = set_device(ctx);
+    if (s != MCS_OK) return s;
+    return build_map(ctx, K, descs, values, map_id);
+}
+
+mcs_status mcs_release_map(mcs_ctx *ctx, int32_t map_id)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    Map *m = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->maps.find(map_id);
+        if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
+        if (it->second->users > 0) return fail(MCS_EBUSY, "map %d is used by a session", map_id);
+        m = it->second;
+        ctx->maps.erase(it);
+        ctx->in_use -= m->bytes;
+    }
+    mcs_status s = set_device(ctx);
+    if (s != MCS_OK) return s;
+    (void)hipFree(m->cells);
+    delete m;
+    return MCS_OK;
+}
+
+mcs_status mcs_session_bytes(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M_max,
+                             uint64_t *bytes)
+{
+    if (!ctx || !bytes) return fail(MCS_EINVAL, "NULL argument");
+    if (N < 1 || M_max < 1) return fail(MCS_EINVAL, "N and M_max must be >= 1");
+    int K = 0;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->maps.find(map_id);
+        if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
+        K = it->second->K;
+    }
+    *bytes = session_layout(N, M_max, K).total;
+    return MCS_OK;
+}
+
+mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M_max,
+                              const float *poses, const float *kf_poses, int32_t *session_id)
+{
+    if (!ctx || !poses || !session_id) return fail(MCS_EINVAL, "NULL argument");
+    if (N < 1 || N > (1 << 28)) return fail(MCS_EINVAL, "N=%d outside [1, 2^28]", N);
+    if (M_max < 1 || M_max > (1 << 24)) return fail(MCS_EINVAL, "M_max=%d outside [1, 2^24]", M_max);
+    mcs_status s = set_device(ctx);
+    if (s != MCS_OK) return s;
+    if ((s = check_poses(poses, (size_t)N)) != MCS_OK) return s;
+    Map *m = nullptr;
+    const Layout *Lp = nullptr;
+    Layout L{};
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->maps.find(map_id);
+        if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
+        m = it->second;
+        if (m->K > 0 && !kf_poses) return fail(MCS_EINVAL, "keyframe map needs kf_poses");
+        L = session_layout(N, M_max, m->K);
+        Lp = &L;
+        if (!budget_allows(ctx, L.total))
+            return fail(MCS_EBUDGET, "session needs %zu bytes; budget %llu, in use %llu", L.total,
+                        (unsigned long long)ctx->budget, (unsigned long long)ctx->in_use);
+        ctx->in_use += L.total;
+        m->users++;
+    }
+    if (m->K > 0 && (s = check_poses(kf_poses, (size_t)N * m->K)) != MCS_OK) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->in_use -= L.total;
+        m->users--;
+        return s;
+    }
+    Session *ss = new Session;
+    ss->map = m;
+    ss->N = N;
+    ss->M_max = M_max;
+    ss->K = m->K;
+    ss->bytes = Lp->total;
+    auto undo = [&](mcs_status st) {
+        if (ss->block) (void)hipFree(ss->block);
+        if (ss->stream) (void)hipStreamDestroy(ss->stream);
+        if (ss->staged) (void)hipEventDestroy(ss->staged);
+        if (ss->pinned) (void)hipHostFree(ss->pinned);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->in_use -= L.total;
+        m->users--;
+        delete ss;
+        return st;
+    };
+    hipError_t e = hipMalloc(&ss->block, L.total);
+    if (e != hipSuccess) { ss->block = nullptr; return undo(hip_fail(e, "hipMalloc(session)")); }
+    e = hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { ss->stream = nullptr; return undo(hip_fail(e, "hipStreamCreate")); }
+    e = hipEventCreateWithFlags(&ss->staged, hipEventDisableTiming);
+    if (e != hipSuccess) { ss->staged = nullptr; return undo(hip_fail(e, "hipEventCreate")); }
+    char *b = (char *)ss->block;
+    ss->pose = (float *)(b + L.off[0]);
+    ss->pose_tmp = (float *)(b + L.off[1]);
+    ss->loglik = (float *)(b + L.off[2]);
+    ss->grad = (float *)(b + L.off[3]);
+    ss->kf_pose = (float *)(b + L.off[4]);
+    ss->kf_pose_tmp = (float *)(b + L.off[5]);
+    ss->noise = (float *)(b + L.off[6]);
+    ss->scan3 = (float *)(b + L.off[7]);
+    ss->scan4 = (float4 *)(b + L.off[8]);
+    ss->logw = (double *)(b + L.off[9]);
+    ss->cdf_local = (double *)(b + L.off[10]);
+    ss->part = (double *)(b + L.off[11]);
+    ss->counters = (unsigned int *)(b + L.off[12]);
+    ss->parents = (int32_t *)(b + L.off[13]);
+    ss->neighbors = (int32_t *)(b + L.off[14]);
+    ss->stats = (StepStatsDev *)(b + L.off[15]);
+    e = hipMemsetAsync(ss->block, 0, L.total, ss->stream);
+    if (e != hipSuccess) return undo(hip_fail(e, "hipMemset(session)"));
+    // Initial state: poses, uniform log-weights, identity parents.
+    std::vector<float> soa((size_t)7 * N);
+    aos_to_soa(poses, soa.data(), (size_t)N, 7);
+    std::vector<double> lw((size_t)N, -std::log((double)N));
+    std::vector<int32_t> par((size_t)N);
+    for (int i = 0; i < N; ++i) par[i] = i;
+    e = hipMemcpyAsync(ss->pose, soa.data(), soa.size() * 4, hipMemcpyHostToDevice, ss->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ss->logw, lw.data(), lw.size() * 8, hipMemcpyHostToDevice, ss->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ss->parents, par.data(), par.size() * 4, hipMemcpyHostToDevice,
+                           ss->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ss->stream);
+    if (e != hipSuccess) return undo(hip_fail(e, "session init upload"));
+    if (ss->K > 0 && (s = upload_kf(ss, kf_poses)) != MCS_OK) return undo(s);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ss->id = ctx->next_id++;
+    ctx->sessions[ss->id] = ss;
+    *session_id = ss->id;
+    return MCS_OK;
+}
+
+mcs_status mcs_session_destroy(mcs_ctx *ctx, int32_t sid)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    Session *s = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->sessions.find(sid);
+        if (it == ctx->sessions.end()) return fail(MCS_ENOTFOUND, "no session %d", sid);
+        s = it->second;
+        ctx->sessions.erase(it);
+    }
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(s->block);
+    (void)hipStreamDestroy(s->stream);
+    (void)hipEventDestroy(s->staged);
+    if (s->pinned) (void)hipHostFree(s->pinned);
+    prof_release(s);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->in_use -= s->bytes;
+    s->map->users--;
+    delete s;
+    return MCS_OK;
+}
+
+mcs_status mcs_set_particles(mcs_ctx *ctx, int32_t sid, const float *poses, const double *logw,
+                             const float *kf_poses)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s->stream), "sync");
+    if (poses) {
+        if ((st = check_poses(poses, (size_t)s->N)) != MCS_OK) return st;
+        std::vector<float> soa((size_t)7 * s->N);
+        aos_to_soa(poses, soa.data(), (size_t)s->N, 7);
+        HIP_TRY(hipMemcpyAsync(s->pose, soa.data(), soa.size() * 4, hipMemcpyHostToDevice,
+                               s->stream), "upload poses");
+        HIP_TRY(hipStreamSynchronize(s->stream), "sync");
+    }
+    if (logw) {
+        for (int i = 0; i < s->N; ++i)
+            if (std::isnan(logw[i]) || logw[i] == INFINITY)
+                return fail(MCS_EINVAL, "logw[%d] is NaN or +inf", i);
+        HIP_TRY(hipMemcpyAsync(s->logw, logw, (size_t)s->N * 8, hipMemcpyHostToDevice, s->stream),
+                "upload logw");
+        HIP_TRY(hipStreamSynchronize(s->stream), "sync");
+    }
+    if (kf_poses) {
+        if (s->K == 0) return fail(MCS_EINVAL, "session has no keyframes");
+        if ((st = check_poses(kf_poses, (size_t)s->N * s->K)) != MCS_OK) return st;
+        if ((st = upload_kf(s, kf_poses)) != MCS_OK) return st;
+    }
+    return MCS_OK;
+}
+
+mcs_status mcs_filter_step(mcs_ctx *ctx, int32_t sid, const float *scan, int32_t M,
+                           const float *noise, const mcs_step_params *p)
+{
+    if (!ctx || !scan) return fail(MCS_EINVAL, "NULL argument");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    mcs_status st = validate_params(s, p, M);
+    if (st != MCS_OK) return st;
+    for (int64_t k = 0; k < (int64_t)M * 3; ++k)
+        if (!std::isfinite(scan[k])) return fail(MCS_EINVAL, "scan value %lld not finite", (long long)k);
+    const bool use_noise = p->predict && noise;
+    if (use_noise)
+        for (int64_t k = 0; k < (int64_t)s->N * 6; ++k)
+            if (!std::isfinite(noise[k])) return fail(MCS_EINVAL, "noise value not finite");
+    if ((st = set_device(ctx)) != MCS_OK) return st;
+    // Stage through pinned host memory; wait for the previous upload from it.
+    const size_t need = (size_t)M * 3 + (use_noise ? (size_t)s->N * 6 : 0);
+    if (s->staged_pending) HIP_TRY(hipEventSynchronize(s->staged), "wait staging");
+    s->staged_pending = false;
+    if (s->pinned_floats < need) {
+        if (s->pinned) (void)hipHostFree(s->pinned);
+        s->pinned = nullptr;
+        s->pinned_floats = 0;
+        HIP_TRY(hipHostMalloc((void **)&s->pinned, need * sizeof(float), hipHostMallocDefault),
+                "hipHostMalloc");
+        s->pinned_floats = need;
+    }
+    std::memcpy(s->pinned, scan, (size_t)M * 3 * sizeof(float));
+    HIP_TRY(hipMemcpyAsync(s->scan3, s->pinned, (size_t)M * 3 * sizeof(float),
+                           hipMemcpyHostToDevice, s->stream), "upload scan");
+    if (use_noise) {
+        std::memcpy(s->pinned + (size_t)M * 3, noise, (size_t)s->N * 6 * sizeof(float));
+        HIP_TRY(hipMemcpyAsync(s->noise, s->pinned + (size_t)M * 3, (size_t)s->N * 6 * sizeof(float),
+                               hipMemcpyHostToDevice, s->stream), "upload noise");
+    }
+    HIP_TRY(hipEventRecord(s->staged, s->stream), "event");
+    s->staged_pending = true;
+    return enqueue_step(s, s->scan3, M, use_noise ? s->noise : nullptr, p, s->stream);
+}
+
+mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev, int32_t M,
+                               const float *noise_dev, const mcs_step_params *p, void *stream)
+{
+    if (!ctx || !scan_dev) return fail(MCS_EINVAL, "NULL argument");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    mcs_status st = validate_params(s, p, M);
+    if (st != MCS_OK) return st;
+    if ((st = set_device(ctx)) != MCS_OK) return st;
+    hipStream_t hs = stream ? (hipStream_t)stream : s->stream;
+    return enqueue_step(s, scan_dev, M, p->predict ? noise_dev : nullptr, p, hs);
+}
+
+mcs_status mcs_session_sync(mcs_ctx *ctx, int32_t sid)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    return MCS_OK;
+}
+
+mcs_status mcs_session_stream(mcs_ctx *ctx, int32_t sid, void **stream)
+{
+    if (!ctx || !stream) return fail(MCS_EINVAL, "NULL argument");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    *stream = (void *)s->stream;
+    return MCS_OK;
+}
+
+mcs_status mcs_get_particles(mcs_ctx *ctx, int32_t sid, float *poses, double *logw,
+                             int32_t *parents, float *loglik, float *grad, float *kf_poses,
+                             mcs_step_stats *stats)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    // Waits for everything queued on the device, whichever stream it used.
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    const size_t N = s->N;
+    if (poses) {
+        std::vector<float> soa(7 * N);
+        HIP_TRY(hipMemcpy(soa.data(), s->pose, soa.size() * 4, hipMemcpyDeviceToHost), "poses");
+        for (size_t i = 0; i < N; ++i) {
+            for (int c = 0; c < 7; ++c) poses[7 * i + c] = soa[c * N + i];
+            if (poses[7 * i + 3] < 0.0f)
+                for (int c = 3; c < 7; ++c) poses[7 * i + c] = -poses[7 * i + c];
+        }
+    }
+    if (logw) HIP_TRY(hipMemcpy(logw, s->logw, N * 8, hipMemcpyDeviceToHost), "logw");
+    if (parents) HIP_TRY(hipMemcpy(parents, s->parents, N * 4, hipMemcpyDeviceToHost), "parents");
+    if (loglik) HIP_TRY(hipMemcpy(loglik, s->loglik, N * 4, hipMemcpyDeviceToHost), "loglik");
+    if (grad) {
+        std::vector<float> soa(6 * N);
+        HIP_TRY(hipMemcpy(soa.data(), s->grad, soa.size() * 4, hipMemcpyDeviceToHost), "grad");
+        for (size_t i = 0; i < N; ++i)
+            for (int c = 0; c < 6; ++c) grad[6 * i + c] = soa[c * N + i];
+    }
+    if (kf_poses && s->K > 0) {
+        const size_t K = s->K;
+        std::vector<float> soa(K * 7 * N);
+        HIP_TRY(hipMemcpy(soa.data(), s->kf_pose, soa.size() * 4, hipMemcpyDeviceToHost), "kf");
+        for (size_t i = 0; i < N; ++i)
+            for (size_t k = 0; k < K; ++k) {
+                float *o = kf_poses + (i * K + k) * 7;
+                for (int c = 0; c < 7; ++c) o[c] = soa[(k * 7 + c) * N + i];
+                if (o[3] < 0.0f)
+                    for (int c = 3; c < 7; ++c) o[c] = -o[c];
+            }
+    }
+    if (stats) {
+        StepStatsDev d{};
+        HIP_TRY(hipMemcpy(&d, s->stats, sizeof d, hipMemcpyDeviceToHost), "stats");
+        stats->lse = d.lse;
+        stats->ess = d.ess;
+        stats->resampled = d.resampled;
+        stats->best = d.best;
+        for (int c = 0; c < 7; ++c) stats->best_pose[c] = d.best_pose[c];
+        if (stats->best_pose[3] < 0.0f)
+            for (int c = 3; c < 7; ++c) stats->best_pose[c] = -stats->best_pose[c];
+        stats->degenerate = d.degenerate;
+        stats->pad = 0;
+    }
+    return MCS_OK;
+}
+
+mcs_status mcs_session_profile(mcs_ctx *ctx, int32_t sid, int32_t enable)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    s->prof_used = 0;
+    s->prof_evals = 0;
+    s->prof_steps = 0;
+    for (double &v : s->prof_ms) v = 0.0;
+    s->profiling = enable != 0;
+    return MCS_OK;
+}
+
+mcs_status mcs_session_profile_read(mcs_ctx *ctx, int32_t sid, mcs_profile *out)
+{
+    if (!ctx || !out) return fail(MCS_EINVAL, "NULL argument");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    if ((st = prof_collect(s)) != MCS_OK) return st;
+    out->predict_ms = s->prof_ms[0];
+    out->eval_ms = s->prof_ms[1];
+    out->weights_ms = s->prof_ms[2];
+    out->resample_ms = s->prof_ms[3];
+    out->steps = s->prof_steps;
+    out->evals = s->prof_evals;
+    return MCS_OK;
+}
+
+}  // extern "C"

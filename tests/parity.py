@@ -1,0 +1,103 @@
+"""Helpers for the GPU-vs-oracle parity tests (stage-wise protocol).
+
+Tolerances (stated per result):
+* log-likelihood: |l_gpu - l_ref| <= 1e-5 |l_ref| + amb_l
+* gradient:       |g_gpu,c - g_ref,c| <= 1e-4 sum_j |dl_j/dxi_c| + amb_g,c
+  where amb_* is the oracle's allowance for points whose index coordinate is
+  within DELTA of a cell face: FP32 rounding of u in the kernel may put them
+  in the neighbouring cell, where the interpolant's one-sided derivative
+  differs.  Their count is reported.
+* pose step (oracle fed the GPU's own gradient): translation within 4 FP32
+  ulps of |t| plus 1e-7 m, rotation within 2e-6 rad.
+* log-sum-exp: relative 1e-13; ESS: relative 1e-10.
+* resampled indices: bit-exact except where the oracle's CDF is within 1e-12
+  of u_k (counted).
+"""
+
+import math
+
+import numpy as np
+
+import oracle
+
+DELTA = 5e-4          # index units; bound on the kernel's FP32 rounding of u
+TIE = 1e-12
+
+
+def quat_angle(qa, qb):
+    """Rotation angle between unit quaternions (rows), sign-invariant."""
+    qa = np.asarray(qa, np.float64)
+    qb = np.asarray(qb, np.float64)
+    qa = qa / np.linalg.norm(qa, axis=-1, keepdims=True)
+    qb = qb / np.linalg.norm(qb, axis=-1, keepdims=True)
+    d = np.abs(np.sum(qa * qb, axis=-1)).clip(0, 1)
+    return 2.0 * np.arccos(d)
+
+
+def ulp32(x):
+    x = np.abs(np.asarray(x, np.float32))
+    return np.spacing(x).astype(np.float64)
+
+
+def check_eval(loglik, grad, ref, idx=None, report=None):
+    """Compare GPU l, g (rows idx of the oracle's arrays) with the oracle."""
+    if idx is None:
+        idx = np.arange(len(loglik))
+    l_ref, g_ref = ref["loglik"][idx], ref["grad"][idx]
+    dl = np.abs(loglik.astype(np.float64) - l_ref)
+    tol_l = 1e-5 * np.abs(l_ref) + ref["amb_l"][idx]
+    dg = np.abs(grad.astype(np.float64) - g_ref)
+    tol_g = 1e-4 * ref["gabs"][idx] + ref["amb_g"][idx] + 1e-6
+    bad_l = np.nonzero(dl > tol_l)[0]
+    bad_g = np.nonzero(np.any(dg > tol_g, axis=1))[0]
+    if report is not None:
+        rel_l = dl / np.maximum(np.abs(l_ref), 1e-30)
+        clean = ref["n_amb"][idx] == 0
+        rel_g = (dg / np.maximum(ref["gabs"][idx], 1e-30))
+        report.update(max_rel_l=float(rel_l.max()),
+                      max_rel_g_clean=float(rel_g[clean].max()) if clean.any() else 0.0,
+                      n_amb=int(ref["n_amb"][idx].sum()), n=len(idx))
+    assert bad_l.size == 0, "loglik off for %d particles, first %d: %r vs %r (tol %r)" % (
+        bad_l.size, idx[bad_l[0]], loglik[bad_l[0]], l_ref[bad_l[0]], tol_l[bad_l[0]])
+    assert bad_g.size == 0, "grad off for %d particles, first %d: %r vs %r" % (
+        bad_g.size, idx[bad_g[0]], grad[bad_g[0]], g_ref[bad_g[0]])
+
+
+def check_step(poses_in, grad_gpu, poses_gpu, params):
+    """Oracle step from the GPU's gradient vs the GPU's stepped poses (rows aligned)."""
+    ref = oracle.step(poses_in, grad_gpu.astype(np.float64), params["alpha_t"], params["alpha_r"],
+                      params["rho_max"], params["phi_max"])
+    dt = np.abs(poses_gpu[:, :3].astype(np.float64) - ref[:, :3])
+    tol_t = 4 * ulp32(ref[:, :3]) + 1e-7
+    assert np.all(dt <= tol_t), "translation off by %g (tol %g)" % (dt.max(), tol_t.max())
+    ang = quat_angle(poses_gpu[:, 3:], ref[:, 3:])
+    assert np.all(ang <= 2e-6), "rotation off by %g rad" % ang.max()
+    return ref
+
+
+def check_weights_resample(logw_in, loglik_gpu, beta, u, out, policy, ess_frac=0.5):
+    """Weights and resampling, the oracle fed the GPU's likelihoods."""
+    N = len(logw_in)
+    lw_ref, L, ess = oracle.weights(logw_in, loglik_gpu.astype(np.float64), beta)
+    st = out["stats"]
+    assert abs(st["lse"] - L) <= 1e-13 * max(1.0, abs(L)), (st["lse"], L)
+    assert abs(st["ess"] - ess) <= 1e-10 * ess, (st["ess"], ess)
+    pre = np.asarray(logw_in, np.float64) + beta * loglik_gpu.astype(np.float64)
+    best = int(np.argmax(pre))
+    assert st["best"] == best
+    fire = {0: False, 1: True, 2: ess < ess_frac * N}[policy]
+    near_trigger = policy == 2 and abs(ess - ess_frac * N) < 1e-9 * N
+    if not near_trigger:
+        assert st["resampled"] == fire
+    n_tie = 0
+    if st["resampled"]:
+        a_ref, margin = oracle.resample(lw_ref, u)
+        mism = np.nonzero(out["parents"] != a_ref)[0]
+        n_tie = int(np.sum(margin < TIE))
+        assert np.all(margin[mism] < TIE), "resampled index mismatch at k=%d (%d vs %d)" % (
+            mism[0], out["parents"][mism[0]], a_ref[mism[0]])
+        assert np.allclose(out["logw"], -math.log(N), rtol=0, atol=1e-15)
+    else:
+        assert np.array_equal(out["parents"], np.arange(N))
+        assert np.allclose(out["logw"], lw_ref, rtol=0, atol=1e-13 * max(1.0, abs(L)))
+    return dict(lse=L, ess=ess, ties=n_tie)

@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library must load, export every entry point include/mcslam.h declares,
+and agree with the binding on struct layouts.  Without a GPU, creating a
+context must fail with a status code and a message, not abort.
+"""
+
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcslam.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcs_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2504_18056_amd import abi
+    if not os.path.exists(abi.LIB_PATH):
+        pytest.fail("libmcslam.so is not built (run __graft_entry__.build())")
+    return abi.lib()
+
+
+def test_exports_every_declared_entry_point(lib):
+    names = declared_functions()
+    assert {"mcs_init_map", "mcs_load_keyframes", "mcs_filter_step", "mcs_get_particles"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", os.path.join(ROOT, "paper_2504_18056_amd",
+                                                                     "libmcslam.so")],
+                         stdout=subprocess.PIPE, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (mcs_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_version_and_error_strings(lib):
+    from paper_2504_18056_amd import abi
+    assert abi.mcs_version().startswith("mcslam")
+    assert isinstance(abi.mcs_last_error(), str)
+
+
+def test_struct_layouts_match_header():
+    """Compile a C probe of sizeof/offsetof against the header and compare with ctypes."""
+    import ctypes as C
+
+    from paper_2504_18056_amd import abi
+    probe = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "mcslam.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
+int main(void) {
+  printf("mcs_grid_desc %zu\n", sizeof(mcs_grid_desc));
+  printf("mcs_step_params %zu\n", sizeof(mcs_step_params));
+  printf("mcs_step_stats %zu\n", sizeof(mcs_step_stats));
+  F(mcs_grid_desc, origin) F(mcs_grid_desc, res) F(mcs_grid_desc, dtype)
+  F(mcs_step_params, oob) F(mcs_step_params, ess_frac) F(mcs_step_params, u)
+  F(mcs_step_params, predict) F(mcs_step_params, delta_T) F(mcs_step_params, n_neighbors)
+  F(mcs_step_stats, resampled) F(mcs_step_stats, best_pose) F(mcs_step_stats, degenerate)
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "p.c")
+        exe = os.path.join(d, "p")
+        open(src, "w").write(probe)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        lines = subprocess.run([exe], stdout=subprocess.PIPE, text=True, check=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in lines if line)
+    assert int(got["mcs_grid_desc"]) == C.sizeof(abi.GridDesc)
+    assert int(got["mcs_step_params"]) == C.sizeof(abi.StepParams)
+    assert int(got["mcs_step_stats"]) == C.sizeof(abi.StepStats)
+    for key, val in got.items():
+        if "." in key:
+            sname, field = key.split(".")
+            cls = {"mcs_grid_desc": abi.GridDesc, "mcs_step_params": abi.StepParams,
+                   "mcs_step_stats": abi.StepStats}[sname]
+            assert getattr(cls, field).offset == int(val), key
+
+
+def test_create_without_gpu_reports_an_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2504_18056_amd import abi
+    with pytest.raises(abi.McsError) as e:
+        abi.mcs_create(0)
+    assert e.value.status in (abi.MCS_EDEVICE, abi.MCS_EINVAL)
+
+
+def test_null_arguments_are_rejected(lib):
+    import ctypes as C
+    from paper_2504_18056_amd import abi
+    assert lib.mcs_create(0, 0, None) == abi.MCS_EINVAL
+    assert lib.mcs_memory_in_use(None, None) == abi.MCS_EINVAL
+    assert lib.mcs_filter_step(None, 1, None, 1, None, None) == abi.MCS_EINVAL
+    assert lib.mcs_get_particles(None, 1, None, None, None, None, None, None, None) == abi.MCS_EINVAL
+    assert lib.mcs_destroy(None) == abi.MCS_OK
+    assert "NULL" in abi.mcs_last_error()
+    del C

@@ -1,0 +1,203 @@
+"""GPU parity: the HIP filter step through the C ABI against the FP64 oracle.
+
+Stage-wise protocol: each stage of the GPU step is checked against the oracle
+started from the GPU's own inputs to that stage (likelihood and gradient at
+the input poses; the pose step from the GPU's gradient; weights from the GPU's
+likelihoods; resampling from those weights).  Tolerances are in parity.py.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_18056_amd import abi
+from synth import configs
+
+from parity import DELTA, check_eval, check_step, check_weights_resample
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = abi.mcs_create(0)
+    yield c
+    abi.mcs_destroy(c)
+
+
+def grid_for(cfg, dtype):
+    if dtype == abi.GRID_FP16:
+        return oracle.quantize_fp16(cfg["grid"])
+    if dtype == abi.GRID_BF16:
+        return oracle.quantize_bf16(cfg["grid"])
+    return cfg["grid"]
+
+
+def one_step(ctx, cfg, params, dtype=abi.GRID_FP32, poses=None, logw=None, scan=None):
+    poses = cfg["poses"] if poses is None else poses
+    scan = cfg["scan"] if scan is None else scan
+    mid = abi.mcs_init_map(ctx, abi.grid_desc(cfg["dims"], cfg["origin"], cfg["h"], dtype), cfg["grid"])
+    sid = abi.mcs_session_create(ctx, mid, poses, M_max=scan.shape[0])
+    try:
+        if logw is not None:
+            abi.mcs_set_particles(ctx, sid, logw=logw)
+        abi.mcs_filter_step(ctx, sid, scan, params)
+        return abi.mcs_get_particles(ctx, sid, poses.shape[0])
+    finally:
+        abi.mcs_session_destroy(ctx, sid)
+        abi.mcs_release_map(ctx, mid)
+
+
+def full_check(cfg, out, params, dtype=abi.GRID_FP32, poses=None, logw=None, scan=None,
+               report=None):
+    poses = cfg["poses"] if poses is None else poses
+    scan = cfg["scan"] if scan is None else scan
+    N = poses.shape[0]
+    logw = np.full(N, -math.log(N)) if logw is None else logw
+    g = grid_for(cfg, dtype)
+    ref = oracle.evaluate(g, cfg["dims"], cfg["origin"], cfg["h"], params["eps"], scan, poses,
+                          oob_skip=params.get("oob", 0) == abi.OOB_SKIP, delta=DELTA)
+    check_eval(out["loglik"], out["grad"], ref, report=report)
+    anc = out["parents"]
+    check_step(poses[anc], out["grad"][anc], out["poses"], params)
+    return check_weights_resample(logw, out["loglik"], params.get("beta", 1.0), params["u"], out,
+                                  params.get("resample", abi.RESAMPLE_ALWAYS),
+                                  params.get("ess_frac", 0.5))
+
+
+@pytest.mark.parametrize("beta", [1.0, 0.002])
+def test_box_room_step(ctx, box_room, beta):
+    p = dict(box_room["params"], u=box_room["u"], beta=beta, resample=abi.RESAMPLE_ALWAYS)
+    out = one_step(ctx, box_room, p)
+    rep = {}
+    res = full_check(box_room, out, p, report=rep)
+    print("box_room beta=%g: %s ess=%.3f ties=%d" % (beta, rep, res["ess"], res["ties"]))
+    if beta < 1:
+        assert len(np.unique(out["parents"])) > 20   # a non-trivial resample
+
+
+@pytest.mark.parametrize("dtype", [abi.GRID_FP16, abi.GRID_BF16])
+def test_box_room_half_grids(ctx, box_room, dtype):
+    p = dict(box_room["params"], u=box_room["u"], beta=0.002)
+    out = one_step(ctx, box_room, p, dtype=dtype)
+    rep = {}
+    full_check(box_room, out, p, dtype=dtype, report=rep)
+    # Quantisation error against the FP32-grid oracle is stated, not bounded.
+    ref32 = oracle.evaluate(box_room["grid"], box_room["dims"], box_room["origin"], box_room["h"],
+                            p["eps"], box_room["scan"], box_room["poses"])
+    q = np.abs(out["loglik"] - ref32["loglik"]) / np.abs(ref32["loglik"])
+    print("dtype %d: %s; vs FP32 grid: max rel l %.3g" % (dtype, rep, q.max()))
+
+
+def test_ragged_sizes_and_policies(ctx):
+    # N not a multiple of 64, M not a multiple of the point batching.
+    c = configs.box_room(N=1000, n_rings=7, n_az=71, seed=77)
+    for policy, oob in [(abi.RESAMPLE_NEVER, abi.OOB_FLOOR), (abi.RESAMPLE_ESS, abi.OOB_SKIP),
+                        (abi.RESAMPLE_ALWAYS, abi.OOB_FLOOR)]:
+        p = dict(c["params"], u=0.37, beta=0.01, resample=policy, oob=oob)
+        full_check(c, one_step(ctx, c, p), p)
+
+
+def test_post_step_likelihood(ctx):
+    """post_eval: the weight uses l at the stepped pose, g stays the last gradient pass's."""
+    c = configs.box_room(N=300, seed=78)
+    p = dict(c["params"], u=0.5, beta=0.01, resample=abi.RESAMPLE_NEVER, post_eval=True)
+    out = one_step(ctx, c, p)
+    pre = oracle.evaluate(c["grid"], c["dims"], c["origin"], c["h"], p["eps"], c["scan"],
+                          c["poses"], delta=DELTA)
+    post = oracle.evaluate(c["grid"], c["dims"], c["origin"], c["h"], p["eps"], c["scan"],
+                           out["poses"], delta=DELTA)
+    check_eval(out["loglik"], out["grad"], dict(pre, loglik=post["loglik"], amb_l=post["amb_l"]))
+    check_step(c["poses"], out["grad"], out["poses"], p)
+
+
+@pytest.mark.parametrize("N,M", [(1, 1), (1, 300), (63, 1), (65, 513), (64, 4)])
+def test_tiny_and_tail_shapes(ctx, N, M):
+    c = configs.box_room(N=max(N, 2), seed=5)
+    poses = c["poses"][:N]
+    scan = c["scan"][:M]
+    p = dict(c["params"], u=0.5, beta=0.01, resample=abi.RESAMPLE_ALWAYS)
+    out = one_step(ctx, c, p, poses=poses, scan=scan)
+    full_check(c, out, p, poses=poses, scan=scan)
+
+
+def test_all_points_outside(ctx, box_room):
+    scan = box_room["scan"] + np.float32(500.0)
+    p = dict(box_room["params"], u=0.25, resample=abi.RESAMPLE_ALWAYS)
+    out = one_step(ctx, box_room, p, scan=scan)
+    M = scan.shape[0]
+    expect = M * math.log(np.float32(p["eps"]))
+    assert np.allclose(out["loglik"], expect, rtol=1e-6)
+    assert np.all(out["grad"] == 0)
+    # Equal weights: ESS = N and the systematic pass is the identity map.
+    assert abs(out["stats"]["ess"] - box_room["poses"].shape[0]) < 1e-6
+    full_check(box_room, out, p, scan=scan)
+
+
+def test_deterministic_and_iteration_fusion(ctx, box_room):
+    p = dict(box_room["params"], u=box_room["u"], beta=0.0, resample=abi.RESAMPLE_NEVER)
+    a = one_step(ctx, box_room, p)
+    b = one_step(ctx, box_room, p)
+    for k in ("poses", "loglik", "grad", "logw"):
+        assert np.array_equal(a[k], b[k]), k
+    # Three fused passes equal three single-pass steps chained through the pose.
+    p3 = dict(p, iters=3)
+    f = one_step(ctx, box_room, p3)
+    poses = box_room["poses"]
+    for _ in range(3):
+        s = one_step(ctx, box_room, p, poses=poses)
+        poses = s["poses"]
+    # Between launches the quaternion is renormalised once more, so the two
+    # paths agree to FP32 rounding rather than bitwise.
+    from parity import quat_angle
+    assert np.abs(f["poses"][:, :3] - poses[:, :3]).max() < 1e-4
+    assert quat_angle(f["poses"][:, 3:], poses[:, 3:]).max() < 1e-4
+    assert np.allclose(f["grad"], s["grad"], rtol=1e-3, atol=1e-3 * np.abs(s["grad"]).max())
+
+
+def test_prediction_matches_oracle(ctx, box_room):
+    rng = np.random.default_rng(3)
+    N = box_room["poses"].shape[0]
+    noise = (rng.normal(size=(N, 6)) * [0.05, 0.05, 0.05, 0.017, 0.017, 0.017]).astype(np.float32)
+    dq = np.array([0.999, 0.01, -0.02, 0.03])
+    dq /= np.linalg.norm(dq)
+    dT = np.concatenate([[0.6, -0.1, 0.02], dq]).astype(np.float32)
+    p = dict(box_room["params"], u=0.5, beta=0.0, resample=abi.RESAMPLE_NEVER,
+             alpha_t=0.0, alpha_r=0.0, delta_T=dT)
+    mid = abi.mcs_init_map(ctx, abi.grid_desc(box_room["dims"], box_room["origin"], box_room["h"]),
+                           box_room["grid"])
+    sid = abi.mcs_session_create(ctx, mid, box_room["poses"], M_max=512)
+    abi.mcs_filter_step(ctx, sid, box_room["scan"], p, noise=noise)
+    out = abi.mcs_get_particles(ctx, sid, N)
+    abi.mcs_session_destroy(ctx, sid)
+    abi.mcs_release_map(ctx, mid)
+    ref = oracle.predict(box_room["poses"], dT.astype(np.float64), noise)
+    from parity import quat_angle, ulp32
+    assert np.all(np.abs(out["poses"][:, :3] - ref[:, :3]) <= 8 * ulp32(ref[:, :3]) + 1e-6)
+    assert quat_angle(out["poses"][:, 3:], ref[:, 3:]).max() < 3e-6
+    # Likelihood at the predicted pose (zero gains: the step leaves the pose).
+    ev = oracle.evaluate(box_room["grid"], box_room["dims"], box_room["origin"], box_room["h"],
+                         p["eps"], box_room["scan"], out["poses"], delta=DELTA)
+    check_eval(out["loglik"], out["grad"], ev)
+
+
+def test_corridors_full_scale_sampled(ctx):
+    """N = 100,000, M = 2,048 on the 512 x 512 x 128 map: sampled particles vs the oracle."""
+    c = configs.corridors(N=100000, n_frames=2)
+    p = dict(c["params"], iters=1, u=float(c["u"][0]), beta=1.0, resample=abi.RESAMPLE_ESS)
+    out = one_step(ctx, c, p)
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(100000, 256, replace=False))
+    ref = oracle.evaluate(c["grid"], c["dims"], c["origin"], c["h"], p["eps"], c["scan"],
+                          c["poses"][idx], delta=DELTA)
+    full = dict(ref)
+    rep = {}
+    pre_l = out["loglik"][idx]
+    pre_g = out["grad"][idx]
+    check_eval(pre_l, pre_g, {k: v for k, v in full.items()}, idx=np.arange(256), report=rep)
+    print("corridors sampled:", rep)
+    anc = out["parents"]
+    check_step(c["poses"][anc], out["grad"][anc], out["poses"], p)
+    check_weights_resample(c["logw"], out["loglik"], 1.0, p["u"], out, abi.RESAMPLE_ESS)
