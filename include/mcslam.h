@@ -199,6 +199,13 @@ mcs_status mcs_get_particles(mcs_ctx *ctx, int32_t session_id, float *poses, dou
                              int32_t *parents, float *loglik, float *grad, float *kf_poses,
                              mcs_step_stats *stats);
 
+/* Keyframe sessions: the neighbour keyframes each particle used in the last
+ * step, nearest first (Sec. III-C.1; squared translation distances in FP32,
+ * ties to the smaller index).  out: N * n_neighbors int32, particle-major,
+ * indexed before resampling.  *n_neighbors receives the count (may be NULL). */
+mcs_status mcs_get_neighbors(mcs_ctx *ctx, int32_t session_id, int32_t *out,
+                             int32_t *n_neighbors);
+
 /* Wait for the session's queued work. */
 mcs_status mcs_session_sync(mcs_ctx *ctx, int32_t session_id);
 
@@ -222,6 +229,72 @@ mcs_status mcs_session_profile(mcs_ctx *ctx, int32_t session_id, int32_t enable)
 
 /* Wait for the session's profiled steps and return the accumulated times. */
 mcs_status mcs_session_profile_read(mcs_ctx *ctx, int32_t session_id, mcs_profile *out);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: a request loop over many concurrent sessions                     */
+/* ------------------------------------------------------------------------ */
+
+/* Each particle, and so each session, updates independently (Sec. III-A), so
+ * the steps of many sessions can share the device.  A server owns a worker
+ * thread that takes submitted frame requests in arrival order and, in
+ * MCS_SERVE_BATCHED mode, runs them in ticks: every tick takes at most one
+ * pending frame per session (up to max_batch sessions), writes a table of
+ * per-session step descriptors and work items, and replays one captured HIP
+ * graph of persistent kernels that process all sessions' work items
+ * together; up to two ticks are in flight, so frames arriving while a tick
+ * runs join the next one.  A session's frames always run in submission order.
+ * Results are identical to mcs_filter_step_dev on the same inputs (the
+ * kernels and their reduction order do not depend on the batch).
+ * MCS_SERVE_SERIAL runs one request at a time with the plain per-session
+ * launches and waits for each (the one-session-at-a-time baseline).
+ * Sessions served must be single-grid sessions whose map has the server's grid
+ * dtype; admission to device memory is the context's HBM budget
+ * (mcs_session_create returns MCS_EBUDGET when it would be exceeded). */
+typedef struct mcs_server mcs_server;
+
+#define MCS_SERVE_BATCHED 0
+#define MCS_SERVE_SERIAL  1
+
+typedef struct {
+    int64_t submit_ns;      /* host steady-clock time of mcs_server_submit */
+    int64_t launch_ns;      /* when the worker enqueued the request's work */
+    int64_t done_ns;        /* when the worker saw the work complete */
+    int32_t session_id;
+    int32_t tick;           /* tick (or serial slot) that ran it */
+} mcs_request_times;
+
+typedef struct {
+    int64_t requests;       /* completed requests */
+    int64_t ticks;          /* ticks (or serial steps) run */
+    int64_t evals;          /* particle x point evaluations completed */
+    int32_t max_batch_seen; /* most sessions in one tick */
+    int32_t pad;
+} mcs_server_stats;
+
+/* Create a server on ctx.  mode: MCS_SERVE_*; dtype: grid dtype of the
+ * sessions it serves; oob: MCS_OOB_*; max_batch: sessions per tick (>= 1);
+ * max_items: capacity of each per-stage work list per tick (0: 262144). */
+mcs_status mcs_server_create(mcs_ctx *ctx, int32_t mode, int32_t dtype, int32_t oob,
+                             int32_t max_batch, int32_t max_items, mcs_server **out);
+
+/* Complete every submitted request, stop the worker and free the server. */
+mcs_status mcs_server_destroy(mcs_server *srv);
+
+/* Queue one frame of a session: scan_dev (M*3 FP32) and noise_dev (N*6 FP32 or
+ * NULL) are device pointers borrowed until the request completes; p as for
+ * mcs_filter_step.  *request_id identifies the request. */
+mcs_status mcs_server_submit(mcs_server *srv, int32_t session_id, const float *scan_dev,
+                             int32_t M, const float *noise_dev, const mcs_step_params *p,
+                             int64_t *request_id);
+
+/* Wait until every request submitted so far has completed. */
+mcs_status mcs_server_drain(mcs_server *srv);
+
+/* Times of a completed request (MCS_EBUSY while it is still pending). */
+mcs_status mcs_server_times(mcs_server *srv, int64_t request_id, mcs_request_times *out);
+
+/* Counters of the server so far. */
+mcs_status mcs_server_stats_get(mcs_server *srv, mcs_server_stats *out);
 
 #ifdef __cplusplus
 }

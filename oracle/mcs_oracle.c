@@ -280,28 +280,15 @@ typedef struct {
     double h;
 } grid_t;
 
-/* Per-point log term and its gradient in world units at index-space point u.
- * Returns 1 when u is inside the grid.  Outside: term ln(eps) (or 0 when
- * oob_skip), zero gradient. */
-static int point_term(const grid_t *g, double eps, int oob_skip, const double u[3],
+/* Per-point log term and its gradient in world units for cell i0 at
+ * fractions f (each in [0, 1]); the cell must lie inside the grid. */
+static void cell_term(const grid_t *g, double eps, const int i0[3], const double f[3],
                       double *lj, double d[3])
 {
-    const int n[3] = {g->nx, g->ny, g->nz};
-    for (int a = 0; a < 3; ++a) {
-        if (!(u[a] >= 0.0 && u[a] < (double)(n[a] - 1))) {
-            *lj = oob_skip ? 0.0 : log(eps);
-            d[0] = d[1] = d[2] = 0.0;
-            return 0;
-        }
-    }
-    int i0[3];
     double w[3][2];
     for (int a = 0; a < 3; ++a) {
-        double fl = floor(u[a]);
-        double f = u[a] - fl;
-        i0[a] = (int)fl;
-        w[a][0] = 1.0 - f;
-        w[a][1] = f;
+        w[a][0] = 1.0 - f[a];
+        w[a][1] = f[a];
     }
     double G = 0.0, dG[3] = {0.0, 0.0, 0.0};
     for (int c = 0; c < 2; ++c)
@@ -317,13 +304,48 @@ static int point_term(const grid_t *g, double eps, int oob_skip, const double u[
     double den = G + eps;
     *lj = log(den);
     for (int a = 0; a < 3; ++a) d[a] = dG[a] / (g->h * den);
+}
+
+static int cell_inside(const grid_t *g, const int i0[3])
+{
+    const int n[3] = {g->nx, g->ny, g->nz};
+    for (int a = 0; a < 3; ++a)
+        if (i0[a] < 0 || i0[a] > n[a] - 2) return 0;
+    return 1;
+}
+
+/* Per-point log term and its gradient in world units at index-space point u.
+ * Returns 1 when u is inside the grid.  Outside: term ln(eps) (or 0 when
+ * oob_skip), zero gradient. */
+static int point_term(const grid_t *g, double eps, int oob_skip, const double u[3],
+                      double *lj, double d[3])
+{
+    const int n[3] = {g->nx, g->ny, g->nz};
+    for (int a = 0; a < 3; ++a) {
+        if (!(u[a] >= 0.0 && u[a] < (double)(n[a] - 1))) {
+            *lj = oob_skip ? 0.0 : log(eps);
+            d[0] = d[1] = d[2] = 0.0;
+            return 0;
+        }
+    }
+    int i0[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        double fl = floor(u[a]);
+        i0[a] = (int)fl;
+        f[a] = u[a] - fl;
+    }
+    cell_term(g, eps, i0, f, lj, d);
     return 1;
 }
 
 /* Allowance for a point whose cell (or inside/outside) decision sits within
  * `delta` index units of a cell face: the largest change of the term and of
- * its xi-derivative over the cells on either side of each such face.  A
- * kernel that rounds u differently may legitimately take either cell. */
+ * its xi-derivative over the positions the kernel may take within delta on
+ * either side of each such face.  Along one axis the term is, in each cell, a
+ * ratio of two linear functions of the fraction (monotone), so its extremes
+ * on [face - delta, face] and [face, face + delta] are at the ends: the lower
+ * cell at fractions 1 - delta and 1, the upper cell at 0 and delta. */
 static int point_ambiguity(const grid_t *g, double eps, int oob_skip, const double u[3],
                            const double v[3], const double R[9], double delta,
                            double lj0, const double d0[3], double *amb_l, double amb_g[6])
@@ -340,12 +362,35 @@ static int point_ambiguity(const grid_t *g, double eps, int oob_skip, const doub
     mat3T_vec(R, d0, g0x);
     cross3(v, d0, vx);
     mat3T_vec(R, vx, g0r);
-    for (int m = 0; m < (1 << na); ++m) {
-        double ua[3] = {u[0], u[1], u[2]};
-        for (int s = 0; s < na; ++s)
-            ua[axes[s]] = face[s] + (((m >> s) & 1) ? delta : -delta);
+    int base_i[3];
+    double base_f[3];
+    for (int a = 0; a < 3; ++a) {
+        double fl = floor(u[a]);
+        base_i[a] = (int)fl;
+        base_f[a] = u[a] - fl;
+    }
+    /* Per ambiguous axis: (cell offset from the face, fraction). */
+    const int cell_off[4] = {-1, -1, 0, 0};
+    const double frac[4] = {1.0 - delta, 1.0, 0.0, delta};
+    int combos = 1;
+    for (int s = 0; s < na; ++s) combos *= 4;
+    for (int m = 0; m < combos; ++m) {
+        int i0[3] = {base_i[0], base_i[1], base_i[2]};
+        double f[3] = {base_f[0], base_f[1], base_f[2]};
+        int mm = m;
+        for (int s = 0; s < na; ++s) {
+            int k = mm % 4;
+            mm /= 4;
+            i0[axes[s]] = (int)face[s] + cell_off[k];
+            f[axes[s]] = frac[k];
+        }
         double lj, d[3], gx[3], gr[3];
-        point_term(g, eps, oob_skip, ua, &lj, d);
+        if (cell_inside(g, i0)) {
+            cell_term(g, eps, i0, f, &lj, d);
+        } else {
+            lj = oob_skip ? 0.0 : log(eps);
+            d[0] = d[1] = d[2] = 0.0;
+        }
         mat3T_vec(R, d, gx);
         cross3(v, d, vx);
         mat3T_vec(R, vx, gr);
@@ -603,19 +648,23 @@ int oracle_resample(const double *logw, int N, double u, int *ancestors, double 
 /* ------------------------------------------------------------------------ */
 
 /* Neighbour keyframes of one particle: the n_nb smallest translation
- * distances |t - t_k| (ties to the smaller k), selected in ascending order. */
-static void select_neighbors(const double t[3], const float *kf, int K, int n_nb, int *nb)
+ * distances |t - t_k| (Sec. III-C.1), ties to the smaller k.  The choice is an
+ * integer decision, so it is taken in the kernel's precision: squared
+ * distance in FP32 as ((dx*dx + dy*dy) + dz*dz) with dx = t_x - t_k,x, each
+ * operation rounded once. */
+static void select_neighbors(const float *t, const float *kf, int K, int n_nb, int *nb)
 {
-    int used_cap = K;
-    char *used = (char *)calloc((size_t)used_cap, 1);
+    char *used = (char *)calloc((size_t)K, 1);
     for (int s = 0; s < n_nb; ++s) {
         int best = -1;
-        double bd = INFINITY;
+        float bd = INFINITY;
         for (int k = 0; k < K; ++k) {
             if (used[k]) continue;
-            double dx = t[0] - (double)kf[7 * k], dy = t[1] - (double)kf[7 * k + 1], dz = t[2] - (double)kf[7 * k + 2];
-            double d = sqrt(dx * dx + dy * dy + dz * dz);
-            if (d < bd) { bd = d; best = k; }
+            float dx = t[0] - kf[7 * k], dy = t[1] - kf[7 * k + 1], dz = t[2] - kf[7 * k + 2];
+            float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+            float s2 = xx + yy;
+            float d = s2 + zz;
+            if (d < bd || best < 0) { bd = d; best = k; }
         }
         nb[s] = best;
         if (best >= 0) used[best] = 1;
@@ -646,7 +695,7 @@ int oracle_kf_eval(const float *grids, int K, int nx, int ny, int nz, const doub
         const float *kf = kf_poses + (size_t)7 * K * i;
         int nb[64];
         int *nbp = (n_nb <= 64) ? nb : (int *)malloc(sizeof(int) * (size_t)n_nb);
-        select_neighbors(pose, kf, K, n_nb, nbp);
+        select_neighbors(poses + 7 * (size_t)i, kf, K, n_nb, nbp);
         eval_out o;
         memset(&o, 0, sizeof o);
         for (int s = 0; s < n_nb; ++s) {

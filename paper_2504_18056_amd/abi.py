@@ -87,6 +87,7 @@ def lib():
             "mcs_get_particles": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, P(StepStats)]),
             "mcs_session_sync": (i32, [vp, i32]),
             "mcs_session_stream": (i32, [vp, i32, P(vp)]),
+            "mcs_get_neighbors": (i32, [vp, i32, vp, P(i32)]),
             "mcs_session_profile": (i32, [vp, i32, i32]),
             "mcs_session_profile_read": (i32, [vp, i32, P(Profile)]),
         }
@@ -275,3 +276,12 @@ def mcs_session_profile_read(ctx, sid):
     p = Profile()
     _check(lib().mcs_session_profile_read(ctx, int(sid), C.byref(p)))
     return {f: getattr(p, f) for f, _ in Profile._fields_}
+
+
+def mcs_get_neighbors(ctx, sid, N, n_nb):
+    out = np.empty((N, n_nb), np.int32)
+    k = C.c_int32()
+    _check(lib().mcs_get_neighbors(ctx, int(sid), _ptr(out), C.byref(k)))
+    if k.value != n_nb:
+        raise McsError(MCS_EINVAL, "session used %d neighbours, asked for %d" % (k.value, n_nb))
+    return out

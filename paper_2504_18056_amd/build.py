@@ -41,13 +41,17 @@ def build(verbose=False, save_temps=False):
     os.makedirs(obj_dir, exist_ok=True)
     k_obj = os.path.join(obj_dir, "kernels.o")
     h_obj = os.path.join(obj_dir, "mcslam.o")
+    s_obj = os.path.join(obj_dir, "server.o")
     extra = ["-save-temps=obj"] if save_temps else []
     _run([hipcc, "-x", "hip", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS + extra +
          ["-c", os.path.join(CSRC, "kernels.hip"), "-o", k_obj], verbose)
     _run([hipcc, "-x", "hip", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS +
          ["-c", os.path.join(CSRC, "mcslam.cpp"), "-o", h_obj], verbose)
+    _run([hipcc, "-x", "hip", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS +
+         ["-c", os.path.join(CSRC, "server.cpp"), "-o", s_obj], verbose)
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, h_obj], verbose)
+    _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp, k_obj, h_obj,
+          s_obj], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -21,6 +21,8 @@
 
 #include <climits>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 
 namespace mcs {
 namespace {
@@ -104,6 +106,130 @@ __device__ __forceinline__ void right_exp(float t[3], float q[4], const float rh
     q[0] = nw; q[1] = nx; q[2] = ny; q[3] = nz;
 }
 
+// FP64 per-particle setup and pose step (O(N) work; the per-point loop stays
+// FP32).  A pose held in FP32 is taken as exact; the grid map is computed
+// from it in FP64 and rounded once, and the translation part is split as
+// b = b_int + b_frac (b_int an exact integer), so that no rounding of a
+// 3-digit offset is shared by every point of the particle.
+struct GridMap {
+    float A[9];            // R / h
+    float bf[3];           // b_frac in [0, 1)
+    float bi[3];           // b_int (integer valued)
+};
+
+__device__ __forceinline__ void grid_map(const float *t, const float *q, double ox, double oy,
+                                         double oz, double h, GridMap &m)
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    const double n = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+    w *= n; x *= n; y *= n; z *= n;
+    const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                         2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                         2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+    const double ih = 1.0 / h;
+    for (int e = 0; e < 9; ++e) m.A[e] = (float)(R[e] * ih);
+    const double o[3] = {ox, oy, oz};
+    for (int a = 0; a < 3; ++a) {
+        const double b = ((double)t[a] - o[a]) * ih - 0.5;
+        const double fl = floor(b);
+        m.bi[a] = (float)fl;
+        m.bf[a] = (float)(b - fl);
+    }
+}
+
+// Rotation matrix of a unit quaternion, FP64.
+__device__ __forceinline__ void rot_of_quat_d(double w, double x, double y, double z, double R[9])
+{
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// (t, q) <- (t, q) Exp([rho; phi]) in FP64: t += R V(phi) rho,
+// q <- q (x) q(phi), renormalised with w >= 0.  q must be a unit quaternion.
+__device__ __forceinline__ void right_exp_d(double t[3], double q[4], const double rho[3],
+                                            const double phi[3])
+{
+    const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+    double a, b, c, cw;
+    if (th2 < 1e-4) {
+        // Series in th^2 (th < 0.01): truncation below 1e-17.
+        a = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+        b = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+        c = 0.5 - th2 / 48.0 + th2 * th2 / 3840.0;
+        cw = 1.0 - th2 / 8.0 + th2 * th2 / 384.0;
+    } else {
+        const double th = sqrt(th2);
+        double s, co, sh, ch;
+        sincos(th, &s, &co);
+        sincos(0.5 * th, &sh, &ch);
+        a = 2.0 * sh * sh / th2;
+        b = (th - s) / (th2 * th);
+        c = sh / th;
+        cw = ch;
+    }
+    const double c1x = phi[1] * rho[2] - phi[2] * rho[1];
+    const double c1y = phi[2] * rho[0] - phi[0] * rho[2];
+    const double c1z = phi[0] * rho[1] - phi[1] * rho[0];
+    const double c2x = phi[1] * c1z - phi[2] * c1y;
+    const double c2y = phi[2] * c1x - phi[0] * c1z;
+    const double c2z = phi[0] * c1y - phi[1] * c1x;
+    const double vx = rho[0] + a * c1x + b * c2x;
+    const double vy = rho[1] + a * c1y + b * c2y;
+    const double vz = rho[2] + a * c1z + b * c2z;
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    double R[9];
+    rot_of_quat_d(w, x, y, z, R);
+    t[0] += R[0] * vx + R[1] * vy + R[2] * vz;
+    t[1] += R[3] * vx + R[4] * vy + R[5] * vz;
+    t[2] += R[6] * vx + R[7] * vy + R[8] * vz;
+    const double dx = c * phi[0], dy = c * phi[1], dz = c * phi[2];
+    const double nw = w * cw - x * dx - y * dy - z * dz;
+    const double nx = w * dx + x * cw + y * dz - z * dy;
+    const double ny = w * dy - x * dz + y * cw + z * dx;
+    const double nz = w * dz + x * dy - y * dx + z * cw;
+    const double m = (nw < 0.0 ? -1.0 : 1.0) / sqrt(nw * nw + nx * nx + ny * ny + nz * nz);
+    q[0] = nw * m; q[1] = nx * m; q[2] = ny * m; q[3] = nz * m;
+}
+
+__device__ __forceinline__ void load_pose_d(const float t[3], const float q[4], double td[3],
+                                            double qd[4])
+{
+    for (int a = 0; a < 3; ++a) td[a] = t[a];
+    const double n = 1.0 / sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] +
+                                (double)q[3] * q[3]);
+    for (int a = 0; a < 4; ++a) qd[a] = q[a] * n;
+}
+
+__device__ __forceinline__ void store_pose_d(const double td[3], const double qd[4], float t[3],
+                                             float q[4])
+{
+    for (int a = 0; a < 3; ++a) t[a] = (float)td[a];
+    for (int a = 0; a < 4; ++a) q[a] = (float)qd[a];
+}
+
+// Gradient-guided step of Eq. 7 from the body-frame gradient g: each block
+// of psi = [a_t g_rho; a_r g_phi] is scaled down to its bound, then
+// T <- T Exp(psi).  FP32: the increment is at most a decimetre, so t + dt is
+// rounded once at t's own precision.
+__device__ __forceinline__ void take_step(float t[3], float q[4], const float g[6], float alpha_t,
+                                          float alpha_r, float rho_max, float phi_max)
+{
+    float rho[3] = {alpha_t * g[0], alpha_t * g[1], alpha_t * g[2]};
+    float phi[3] = {alpha_r * g[3], alpha_r * g[4], alpha_r * g[5]};
+    const float nr = sqrtf(rho[0] * rho[0] + rho[1] * rho[1] + rho[2] * rho[2]);
+    const float np = sqrtf(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
+    if (nr > rho_max) {
+        const float k = rho_max / nr;
+        rho[0] *= k; rho[1] *= k; rho[2] *= k;
+    }
+    if (np > phi_max) {
+        const float k = phi_max / np;
+        phi[0] *= k; phi[1] *= k; phi[2] *= k;
+    }
+    right_exp(t, q, rho, phi);
+}
+
 // ---------------------------------------------------------------------------
 // Grid records
 // ---------------------------------------------------------------------------
@@ -174,7 +300,7 @@ template <> __device__ __forceinline__ void decode<2>(const Cell<2> &c, float v[
 
 // Running sums of one particle over its share of the scan.
 struct Acc {
-    double l;              // sum of log2(G + eps) (times the skip mask)
+    double l;              // sum of log2(G + eps)
     float ax, ay, az;      // sum of dG/du / (G + eps)
     float bx, by, bz;      // sum of v' x (dG/du / (G + eps)), v' = A p
 };
@@ -182,50 +308,64 @@ struct Acc {
 // Grid constants of one evaluation loop.
 struct GridK {
     __amdgpu_buffer_rsrc_t rs;
-    float nxm, nym, nzm;   // n - 1 per axis: the valid index range is [0, n - 1)
-    uint32_t cx, cxy;      // record strides: cells per row and per slab
+    uint32_t nxm, nym, nzm;  // cells per axis (n - 1): valid cell indices are [0, n - 1)
+    uint32_t cx, cxy;        // record strides: cells per row and per slab
     float eps;
-    float skip;            // 1: outside points contribute nothing; 0: ln(eps)
 };
 
-// Transformed point, cell fractions, inside mask and record offset.
+// Offset of a point outside the grid: beyond the buffer's range, so its
+// record loads return zeros (G = 0, dG = 0).  Record bytes are < 2^32 - 32.
+constexpr uint32_t kOutside = 0xFFFFFFE0u;
+
+// floor(x) as int32 in one instruction (saturating for out-of-range x).
+__device__ __forceinline__ int cvt_floor(float x)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// Transformed point, cell fractions and record offset.
 struct Pt {
     float vx, vy, vz;      // v' = A p (grid units)
-    float fx, fy, fz;
-    float m;               // 1 inside, 0 outside
-    uint32_t off;          // byte offset of the cell record
+    float fx, fy, fz;      // position inside the cell
+    uint32_t off;          // byte offset of the cell record, kOutside when outside
+    bool inside;
 };
 
 template <int DT, bool BIG>
-__device__ __forceinline__ Pt prep_point(const GridK &g, const float A[9], const float b[3],
-                                         float px, float py, float pz)
+__device__ __forceinline__ Pt prep_point(const GridK &g, const GridMap &gm, float px, float py,
+                                         float pz)
 {
     Pt p;
+    const float *A = gm.A;
     p.vx = fmaf(A[0], px, fmaf(A[1], py, A[2] * pz));
     p.vy = fmaf(A[3], px, fmaf(A[4], py, A[5] * pz));
     p.vz = fmaf(A[6], px, fmaf(A[7], py, A[8] * pz));
-    const float ux = p.vx + b[0], uy = p.vy + b[1], uz = p.vz + b[2];
-    const bool inside = (ux >= 0.0f) & (ux < g.nxm) & (uy >= 0.0f) & (uy < g.nym) &
-                        (uz >= 0.0f) & (uz < g.nzm);
-    p.m = inside ? 1.0f : 0.0f;
-    // Outside points read cell 0 and are masked.
-    const float sx = inside ? ux : 0.0f, sy = inside ? uy : 0.0f, sz = inside ? uz : 0.0f;
-    const float flx = floorf(sx), fly = floorf(sy), flz = floorf(sz);
-    p.fx = sx - flx; p.fy = sy - fly; p.fz = sz - flz;
-    const uint32_t ix = (uint32_t)flx, iy = (uint32_t)fly, iz = (uint32_t)flz;
-    const uint32_t rec = BIG ? ix + g.cx * iy + g.cxy * iz
-                             : ix + __umul24(g.cx, iy) + __umul24(g.cxy, iz);
-    p.off = rec << record_shift<DT>();
+    // u = (v' + b_frac) + b_int: the integer part is added last and exactly.
+    const float ux = (p.vx + gm.bf[0]) + gm.bi[0];
+    const float uy = (p.vy + gm.bf[1]) + gm.bi[1];
+    const float uz = (p.vz + gm.bf[2]) + gm.bi[2];
+    const int ix = cvt_floor(ux), iy = cvt_floor(uy), iz = cvt_floor(uz);
+    p.fx = __builtin_amdgcn_fractf(ux);
+    p.fy = __builtin_amdgcn_fractf(uy);
+    p.fz = __builtin_amdgcn_fractf(uz);
+    // 0 <= floor(u) < n - 1  <=>  0 <= u < n - 1; negative indices wrap high.
+    p.inside = ((uint32_t)ix < g.nxm) & ((uint32_t)iy < g.nym) & ((uint32_t)iz < g.nzm);
+    const uint32_t rec = BIG ? (uint32_t)ix + g.cx * (uint32_t)iy + g.cxy * (uint32_t)iz
+                             : (uint32_t)ix + __umul24(g.cx, (uint32_t)iy) +
+                                   __umul24(g.cxy, (uint32_t)iz);
+    p.off = p.inside ? (rec << record_shift<DT>()) : kOutside;
     return p;
 }
 
+// Trilinear value and gradient (index units) of one cell record.
 template <int DT>
-__device__ __forceinline__ void accumulate(const GridK &g, const Pt &p, const Cell<DT> &cell,
-                                           Acc &acc)
+__device__ __forceinline__ void trilinear(const Cell<DT> &cell, float fx, float fy, float fz,
+                                          float &G, float &gx, float &gy, float &gz)
 {
     float c[8];
     decode<DT>(cell, c);
-    const float fx = p.fx, fy = p.fy, fz = p.fz;
     // Along x on the four y/z edges.
     const float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
     const float e00 = fmaf(fx, d00, c[0]), e10 = fmaf(fx, d10, c[2]);
@@ -234,29 +374,67 @@ __device__ __forceinline__ void accumulate(const GridK &g, const Pt &p, const Ce
     const float gy0 = e10 - e00, gy1 = e11 - e01;
     const float f0 = fmaf(fy, gy0, e00), f1 = fmaf(fy, gy1, e01);
     // Along z.
-    const float gz = f1 - f0;
-    const float G = fmaf(fz, gz, f0) * p.m;
-    const float dGy = fmaf(fz, gy1 - gy0, gy0);
+    gz = f1 - f0;
+    G = fmaf(fz, gz, f0);
+    gy = fmaf(fz, gy1 - gy0, gy0);
     const float dx0 = fmaf(fy, d10 - d00, d00), dx1 = fmaf(fy, d11 - d01, d01);
-    const float dGx = fmaf(fz, dx1 - dx0, dx0);
-    const float den = G + g.eps;
-    // Outside: G = 0 gives log2(eps); with skipping the term is scaled to 0.
-    const float keep = fmaf(g.skip, p.m - 1.0f, 1.0f);
-    acc.l += (double)(fast_log2(den) * keep);
-    const float r = fast_rcp(den) * p.m;
-    const float dx = dGx * r, dy = dGy * r, dz = gz * r;
+    gx = fmaf(fz, dx1 - dx0, dx0);
+}
+
+// Gradient sums of one point given 1/(G + eps).
+__device__ __forceinline__ void add_grad(const Pt &p, float gx, float gy, float gz, float inv,
+                                         Acc &acc)
+{
+    const float dx = gx * inv, dy = gy * inv, dz = gz * inv;
     acc.ax += dx; acc.ay += dy; acc.az += dz;
     acc.bx = fmaf(p.vy, dz, fmaf(-p.vz, dy, acc.bx));
     acc.by = fmaf(p.vz, dx, fmaf(-p.vx, dz, acc.by));
     acc.bz = fmaf(p.vx, dy, fmaf(-p.vy, dx, acc.bz));
 }
 
-// Points [j0, j1) of the scan against one pose, U points per batch: the U
-// record loads are issued before any of their arithmetic.
-template <int DT, bool BIG, int U>
-__device__ __forceinline__ void eval_range(const GridK &g, scan_ptr scan, int j0, int j1,
-                                           const float A[9], const float b[3], Acc &acc)
+// Two points share one log2 and one reciprocal:
+//   log2(d0) + log2(d1) = log2(d0 d1),  1/d0 = d1 / (d0 d1),  1/d1 = d0 / (d0 d1),
+// with d in [eps, 1 + eps], so d0 d1 stays a normal FP32 number.  An outside
+// point has G = 0 (zero record), d = eps and a zero gradient; with SKIP its
+// factor is 1 so it adds nothing to the log sum.
+template <int DT, bool SKIP>
+__device__ __forceinline__ void accumulate2(const GridK &g, const Pt &p0, const Cell<DT> &c0,
+                                            const Pt &p1, const Cell<DT> &c1, Acc &acc)
 {
+    float G0, x0, y0, z0, G1, x1, y1, z1;
+    trilinear<DT>(c0, p0.fx, p0.fy, p0.fz, G0, x0, y0, z0);
+    trilinear<DT>(c1, p1.fx, p1.fy, p1.fz, G1, x1, y1, z1);
+    float d0 = G0 + g.eps, d1 = G1 + g.eps;
+    if (SKIP) {
+        d0 = p0.inside ? d0 : 1.0f;
+        d1 = p1.inside ? d1 : 1.0f;
+    }
+    const float prod = d0 * d1;
+    acc.l += (double)fast_log2(prod);
+    const float r = fast_rcp(prod);
+    add_grad(p0, x0, y0, z0, d1 * r, acc);
+    add_grad(p1, x1, y1, z1, d0 * r, acc);
+}
+
+template <int DT, bool SKIP>
+__device__ __forceinline__ void accumulate1(const GridK &g, const Pt &p, const Cell<DT> &c,
+                                            Acc &acc)
+{
+    float G, x, y, z;
+    trilinear<DT>(c, p.fx, p.fy, p.fz, G, x, y, z);
+    float d = G + g.eps;
+    if (SKIP) d = p.inside ? d : 1.0f;
+    acc.l += (double)fast_log2(d);
+    add_grad(p, x, y, z, fast_rcp(d), acc);
+}
+
+// Points [j0, j1) of the scan against one pose.  U (even) points per batch:
+// all U record loads are issued before any of their arithmetic.
+template <int DT, bool BIG, bool SKIP, int U>
+__device__ __forceinline__ void eval_range(const GridK &g, scan_ptr scan, int j0, int j1,
+                                           const GridMap &gm, Acc &acc)
+{
+    static_assert(U % 2 == 0, "U must be even");
     int j = j0;
     for (; j + U <= j1; j += U) {
         Pt p[U];
@@ -264,27 +442,188 @@ __device__ __forceinline__ void eval_range(const GridK &g, scan_ptr scan, int j0
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const f4v s = scan[j + k];
-            p[k] = prep_point<DT, BIG>(g, A, b, s.x, s.y, s.z);
+            p[k] = prep_point<DT, BIG>(g, gm, s.x, s.y, s.z);
             load_cell<DT>(g.rs, p[k].off, c[k]);
         }
 #pragma unroll
-        for (int k = 0; k < U; ++k) accumulate<DT>(g, p[k], c[k], acc);
+        for (int k = 0; k < U; k += 2) accumulate2<DT, SKIP>(g, p[k], c[k], p[k + 1], c[k + 1], acc);
     }
     for (; j < j1; ++j) {
         const f4v s = scan[j];
-        const Pt p = prep_point<DT, BIG>(g, A, b, s.x, s.y, s.z);
+        const Pt p = prep_point<DT, BIG>(g, gm, s.x, s.y, s.z);
         Cell<DT> c;
         load_cell<DT>(g.rs, p.off, c);
-        accumulate<DT>(g, p, c, acc);
+        accumulate1<DT, SKIP>(g, p, c, acc);
+    }
+}
+
+// FP64 transform variant: the grid map stays in FP64 (A = R/h, b), points
+// arrive as FP64 (scalar loads of the FP64 copy of the scan), and u = A p + b,
+// floor(u) and the fraction are computed in FP64; only the fraction and v'
+// are rounded to FP32.  This removes the one systematic FP32 error left, the
+// rounding of A itself, at ~6 extra full-rate FP64 ops per evaluation.
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) d4v *scan64_ptr;
+
+struct GridMap64 {
+    double A[9];
+    double b[3];
+};
+
+__device__ __forceinline__ void grid_map64(const float *t, const float *q, double ox, double oy,
+                                           double oz, double h, GridMap64 &m)
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    const double n = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+    w *= n; x *= n; y *= n; z *= n;
+    double R[9];
+    rot_of_quat_d(w, x, y, z, R);
+    const double ih = 1.0 / h;
+    for (int e = 0; e < 9; ++e) m.A[e] = R[e] * ih;
+    m.b[0] = ((double)t[0] - ox) * ih - 0.5;
+    m.b[1] = ((double)t[1] - oy) * ih - 0.5;
+    m.b[2] = ((double)t[2] - oz) * ih - 0.5;
+}
+
+// floor(x) as int32 in one instruction (saturating for out-of-range x).
+__device__ __forceinline__ int cvt_floor_d(double x)
+{
+    int r;
+    const double f = floor(x);
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(f));
+    return r;
+}
+
+template <int DT, bool BIG>
+__device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, double px,
+                                           double py, double pz)
+{
+    Pt p;
+    const double *A = gm.A;
+    const double vx = fma(A[0], px, fma(A[1], py, A[2] * pz));
+    const double vy = fma(A[3], px, fma(A[4], py, A[5] * pz));
+    const double vz = fma(A[6], px, fma(A[7], py, A[8] * pz));
+    const double ux = vx + gm.b[0], uy = vy + gm.b[1], uz = vz + gm.b[2];
+    p.vx = (float)vx; p.vy = (float)vy; p.vz = (float)vz;
+    const int ix = cvt_floor_d(ux), iy = cvt_floor_d(uy), iz = cvt_floor_d(uz);
+    p.fx = (float)__builtin_amdgcn_fract(ux);
+    p.fy = (float)__builtin_amdgcn_fract(uy);
+    p.fz = (float)__builtin_amdgcn_fract(uz);
+    p.inside = ((uint32_t)ix < g.nxm) & ((uint32_t)iy < g.nym) & ((uint32_t)iz < g.nzm);
+    const uint32_t rec = BIG ? (uint32_t)ix + g.cx * (uint32_t)iy + g.cxy * (uint32_t)iz
+                             : (uint32_t)ix + __umul24(g.cx, (uint32_t)iy) +
+                                   __umul24(g.cxy, (uint32_t)iz);
+    p.off = p.inside ? (rec << record_shift<DT>()) : kOutside;
+    return p;
+}
+
+template <int DT, bool BIG, bool SKIP, int U>
+__device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, int j0, int j1,
+                                             const GridMap64 &gm, Acc &acc)
+{
+    static_assert(U % 2 == 0, "U must be even");
+    int j = j0;
+    for (; j + U <= j1; j += U) {
+        Pt p[U];
+        Cell<DT> c[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const d4v s = scan[j + k];
+            p[k] = prep_point64<DT, BIG>(g, gm, s.x, s.y, s.z);
+            load_cell<DT>(g.rs, p[k].off, c[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < U; k += 2) accumulate2<DT, SKIP>(g, p[k], c[k], p[k + 1], c[k + 1], acc);
+    }
+    for (; j < j1; ++j) {
+        const d4v s = scan[j];
+        const Pt p = prep_point64<DT, BIG>(g, gm, s.x, s.y, s.z);
+        Cell<DT> c;
+        load_cell<DT>(g.rs, p.off, c);
+        accumulate1<DT, SKIP>(g, p, c, acc);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Likelihood + gradient + pose step, single grid
+// Likelihood + gradient + pose step, single grid: one 64-particle tile
 // ---------------------------------------------------------------------------
 
-template <int DT, bool BIG, int W, int U>
-__global__ __launch_bounds__(64 * W) void k_eval_step(EvalArgs a)
+// Body-frame gradient of the 7 sums: g_rho = R^T (sum d') / h,
+// g_phi = R^T sum (v' x d'), R from the tile's pose q.
+__device__ __forceinline__ void body_gradient(const float q[4], const float s[6], float inv_h,
+                                              float gr[6])
+{
+    float qn[4] = {q[0], q[1], q[2], q[3]};
+    normalize_quat(qn[0], qn[1], qn[2], qn[3]);
+    float R[9];
+    rot_of_quat(qn[0], qn[1], qn[2], qn[3], R);
+    const float ax = s[0] * inv_h, ay = s[1] * inv_h, az = s[2] * inv_h;
+    gr[0] = R[0] * ax + R[3] * ay + R[6] * az;
+    gr[1] = R[1] * ax + R[4] * ay + R[7] * az;
+    gr[2] = R[2] * ax + R[5] * ay + R[8] * az;
+    gr[3] = R[0] * s[3] + R[3] * s[4] + R[6] * s[5];
+    gr[4] = R[1] * s[3] + R[4] * s[4] + R[7] * s[5];
+    gr[5] = R[2] * s[3] + R[5] * s[4] + R[8] * s[5];
+}
+
+// Load the tile's poses into LDS (normalised quaternions).
+__device__ __forceinline__ void load_tile_pose(const StepDesc &d, int i, int lane, float (*s_pose)[64])
+{
+    const int N = d.N;
+    const int ic = i < N ? i : N - 1;
+    float q[4] = {d.pose[3 * N + ic], d.pose[4 * N + ic], d.pose[5 * N + ic], d.pose[6 * N + ic]};
+    normalize_quat(q[0], q[1], q[2], q[3]);
+    s_pose[0][lane] = d.pose[ic]; s_pose[1][lane] = d.pose[N + ic]; s_pose[2][lane] = d.pose[2 * N + ic];
+    s_pose[3][lane] = q[0]; s_pose[4][lane] = q[1]; s_pose[5][lane] = q[2]; s_pose[6][lane] = q[3];
+}
+
+// Reduce the W partial sums (fixed order), store l and g, take the step.
+template <int W>
+__device__ __forceinline__ void tile_epilogue(const StepDesc &d, int i, int lane, int pass,
+                                              const double (*s_l)[64], const float (*s_g)[W][64],
+                                              float (*s_pose)[64])
+{
+    double l = 0.0;
+    float s[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int w = 0; w < W; ++w) {
+        l += s_l[w][lane];
+        for (int c = 0; c < 6; ++c) s[c] += s_g[c][w][lane];
+    }
+    float t[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
+    float q[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
+    float gr[6];
+    if (d.K > 0) {
+        for (int c = 0; c < 6; ++c) gr[c] = s[c];   // already body-frame, summed over neighbours
+    } else {
+        body_gradient(q, s, d.inv_h, gr);
+    }
+    const int N = d.N;
+    const bool stepping = pass < d.iters;
+    if (i < N) {
+        d.loglik[i] = (float)(l * kLn2);
+        if (stepping)
+            for (int c = 0; c < 6; ++c) d.grad[c * N + i] = gr[c];
+    }
+    if (stepping) {
+        take_step(t, q, gr, d.alpha_t, d.alpha_r, d.rho_max, d.phi_max);
+        s_pose[0][lane] = t[0]; s_pose[1][lane] = t[1]; s_pose[2][lane] = t[2];
+        s_pose[3][lane] = q[0]; s_pose[4][lane] = q[1]; s_pose[5][lane] = q[2]; s_pose[6][lane] = q[3];
+    }
+}
+
+__device__ __forceinline__ void store_tile_pose(const StepDesc &d, int i, int lane,
+                                                const float (*s_pose)[64])
+{
+    const int N = d.N;
+    if (i < N) {
+        d.pose[i] = s_pose[0][lane]; d.pose[N + i] = s_pose[1][lane]; d.pose[2 * N + i] = s_pose[2][lane];
+        d.pose[3 * N + i] = s_pose[3][lane]; d.pose[4 * N + i] = s_pose[4][lane];
+        d.pose[5 * N + i] = s_pose[5][lane]; d.pose[6 * N + i] = s_pose[6][lane];
+    }
+}
+
+template <int DT, bool BIG, bool SKIP, int W, int U, bool TX64>
+__device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
 {
     __shared__ double s_l[W][64];
     __shared__ float s_g[6][W][64];
@@ -292,124 +631,281 @@ __global__ __launch_bounds__(64 * W) void k_eval_step(EvalArgs a)
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int N = a.N;
-    const int i = blockIdx.x * 64 + lane;
-    const int ic = i < N ? i : N - 1;
-
-    float t[3] = {a.pose[ic], a.pose[N + ic], a.pose[2 * N + ic]};
-    float q[4] = {a.pose[3 * N + ic], a.pose[4 * N + ic], a.pose[5 * N + ic], a.pose[6 * N + ic]};
+    const int i = tile * 64 + lane;
+    if (wave == 0) load_tile_pose(d, i, lane, s_pose);
 
     GridK g;
-    const uint32_t n_rec = (uint32_t)(a.grid.nx - 1) * (uint32_t)(a.grid.ny - 1) *
-                           (uint32_t)(a.grid.nz - 1);
-    g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(a.grid.cells), (short)0,
-                                             (int)(n_rec << record_shift<DT>()), kRsrcWord3);
-    g.nxm = (float)(a.grid.nx - 1);
-    g.nym = (float)(a.grid.ny - 1);
-    g.nzm = (float)(a.grid.nz - 1);
-    g.cx = (uint32_t)(a.grid.nx - 1);
-    g.cxy = (uint32_t)(a.grid.nx - 1) * (uint32_t)(a.grid.ny - 1);
-    g.eps = a.eps;
-    g.skip = a.oob_skip ? 1.0f : 0.0f;
-    const float inv_h = a.grid.inv_h;
-    const scan_ptr scan = (scan_ptr)a.scan;
-
-    const int M = a.M;
+    const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
+    g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
+                                             (int)((cxn * cyn * czn) << record_shift<DT>()),
+                                             kRsrcWord3);
+    g.nxm = cxn; g.nym = cyn; g.nzm = czn;
+    g.cx = cxn;
+    g.cxy = cxn * cyn;
+    g.eps = d.eps;
+    const scan_ptr scan = (scan_ptr)d.scan4;
+    const int M = d.M;
     const int chunk = (M + W - 1) / W;
     const int j0 = min(M, wave * chunk);
     const int j1 = min(M, j0 + chunk);
-    const int passes = a.iters + a.post_eval;
+    const int passes = d.iters + d.post_eval;
+    __syncthreads();
 
     for (int pass = 0; pass < passes; ++pass) {
-        normalize_quat(q[0], q[1], q[2], q[3]);
-        float A[9], b[3];
-        {
-            float R[9];
-            rot_of_quat(q[0], q[1], q[2], q[3], R);
-            for (int e = 0; e < 9; ++e) A[e] = R[e] * inv_h;
-        }
-        b[0] = fmaf(t[0] - a.grid.ox, inv_h, -0.5f);
-        b[1] = fmaf(t[1] - a.grid.oy, inv_h, -0.5f);
-        b[2] = fmaf(t[2] - a.grid.oz, inv_h, -0.5f);
-
         Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        eval_range<DT, BIG, U>(g, scan, j0, j1, A, b, acc);
-
+        {
+            const float t[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
+            const float q[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
+            if (TX64) {
+                GridMap64 gm;
+                grid_map64(t, q, d.ox, d.oy, d.oz, d.h, gm);
+                eval_range64<DT, BIG, SKIP, U>(g, (scan64_ptr)d.scan8, j0, j1, gm, acc);
+            } else {
+                GridMap gm;
+                grid_map(t, q, d.ox, d.oy, d.oz, d.h, gm);
+                eval_range<DT, BIG, SKIP, U>(g, scan, j0, j1, gm, acc);
+            }
+        }
         s_l[wave][lane] = acc.l;
         s_g[0][wave][lane] = acc.ax; s_g[1][wave][lane] = acc.ay; s_g[2][wave][lane] = acc.az;
         s_g[3][wave][lane] = acc.bx; s_g[4][wave][lane] = acc.by; s_g[5][wave][lane] = acc.bz;
         __syncthreads();
-        if (wave == 0) {
-            double l = 0.0;
-            float s[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            for (int w = 0; w < W; ++w) {
-                l += s_l[w][lane];
-                for (int c = 0; c < 6; ++c) s[c] += s_g[c][w][lane];
-            }
-            // World gradient of l wrt the point is (sum d') / h; the body-frame
-            // gradient is g_rho = R^T (sum d') / h, g_phi = R^T sum (v' x d').
-            float R[9];
-            rot_of_quat(q[0], q[1], q[2], q[3], R);
-            const float ax = s[0] * inv_h, ay = s[1] * inv_h, az = s[2] * inv_h;
-            float gr[6];
-            gr[0] = R[0] * ax + R[3] * ay + R[6] * az;
-            gr[1] = R[1] * ax + R[4] * ay + R[7] * az;
-            gr[2] = R[2] * ax + R[5] * ay + R[8] * az;
-            gr[3] = R[0] * s[3] + R[3] * s[4] + R[6] * s[5];
-            gr[4] = R[1] * s[3] + R[4] * s[4] + R[7] * s[5];
-            gr[5] = R[2] * s[3] + R[5] * s[4] + R[8] * s[5];
-            const bool stepping = pass < a.iters;
-            if (i < N) {
-                a.loglik[i] = (float)(l * kLn2);
-                if (stepping)
-                    for (int c = 0; c < 6; ++c) a.grad[c * N + i] = gr[c];
-            }
-            if (stepping) {
-                float rho[3] = {a.alpha_t * gr[0], a.alpha_t * gr[1], a.alpha_t * gr[2]};
-                float phi[3] = {a.alpha_r * gr[3], a.alpha_r * gr[4], a.alpha_r * gr[5]};
-                const float nr = sqrtf(rho[0] * rho[0] + rho[1] * rho[1] + rho[2] * rho[2]);
-                const float np = sqrtf(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
-                if (nr > a.rho_max) {
-                    const float k = a.rho_max / nr;
-                    rho[0] *= k; rho[1] *= k; rho[2] *= k;
-                }
-                if (np > a.phi_max) {
-                    const float k = a.phi_max / np;
-                    phi[0] *= k; phi[1] *= k; phi[2] *= k;
-                }
-                right_exp(t, q, rho, phi);
-            }
-            s_pose[0][lane] = t[0]; s_pose[1][lane] = t[1]; s_pose[2][lane] = t[2];
-            s_pose[3][lane] = q[0]; s_pose[4][lane] = q[1]; s_pose[5][lane] = q[2];
-            s_pose[6][lane] = q[3];
-        }
+        if (wave == 0) tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose);
         __syncthreads();
-        t[0] = s_pose[0][lane]; t[1] = s_pose[1][lane]; t[2] = s_pose[2][lane];
-        q[0] = s_pose[3][lane]; q[1] = s_pose[4][lane]; q[2] = s_pose[5][lane];
-        q[3] = s_pose[6][lane];
     }
-    if (wave == 0 && i < N) {
-        normalize_quat(q[0], q[1], q[2], q[3]);
-        a.pose[i] = t[0]; a.pose[N + i] = t[1]; a.pose[2 * N + i] = t[2];
-        a.pose[3 * N + i] = q[0]; a.pose[4 * N + i] = q[1]; a.pose[5 * N + i] = q[2];
-        a.pose[6 * N + i] = q[3];
-    }
+    if (wave == 0) store_tile_pose(d, i, lane, s_pose);
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// Small kernels: scan packing, grid records, prediction
+// Keyframe map: sum over neighbour keyframes (Eq. 2) under T_k^-1 T (Eq. 4)
 // ---------------------------------------------------------------------------
 
-// Packs M x 3 points into float4.  A point with a non-finite or huge
-// coordinate becomes (1e30, 1e30, 1e30): outside every grid, with finite
-// products in the kernels, so it contributes exactly like an outside point.
-__global__ void k_pack_scan(const float *__restrict__ s3, float4 *__restrict__ s4, int M)
+// Squared translation distance in FP32 with a fixed operation order (no
+// contraction): the neighbour choice is an integer decision that the checks
+// reproduce bit for bit.
+__device__ __forceinline__ float dist2_rn(float ax, float ay, float az, float bx, float by, float bz)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M) return;
-    const float x = s3[3 * j], y = s3[3 * j + 1], z = s3[3 * j + 2];
+    const float dx = __fsub_rn(ax, bx), dy = __fsub_rn(ay, by), dz = __fsub_rn(az, bz);
+    return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+}
+
+template <int DT>
+__device__ __forceinline__ void load_cell_g(uint64_t addr, Cell<DT> &c);
+template <>
+__device__ __forceinline__ void load_cell_g<0>(uint64_t addr, Cell<0> &c)
+{
+    const f4v *p = reinterpret_cast<const f4v *>(addr);
+    c.a = p[0];
+    c.b = p[1];
+}
+template <>
+__device__ __forceinline__ void load_cell_g<1>(uint64_t addr, Cell<1> &c)
+{
+    c.a = *reinterpret_cast<const u4v *>(addr);
+}
+template <>
+__device__ __forceinline__ void load_cell_g<2>(uint64_t addr, Cell<2> &c)
+{
+    c.a = *reinterpret_cast<const u4v *>(addr);
+}
+
+template <int DT, bool SKIP, int W>
+__device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
+{
+    __shared__ double s_l[W][64];
+    __shared__ float s_g[6][W][64];
+    __shared__ float s_pose[7][64];
+    __shared__ float s_aff[kKfMaxNb][15][64];   // per neighbour: A' (9), b_frac (3), b_int (3)
+    __shared__ int s_nb[kKfMaxNb][64];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int N = d.N, K = d.K, n_nb = d.n_nb;
+    const int i = tile * 64 + lane;
+    const int ic = i < N ? i : N - 1;
+    const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
+    const float nxm = (float)cxn, nym = (float)cyn, nzm = (float)czn;
+    const uint64_t grid_bytes = (uint64_t)d.grid_stride;
+    const uint64_t base = (uint64_t)d.cells;
+    const scan_ptr scan = (scan_ptr)d.scan4;
+
+    if (wave == 0) {
+        load_tile_pose(d, i, lane, s_pose);
+        // Neighbour keyframes: the n_nb smallest squared distances, ties to the smaller k.
+        const float tx = s_pose[0][lane], ty = s_pose[1][lane], tz = s_pose[2][lane];
+        float bd[kKfMaxNb];
+        int bk[kKfMaxNb];
+        for (int s = 0; s < kKfMaxNb; ++s) { bd[s] = INFINITY; bk[s] = K; }
+        for (int k = 0; k < K; ++k) {
+            const size_t r = (size_t)k * 7 * N + ic;
+            const float dd = dist2_rn(tx, ty, tz, d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]);
+            // Insert (dd, k) into the sorted list; k ascending keeps ties on the smaller k.
+            float cd = dd;
+            int ck = k;
+            for (int s = 0; s < kKfMaxNb; ++s) {
+                if (s < n_nb && cd < bd[s]) {
+                    const float td = bd[s];
+                    const int tk = bk[s];
+                    bd[s] = cd; bk[s] = ck;
+                    cd = td; ck = tk;
+                }
+            }
+        }
+        // Every slot below n_nb <= K is filled (distances are finite); guard anyway.
+        for (int s = 0; s < kKfMaxNb; ++s) s_nb[s][lane] = bk[s] < K ? bk[s] : 0;
+        if (i < N)
+            for (int s = 0; s < n_nb; ++s) d.neighbors[(size_t)s * N + i] = s_nb[s][lane];
+    }
+    const int chunk = (d.M + W - 1) / W;
+    const int j0 = min(d.M, wave * chunk);
+    const int j1 = min(d.M, j0 + chunk);
+    const int passes = d.iters + d.post_eval;
+    __syncthreads();
+
+    for (int pass = 0; pass < passes; ++pass) {
+        if (wave == 0) {
+            // Relative poses kT = T_k^-1 T in FP64: R' = R_k^T R, t' = R_k^T (t - t_k),
+            // as grid maps A' = R'/h and b' = (t' - o_k)/h - 1/2 = b_int + b_frac.
+            const float tf[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
+            const float qf[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
+            double t[3], q[4], R[9];
+            load_pose_d(tf, qf, t, q);
+            rot_of_quat_d(q[0], q[1], q[2], q[3], R);
+            const double ih = 1.0 / (double)d.h;
+            for (int s = 0; s < n_nb; ++s) {
+                const int k = s_nb[s][lane];
+                const size_t r = (size_t)k * 7 * N + ic;
+                const float ktf[3] = {d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]};
+                const float kqf[4] = {d.kf_pose[r + 3 * N], d.kf_pose[r + 4 * N], d.kf_pose[r + 5 * N],
+                                      d.kf_pose[r + 6 * N]};
+                double kt[3], kq[4], Rk[9];
+                load_pose_d(ktf, kqf, kt, kq);
+                rot_of_quat_d(kq[0], kq[1], kq[2], kq[3], Rk);
+                const double dt[3] = {t[0] - kt[0], t[1] - kt[1], t[2] - kt[2]};
+                for (int row = 0; row < 3; ++row) {
+                    for (int col = 0; col < 3; ++col)
+                        s_aff[s][3 * row + col][lane] =
+                            (float)((Rk[row] * R[col] + Rk[3 + row] * R[3 + col] + Rk[6 + row] * R[6 + col]) * ih);
+                    const double tr = Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2];
+                    const double bb = (tr - (double)d.origins[3 * k + row]) * ih - 0.5;
+                    const double fl = floor(bb);
+                    s_aff[s][9 + row][lane] = (float)(bb - fl);
+                    s_aff[s][12 + row][lane] = (float)fl;
+                }
+            }
+        }
+        __syncthreads();
+        double l = 0.0;
+        float g[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (int s = 0; s < n_nb; ++s) {
+            float A[9], bf[3], bi[3];
+            for (int e = 0; e < 9; ++e) A[e] = s_aff[s][e][lane];
+            for (int e = 0; e < 3; ++e) bf[e] = s_aff[s][9 + e][lane];
+            for (int e = 0; e < 3; ++e) bi[e] = s_aff[s][12 + e][lane];
+            const uint64_t gbase = base + (uint64_t)s_nb[s][lane] * grid_bytes;
+            Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            for (int j = j0; j < j1; ++j) {
+                const f4v sp = scan[j];
+                Pt p;
+                p.vx = fmaf(A[0], sp.x, fmaf(A[1], sp.y, A[2] * sp.z));
+                p.vy = fmaf(A[3], sp.x, fmaf(A[4], sp.y, A[5] * sp.z));
+                p.vz = fmaf(A[6], sp.x, fmaf(A[7], sp.y, A[8] * sp.z));
+                const float ux = (p.vx + bf[0]) + bi[0];
+                const float uy = (p.vy + bf[1]) + bi[1];
+                const float uz = (p.vz + bf[2]) + bi[2];
+                const bool inside = (ux >= 0.0f) & (ux < nxm) & (uy >= 0.0f) & (uy < nym) &
+                                    (uz >= 0.0f) & (uz < nzm);
+                const float sx = inside ? ux : 0.0f, sy = inside ? uy : 0.0f, sz = inside ? uz : 0.0f;
+                const int ix = cvt_floor(sx), iy = cvt_floor(sy), iz = cvt_floor(sz);
+                const float fx = __builtin_amdgcn_fractf(sx);
+                const float fy = __builtin_amdgcn_fractf(sy);
+                const float fz = __builtin_amdgcn_fractf(sz);
+                const uint64_t rec = (uint64_t)ix + (uint64_t)cxn * ((uint64_t)iy + (uint64_t)cyn * iz);
+                Cell<DT> c;
+                load_cell_g<DT>(gbase + (rec << record_shift<DT>()), c);
+                float G, gx, gy, gz;
+                trilinear<DT>(c, fx, fy, fz, G, gx, gy, gz);
+                const float m = inside ? 1.0f : 0.0f;
+                float dd = fmaf(G, m, d.eps);
+                if (SKIP) dd = inside ? dd : 1.0f;
+                acc.l += (double)fast_log2(dd);
+                add_grad(p, gx * m, gy * m, gz * m, fast_rcp(dd), acc);
+            }
+            l += acc.l;
+            // Body-frame gradient of this neighbour: R'^T A_n / h = A'^T A_n, R'^T B_n = h A'^T B_n.
+            const float h = d.h;
+            g[0] += A[0] * acc.ax + A[3] * acc.ay + A[6] * acc.az;
+            g[1] += A[1] * acc.ax + A[4] * acc.ay + A[7] * acc.az;
+            g[2] += A[2] * acc.ax + A[5] * acc.ay + A[8] * acc.az;
+            g[3] += h * (A[0] * acc.bx + A[3] * acc.by + A[6] * acc.bz);
+            g[4] += h * (A[1] * acc.bx + A[4] * acc.by + A[7] * acc.bz);
+            g[5] += h * (A[2] * acc.bx + A[5] * acc.by + A[8] * acc.bz);
+        }
+        s_l[wave][lane] = l;
+        for (int c = 0; c < 6; ++c) s_g[c][wave][lane] = g[c];
+        __syncthreads();
+        if (wave == 0) tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose);
+        __syncthreads();
+    }
+    if (wave == 0) store_tile_pose(d, i, lane, s_pose);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Scan packing, grid records, prediction
+// ---------------------------------------------------------------------------
+
+// Packs points [256 b, 256 b + 256) into float4.  A point with a non-finite
+// or huge coordinate becomes (1e30, 1e30, 1e30): outside every grid, with
+// finite products in the kernels, so it contributes as an outside point.
+__device__ __forceinline__ void pack_blk(const StepDesc &d, int b)
+{
+    const int j = b * kWeightBlock + threadIdx.x;
+    if (j >= d.M) return;
+    const float x = d.scan3[3 * j], y = d.scan3[3 * j + 1], z = d.scan3[3 * j + 2];
     const bool ok = fabsf(x) <= 1e30f && fabsf(y) <= 1e30f && fabsf(z) <= 1e30f;
-    s4[j] = ok ? make_float4(x, y, z, 0.0f) : make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+    const float4 v = ok ? make_float4(x, y, z, 0.0f) : make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+    d.scan4[j] = v;
+    d.scan8[j] = make_double4(v.x, v.y, v.z, 0.0);
+}
+
+// T_i <- T_i * dT * Exp(delta_i)  (Eq. 1), in FP64, rounded to FP32 once.
+__device__ __forceinline__ void predict_blk(const StepDesc &d, int b)
+{
+    const int i = b * kWeightBlock + threadIdx.x;
+    const int N = d.N;
+    if (i >= N) return;
+    float *pose = d.pose;
+    const float tf[3] = {pose[i], pose[N + i], pose[2 * N + i]};
+    const float qf[4] = {pose[3 * N + i], pose[4 * N + i], pose[5 * N + i], pose[6 * N + i]};
+    double t[3], q[4], R[9];
+    load_pose_d(tf, qf, t, q);
+    rot_of_quat_d(q[0], q[1], q[2], q[3], R);
+    const float *dv = d.dT;
+    t[0] += R[0] * dv[0] + R[1] * dv[1] + R[2] * dv[2];
+    t[1] += R[3] * dv[0] + R[4] * dv[1] + R[5] * dv[2];
+    t[2] += R[6] * dv[0] + R[7] * dv[1] + R[8] * dv[2];
+    double bw = dv[3], bx = dv[4], by = dv[5], bz = dv[6];
+    const double bn = 1.0 / sqrt(bw * bw + bx * bx + by * by + bz * bz);
+    bw *= bn; bx *= bn; by *= bn; bz *= bn;
+    double nq[4] = {q[0] * bw - q[1] * bx - q[2] * by - q[3] * bz,
+                    q[0] * bx + q[1] * bw + q[2] * bz - q[3] * by,
+                    q[0] * by - q[1] * bz + q[2] * bw + q[3] * bx,
+                    q[0] * bz + q[1] * by - q[2] * bx + q[3] * bw};
+    const double m = (nq[0] < 0.0 ? -1.0 : 1.0) /
+                     sqrt(nq[0] * nq[0] + nq[1] * nq[1] + nq[2] * nq[2] + nq[3] * nq[3]);
+    for (int a = 0; a < 4; ++a) nq[a] *= m;
+    if (d.noise) {
+        const float *nz = d.noise + 6 * (size_t)i;
+        const double rho[3] = {nz[0], nz[1], nz[2]};
+        const double phi[3] = {nz[3], nz[4], nz[5]};
+        right_exp_d(t, nq, rho, phi);
+    }
+    float to[3], qo[4];
+    store_pose_d(t, nq, to, qo);
+    pose[i] = to[0]; pose[N + i] = to[1]; pose[2 * N + i] = to[2];
+    pose[3 * N + i] = qo[0]; pose[4 * N + i] = qo[1]; pose[5 * N + i] = qo[2]; pose[6 * N + i] = qo[3];
 }
 
 __device__ __forceinline__ uint32_t pack_f16(float lo, float hi)
@@ -456,40 +952,6 @@ __global__ void k_build_cells(const float *__restrict__ grid, void *__restrict__
     }
 }
 
-struct Pose7 { float v[7]; };
-
-// T_i <- T_i * dT * Exp(delta_i)  (Eq. 1).
-__global__ void k_predict(float *__restrict__ pose, int N, Pose7 dT,
-                          const float *__restrict__ noise)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    float t[3] = {pose[i], pose[N + i], pose[2 * N + i]};
-    float q[4] = {pose[3 * N + i], pose[4 * N + i], pose[5 * N + i], pose[6 * N + i]};
-    normalize_quat(q[0], q[1], q[2], q[3]);
-    float R[9];
-    rot_of_quat(q[0], q[1], q[2], q[3], R);
-    const float *d = dT.v;
-    t[0] += R[0] * d[0] + R[1] * d[1] + R[2] * d[2];
-    t[1] += R[3] * d[0] + R[4] * d[1] + R[5] * d[2];
-    t[2] += R[6] * d[0] + R[7] * d[1] + R[8] * d[2];
-    float bw = d[3], bx = d[4], by = d[5], bz = d[6];
-    normalize_quat(bw, bx, by, bz);
-    float nw = q[0] * bw - q[1] * bx - q[2] * by - q[3] * bz;
-    float nx = q[0] * bx + q[1] * bw + q[2] * bz - q[3] * by;
-    float ny = q[0] * by - q[1] * bz + q[2] * bw + q[3] * bx;
-    float nz = q[0] * bz + q[1] * by - q[2] * bx + q[3] * bw;
-    normalize_quat(nw, nx, ny, nz);
-    q[0] = nw; q[1] = nx; q[2] = ny; q[3] = nz;
-    if (noise) {
-        const float rho[3] = {noise[6 * (size_t)i], noise[6 * (size_t)i + 1], noise[6 * (size_t)i + 2]};
-        const float phi[3] = {noise[6 * (size_t)i + 3], noise[6 * (size_t)i + 4], noise[6 * (size_t)i + 5]};
-        right_exp(t, q, rho, phi);
-    }
-    pose[i] = t[0]; pose[N + i] = t[1]; pose[2 * N + i] = t[2];
-    pose[3 * N + i] = q[0]; pose[4 * N + i] = q[1]; pose[5 * N + i] = q[2]; pose[6 * N + i] = q[3];
-}
-
 // ---------------------------------------------------------------------------
 // Weights: logw += beta l, log-sum-exp, ESS, representative, resample flag
 // ---------------------------------------------------------------------------
@@ -534,7 +996,8 @@ __device__ __forceinline__ void block_argmax(double &v, int &idx, double *shv, i
     __syncthreads();
 }
 
-__device__ __forceinline__ bool arrive_last(unsigned int *counter)
+// True in the block that arrives last among the n blocks counted on `counter`.
+__device__ __forceinline__ bool arrive_last(unsigned int *counter, int n)
 {
     __shared__ int s_last;
     __threadfence();
@@ -542,7 +1005,7 @@ __device__ __forceinline__ bool arrive_last(unsigned int *counter)
     if (threadIdx.x == 0) {
         const unsigned int t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
                                                       __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == gridDim.x - 1);
+        s_last = (t == (unsigned int)(n - 1));
     }
     __syncthreads();
     const bool last = s_last != 0;
@@ -550,18 +1013,19 @@ __device__ __forceinline__ bool arrive_last(unsigned int *counter)
     return last;
 }
 
-__global__ __launch_bounds__(kWeightBlock) void k_weights(WeightArgs a)
+__device__ __forceinline__ void weights_blk(const StepDesc &d, int b)
 {
     constexpr int B = kWeightBlock;
     __shared__ double sh[B];
     __shared__ int shi[B];
     const int tid = threadIdx.x;
-    const int i = blockIdx.x * B + tid;
-    const int N = a.N;
+    const int i = b * B + tid;
+    const int N = d.N;
+    const int nb = weight_blocks(N);
     double lw = -INFINITY;
     if (i < N) {
-        lw = a.logw[i] + a.beta * (double)a.loglik[i];
-        a.logw[i] = lw;
+        lw = d.logw[i] + d.beta * (double)d.loglik[i];
+        d.logw[i] = lw;
     }
     double m = lw;
     int am = i < N ? i : INT_MAX;
@@ -570,36 +1034,35 @@ __global__ __launch_bounds__(kWeightBlock) void k_weights(WeightArgs a)
     const double S = block_sum<B>(e, sh);
     const double Q = block_sum<B>(e * e, sh);
     if (tid == 0) {
-        double *p = a.part + 4 * (size_t)blockIdx.x;
+        double *p = d.part + 4 * (size_t)b;
         p[0] = m; p[1] = S; p[2] = Q; p[3] = (double)am;
     }
-    if (!arrive_last(a.counter)) return;
+    if (!arrive_last(d.counters, nb)) return;
 
-    // Last block: combine the per-block (max, sums) in block order.
-    const int nb = gridDim.x;
+    // Last block of the session: combine the per-block (max, sums) in block order.
     double gm = -INFINITY;
     int gam = INT_MAX;
     for (int bk = tid; bk < nb; bk += B) {
-        const double bm = a.part[4 * (size_t)bk];
-        const int bi = (int)a.part[4 * (size_t)bk + 3];
+        const double bm = d.part[4 * (size_t)bk];
+        const int bi = (int)d.part[4 * (size_t)bk + 3];
         if (bm > gm || (bm == gm && bi < gam)) { gm = bm; gam = bi; }
     }
     block_argmax<B>(gm, gam, sh, shi);
     double s = 0.0, q = 0.0;
     if (gm > -INFINITY) {
         for (int bk = tid; bk < nb; bk += B) {
-            const double bm = a.part[4 * (size_t)bk];
+            const double bm = d.part[4 * (size_t)bk];
             if (bm > -INFINITY) {
                 const double f = exp(bm - gm);
-                s += a.part[4 * (size_t)bk + 1] * f;
-                q += a.part[4 * (size_t)bk + 2] * f * f;
+                s += d.part[4 * (size_t)bk + 1] * f;
+                q += d.part[4 * (size_t)bk + 2] * f * f;
             }
         }
     }
     const double St = block_sum<B>(s, sh);
     const double Qt = block_sum<B>(q, sh);
     if (tid == 0) {
-        StepStatsDev *st = a.stats;
+        StepStatsDev *st = d.stats;
         const bool degenerate = !(gm > -INFINITY) || !(St > 0.0) || isnan(St);
         if (degenerate) {
             st->lse = NAN;
@@ -612,13 +1075,13 @@ __global__ __launch_bounds__(kWeightBlock) void k_weights(WeightArgs a)
             const double ess = St * St / Qt;
             st->lse = L;
             st->ess = ess;
-            st->resampled = (a.policy == 1) || (a.policy == 2 && ess < a.ess_frac * (double)N);
+            st->resampled = (d.policy == 1) || (d.policy == 2 && ess < d.ess_frac * (double)N);
             st->best = gam;
             st->degenerate = 0;
         }
-        const int b = degenerate ? 0 : gam;
-        for (int c = 0; c < 7; ++c) st->best_pose[c] = a.pose[(size_t)c * N + b];
-        __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int bb = degenerate ? 0 : gam;
+        for (int c = 0; c < 7; ++c) st->best_pose[c] = d.pose[(size_t)c * N + bb];
+        __hip_atomic_store(d.counters, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -629,21 +1092,22 @@ __global__ __launch_bounds__(kWeightBlock) void k_weights(WeightArgs a)
 // logw -= L (uniform reset when degenerate); when resampling, the block-local
 // inclusive scan of w = exp(logw) and, in the last block, the exclusive
 // prefix of the block totals.
-__global__ __launch_bounds__(kWeightBlock) void k_normalize_scan(ResampleArgs a)
+__device__ __forceinline__ void normscan_blk(const StepDesc &d, int b)
 {
     constexpr int B = kWeightBlock;
     __shared__ double sh[2][B];
     const int tid = threadIdx.x;
-    const int i = blockIdx.x * B + tid;
-    const int N = a.N;
-    const StepStatsDev *st = a.stats;
+    const int i = b * B + tid;
+    const int N = d.N;
+    const int nb = weight_blocks(N);
+    const StepStatsDev *st = d.stats;
     const int degenerate = st->degenerate;
     const int resampled = st->resampled;
     const double L = st->lse;
     double lw = -INFINITY;
     if (i < N) {
-        lw = degenerate ? -log((double)N) : a.logw[i] - L;
-        a.logw[i] = lw;
+        lw = degenerate ? -log((double)N) : d.logw[i] - L;
+        d.logw[i] = lw;
     }
     if (!resampled) return;
     double v = (i < N) ? exp(lw) : 0.0;
@@ -658,67 +1122,138 @@ __global__ __launch_bounds__(kWeightBlock) void k_normalize_scan(ResampleArgs a)
         __syncthreads();
     }
     v = sh[cur][tid];
-    if (i < N) a.cdf_local[i] = v;
-    if (tid == B - 1) a.part[blockIdx.x] = v;
-    if (!arrive_last(a.counter)) return;
-    if (tid == 0) {
-        double off = 0.0;
-        for (int bk = 0; bk < (int)gridDim.x; ++bk) {
-            const double tot = a.part[bk];
-            a.part[bk] = off;
-            off += tot;
-        }
-        __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (i < N) d.cdf_local[i] = v;
+    if (tid == B - 1) d.part[b] = v;
+    if (!arrive_last(d.counters + 1, nb)) return;
+    // Exclusive prefix of the block totals: thread t owns a contiguous chunk,
+    // chunk sums are scanned in LDS, then each chunk is written sequentially.
+    const int per = (nb + B - 1) / B;
+    const int c0 = min(nb, tid * per), c1 = min(nb, c0 + per);
+    double csum = 0.0;
+    for (int bk = c0; bk < c1; ++bk) csum += d.part[bk];
+    cur = 0;
+    sh[cur][tid] = csum;
+    __syncthreads();
+    for (int off = 1; off < B; off <<= 1) {
+        const double x = sh[cur][tid] + (tid >= off ? sh[cur][tid - off] : 0.0);
+        sh[cur ^ 1][tid] = (tid >= off) ? x : sh[cur][tid];
+        cur ^= 1;
+        __syncthreads();
     }
+    double off = tid > 0 ? sh[cur][tid - 1] : 0.0;   // exclusive prefix of this chunk
+    for (int bk = c0; bk < c1; ++bk) {
+        const double tot = d.part[bk];
+        d.part[bk] = off;
+        off += tot;
+    }
+    if (tid == 0) __hip_atomic_store(d.counters + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
 }
 
 // a_k = min{i : CDF_i > (u + k)/N} (N - 1 if none) by binary search on
 // CDF_i = offset[i / B] + local_i, then gather of the pose rows.
-__global__ void k_search_gather(ResampleArgs a)
+__device__ __forceinline__ void search_blk(const StepDesc &d, int b)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int N = a.N;
+    const int k = b * kWeightBlock + threadIdx.x;
+    const int N = d.N;
     if (k >= N) return;
-    if (!a.stats->resampled) {
-        a.parents[k] = k;
+    if (!d.stats->resampled) {
+        d.parents[k] = k;
         return;
     }
-    const double uk = (a.u + (double)k) / (double)N;
+    const double uk = (d.u + (double)k) / (double)N;
     int lo = 0, hi = N;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        const double c = a.part[mid / kWeightBlock] + a.cdf_local[mid];
+        const double c = d.part[mid / kWeightBlock] + d.cdf_local[mid];
         if (c > uk) hi = mid; else lo = mid + 1;
     }
     const int anc = lo < N ? lo : N - 1;
-    a.parents[k] = anc;
-    for (int c = 0; c < 7; ++c) a.pose_tmp[(size_t)c * N + k] = a.pose[(size_t)c * N + anc];
+    d.parents[k] = anc;
+    for (int c = 0; c < 7; ++c) d.pose_tmp[(size_t)c * N + k] = d.pose[(size_t)c * N + anc];
+    for (int r = 0; r < 7 * d.K; ++r) d.kf_pose_tmp[(size_t)r * N + k] = d.kf_pose[(size_t)r * N + anc];
 }
 
-// Keyframe poses of the ancestors: rows r of [K*7][N].
-__global__ void k_gather_rows(ResampleArgs a)
+__device__ __forceinline__ void commit_blk(const StepDesc &d, int b)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = blockIdx.y;
-    const int N = a.N;
-    if (k >= N || !a.stats->resampled) return;
-    const int anc = a.parents[k];
-    a.kf_pose_tmp[(size_t)r * N + k] = a.kf_pose[(size_t)r * N + anc];
+    const int k = b * kWeightBlock + threadIdx.x;
+    const int N = d.N;
+    if (k >= N || !d.stats->resampled) return;
+    for (int r = 0; r < 7; ++r) d.pose[(size_t)r * N + k] = d.pose_tmp[(size_t)r * N + k];
+    for (int r = 0; r < 7 * d.K; ++r) d.kf_pose[(size_t)r * N + k] = d.kf_pose_tmp[(size_t)r * N + k];
+    d.logw[k] = -log((double)N);
 }
 
-__global__ void k_commit(ResampleArgs a)
+// ---------------------------------------------------------------------------
+// Kernels: one session per launch (grid = that session's blocks)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kWeightBlock) void k_pack(StepDesc d) { pack_blk(d, blockIdx.x); }
+__global__ __launch_bounds__(kWeightBlock) void k_predict(StepDesc d) { predict_blk(d, blockIdx.x); }
+
+template <int DT, bool BIG, bool SKIP, int W, int U, bool TX64>
+__global__ __launch_bounds__(64 * W) void k_eval(StepDesc d)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = blockIdx.y;              // 0..6 pose rows, then keyframe rows
-    const int N = a.N;
-    if (k >= N || !a.stats->resampled) return;
-    if (r < 7) {
-        a.pose[(size_t)r * N + k] = a.pose_tmp[(size_t)r * N + k];
-        if (r == 0) a.logw[k] = -log((double)N);
-    } else {
-        const size_t o = (size_t)(r - 7) * N + k;
-        a.kf_pose[o] = a.kf_pose_tmp[o];
+    eval_tile<DT, BIG, SKIP, W, U, TX64>(d, blockIdx.x);
+}
+
+template <int DT, bool SKIP, int W>
+__global__ __launch_bounds__(64 * W) void k_kf_eval(StepDesc d)
+{
+    kf_tile<DT, SKIP, W>(d, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kWeightBlock) void k_weights(StepDesc d) { weights_blk(d, blockIdx.x); }
+__global__ __launch_bounds__(kWeightBlock) void k_normscan(StepDesc d) { normscan_blk(d, blockIdx.x); }
+__global__ __launch_bounds__(kWeightBlock) void k_search(StepDesc d) { search_blk(d, blockIdx.x); }
+__global__ __launch_bounds__(kWeightBlock) void k_commit(StepDesc d) { commit_blk(d, blockIdx.x); }
+
+// ---------------------------------------------------------------------------
+// Kernels: persistent, batched over many sessions
+// ---------------------------------------------------------------------------
+
+// Pull the next work item of `kind`; false when the list is exhausted.  The
+// item is uniform across the workgroup.
+__device__ __forceinline__ bool next_item(const BatchTables &t, int kind, int2 &w)
+{
+    __shared__ int s_item;
+    if (threadIdx.x == 0)
+        s_item = (int)__hip_atomic_fetch_add(t.heads + kind, 1u, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= t.counts[kind]) return false;
+    const int2 v = t.items[kind][it];
+    w.x = __builtin_amdgcn_readfirstlane(v.x);
+    w.y = __builtin_amdgcn_readfirstlane(v.y);
+    return true;
+}
+
+__global__ void kb_reset(unsigned int *heads)
+{
+    if (threadIdx.x < kNumKinds) heads[threadIdx.x] = 0u;
+}
+
+#define MCS_BATCH_LOOP(KIND, BODY)                 \
+    int2 w;                                        \
+    while (next_item(t, KIND, w)) {                \
+        const StepDesc &d = t.descs[w.x];          \
+        BODY;                                      \
+        __syncthreads();                           \
     }
+
+__global__ __launch_bounds__(kWeightBlock) void kb_pack(BatchTables t) { MCS_BATCH_LOOP(kPack, pack_blk(d, w.y)) }
+__global__ __launch_bounds__(kWeightBlock) void kb_predict(BatchTables t) { MCS_BATCH_LOOP(kPredict, predict_blk(d, w.y)) }
+__global__ __launch_bounds__(kWeightBlock) void kb_weights(BatchTables t) { MCS_BATCH_LOOP(kWeights, weights_blk(d, w.y)) }
+__global__ __launch_bounds__(kWeightBlock) void kb_normscan(BatchTables t) { MCS_BATCH_LOOP(kNormScan, normscan_blk(d, w.y)) }
+__global__ __launch_bounds__(kWeightBlock) void kb_search(BatchTables t) { MCS_BATCH_LOOP(kSearch, search_blk(d, w.y)) }
+__global__ __launch_bounds__(kWeightBlock) void kb_commit(BatchTables t) { MCS_BATCH_LOOP(kCommit, commit_blk(d, w.y)) }
+
+template <int DT, bool SKIP, int W, int U>
+__global__ __launch_bounds__(64 * W) void kb_eval(BatchTables t)
+{
+    MCS_BATCH_LOOP(kEval, (eval_tile<DT, false, SKIP, W, U, true>(d, w.y)))
 }
 
 }  // namespace
@@ -727,12 +1262,8 @@ __global__ void k_commit(ResampleArgs a)
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_pack_scan(const float *scan3, float4 *scan4, int M, hipStream_t st)
-{
-    if (M <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_scan, dim3((M + 255) / 256), dim3(256), 0, st, scan3, scan4, M);
-    return hipGetLastError();
-}
+constexpr int kEvalW = 4, kEvalU = 2;   // waves per workgroup, points per batch
+constexpr int kKfW = 4;
 
 hipError_t launch_build_cells(const float *grid, void *cells, int nx, int ny, int nz, int dtype,
                               hipStream_t st)
@@ -744,65 +1275,115 @@ hipError_t launch_build_cells(const float *grid, void *cells, int nx, int ny, in
     return hipGetLastError();
 }
 
-hipError_t launch_predict(float *pose, int N, const float dT[7], const float *noise, hipStream_t st)
+hipError_t launch_pack_predict(const StepDesc &d, hipStream_t st)
 {
-    Pose7 d;
-    for (int c = 0; c < 7; ++c) d.v[c] = dT[c];
-    hipLaunchKernelGGL(k_predict, dim3((N + 255) / 256), dim3(256), 0, st, pose, N, d, noise);
+    hipLaunchKernelGGL(k_pack, dim3(scan_blocks(d.M)), dim3(kWeightBlock), 0, st, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !d.predict) return e;
+    hipLaunchKernelGGL(k_predict, dim3(weight_blocks(d.N)), dim3(kWeightBlock), 0, st, d);
     return hipGetLastError();
 }
 
-template <int DT, bool BIG>
-static hipError_t launch_eval_dt(const EvalArgs &a, hipStream_t st)
+static bool big_slab(const StepDesc &d)
 {
-    constexpr int W = 4, U = 2;
-    const unsigned blocks = (unsigned)((a.N + 63) / 64);
-    hipLaunchKernelGGL((k_eval_step<DT, BIG, W, U>), dim3(blocks), dim3(64 * W), 0, st, a);
+    return (uint64_t)(d.nx - 1) >= (1u << 24) || (uint64_t)(d.nx - 1) * (d.ny - 1) >= (1u << 24);
+}
+
+bool eval_supported(const StepDesc &d)
+{
+    if (d.K > 0) return d.n_nb >= 1 && d.n_nb <= kKfMaxNb && d.n_nb <= d.K;
+    const uint64_t n_rec = (uint64_t)(d.nx - 1) * (d.ny - 1) * (d.nz - 1);
+    return (n_rec << (d.dtype == 0 ? 5 : 4)) <= (uint64_t)kOutside;
+}
+
+// MCSLAM_EVAL_TX32=1 selects the FP32 transform (split offset) instead of the
+// FP64 one, for comparison.
+static bool use_tx32()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("MCSLAM_EVAL_TX32");
+        v = (e && e[0] == '1') ? 1 : 0;
+    }
+    return v == 1;
+}
+
+template <int DT, bool SKIP>
+static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)particle_tiles(d.N);
+    const dim3 wg(64 * kEvalW);
+    if (d.K > 0) {
+        hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW>), dim3(blocks), dim3(64 * kKfW), 0, st, d);
+    } else if (big_slab(d)) {
+        hipLaunchKernelGGL((k_eval<DT, true, SKIP, kEvalW, kEvalU, true>), dim3(blocks), wg, 0, st, d);
+    } else if (use_tx32()) {
+        hipLaunchKernelGGL((k_eval<DT, false, SKIP, kEvalW, kEvalU, false>), dim3(blocks), wg, 0, st, d);
+    } else {
+        hipLaunchKernelGGL((k_eval<DT, false, SKIP, kEvalW, kEvalU, true>), dim3(blocks), wg, 0, st, d);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_eval_step(const EvalArgs &a, hipStream_t st)
+hipError_t launch_eval(const StepDesc &d, hipStream_t st)
 {
-    const uint64_t n_rec = (uint64_t)(a.grid.nx - 1) * (a.grid.ny - 1) * (a.grid.nz - 1);
-    if ((n_rec << (a.grid.dtype == 0 ? 5 : 4)) >= (1ull << 32)) return hipErrorInvalidValue;
-    const bool big = (uint64_t)(a.grid.nx - 1) >= (1u << 24) ||
-                     (uint64_t)(a.grid.nx - 1) * (a.grid.ny - 1) >= (1u << 24);
-    switch (a.grid.dtype * 2 + (big ? 1 : 0)) {
-    case 0: return launch_eval_dt<0, false>(a, st);
-    case 1: return launch_eval_dt<0, true>(a, st);
-    case 2: return launch_eval_dt<1, false>(a, st);
-    case 3: return launch_eval_dt<1, true>(a, st);
-    case 4: return launch_eval_dt<2, false>(a, st);
-    case 5: return launch_eval_dt<2, true>(a, st);
+    if (!eval_supported(d)) return hipErrorInvalidValue;
+    const bool skip = d.oob_skip != 0;
+    switch (d.dtype) {
+    case 0: return skip ? launch_eval_dt<0, true>(d, st) : launch_eval_dt<0, false>(d, st);
+    case 1: return skip ? launch_eval_dt<1, true>(d, st) : launch_eval_dt<1, false>(d, st);
+    case 2: return skip ? launch_eval_dt<2, true>(d, st) : launch_eval_dt<2, false>(d, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_kf_eval_step(const KfEvalArgs &, hipStream_t)
+hipError_t launch_weights(const StepDesc &d, hipStream_t st)
 {
-    return hipErrorNotSupported;
-}
-
-hipError_t launch_weights(const WeightArgs &a, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_weights, dim3(weight_blocks(a.N)), dim3(kWeightBlock), 0, st, a);
+    hipLaunchKernelGGL(k_weights, dim3(weight_blocks(d.N)), dim3(kWeightBlock), 0, st, d);
     return hipGetLastError();
 }
 
-hipError_t launch_resample(const ResampleArgs &a, hipStream_t st)
+hipError_t launch_resample(const StepDesc &d, hipStream_t st)
 {
-    const unsigned nb = (unsigned)weight_blocks(a.N);
-    hipLaunchKernelGGL(k_normalize_scan, dim3(nb), dim3(kWeightBlock), 0, st, a);
+    const unsigned nb = (unsigned)weight_blocks(d.N);
+    hipLaunchKernelGGL(k_normscan, dim3(nb), dim3(kWeightBlock), 0, st, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_search_gather, dim3(nb), dim3(kWeightBlock), 0, st, a);
+    hipLaunchKernelGGL(k_search, dim3(nb), dim3(kWeightBlock), 0, st, d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (a.K > 0) {
-        hipLaunchKernelGGL(k_gather_rows, dim3(nb, 7 * a.K), dim3(kWeightBlock), 0, st, a);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_commit, dim3(nb, 7 + 7 * a.K), dim3(kWeightBlock), 0, st, a);
+    hipLaunchKernelGGL(k_commit, dim3(nb), dim3(kWeightBlock), 0, st, d);
     return hipGetLastError();
+}
+
+// Persistent grid sizes: enough workgroups to fill 256 CUs several times.
+constexpr unsigned kBatchGridSmall = 2048;
+constexpr unsigned kBatchGridEval = 1280;
+
+template <int DT, bool SKIP>
+static hipError_t launch_batch_dt(const BatchTables &t, hipStream_t st)
+{
+    hipLaunchKernelGGL(kb_reset, dim3(1), dim3(64), 0, st, t.heads);
+    hipLaunchKernelGGL(kb_pack, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
+    hipLaunchKernelGGL(kb_predict, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
+    hipLaunchKernelGGL((kb_eval<DT, SKIP, kEvalW, kEvalU>), dim3(kBatchGridEval), dim3(64 * kEvalW), 0, st, t);
+    hipLaunchKernelGGL(kb_weights, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
+    hipLaunchKernelGGL(kb_normscan, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
+    hipLaunchKernelGGL(kb_search, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
+    hipLaunchKernelGGL(kb_commit, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchTables &t, int dtype, int skip, hipStream_t st)
+{
+    switch (dtype * 2 + (skip ? 1 : 0)) {
+    case 0: return launch_batch_dt<0, false>(t, st);
+    case 1: return launch_batch_dt<0, true>(t, st);
+    case 2: return launch_batch_dt<1, false>(t, st);
+    case 3: return launch_batch_dt<1, true>(t, st);
+    case 4: return launch_batch_dt<2, false>(t, st);
+    case 5: return launch_batch_dt<2, true>(t, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace mcs

@@ -1,8 +1,7 @@
 // C ABI of the MI355X gradient-guided Monte Carlo SLAM particle update: the
 // context, the map store, sessions, admission by HBM budget and the step
 // sequence enqueued on a session's stream.  Kernels live in kernels.hip.
-#include "../../include/mcslam.h"
-#include "internal.h"
+#include "state.h"
 
 #include <algorithm>
 #include <array>
@@ -18,8 +17,10 @@
 using namespace mcs;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace mcs {
 
 mcs_status fail(mcs_status code, const char *fmt, ...)
 {
@@ -37,59 +38,6 @@ mcs_status hip_fail(hipError_t e, const char *what)
     if (e == hipErrorOutOfMemory) return fail(MCS_ENOMEM, "%s: %s", what, hipGetErrorString(e));
     return fail(MCS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
-
-#define HIP_TRY(expr, what)                       \
-    do {                                          \
-        hipError_t e_ = (expr);                   \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-constexpr int kMaxNeighbors = 16;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-size_t record_bytes(int dtype) { return dtype == MCS_GRID_FP32 ? 32 : 16; }
-
-struct Map {
-    int id = 0;
-    int K = 0;                       // 0: single grid; >0: keyframe grids
-    mcs_grid_desc desc{};            // dims, res, dtype (origin of grid 0)
-    std::vector<float> origins;      // K x 3 (or 1 x 3)
-    void *cells = nullptr;
-    size_t bytes = 0;
-    int64_t records = 0;             // per grid
-    float *origins_dev = nullptr;
-    int users = 0;
-};
-
-struct Session {
-    int id = 0;
-    Map *map = nullptr;
-    int N = 0, M_max = 0, K = 0;
-    hipStream_t stream = nullptr;
-    void *block = nullptr;           // one device allocation holding every buffer
-    size_t bytes = 0;
-    float *pose = nullptr, *pose_tmp = nullptr, *loglik = nullptr, *grad = nullptr;
-    float *kf_pose = nullptr, *kf_pose_tmp = nullptr, *noise = nullptr, *scan3 = nullptr;
-    float4 *scan4 = nullptr;
-    double *logw = nullptr, *cdf_local = nullptr, *part = nullptr;
-    unsigned int *counters = nullptr;
-    int32_t *parents = nullptr, *neighbors = nullptr;
-    StepStatsDev *stats = nullptr;
-    float *pinned = nullptr;         // host staging for host-pointer steps
-    size_t pinned_floats = 0;
-    hipEvent_t staged = nullptr;     // last upload from `pinned` done
-    bool staged_pending = false;
-    // Stage timing: 5 events per profiled step (start, after predict, after
-    // eval, after weights, after resample).
-    bool profiling = false;
-    std::vector<std::array<hipEvent_t, 5>> prof_events;
-    size_t prof_used = 0;
-    int64_t prof_evals = 0;
-    double prof_ms[4] = {0, 0, 0, 0};
-    int64_t prof_steps = 0;
-};
 
 struct Layout {
     size_t off[20];
@@ -116,6 +64,7 @@ Layout session_layout(int N, int M_max, int K)
         n * 4,                      // 13 parents
         (K > 0 ? (size_t)kMaxNeighbors * n * 4 : 0),  // 14 neighbors
         sizeof(StepStatsDev),       // 15 stats
+        (size_t)M_max * 32,         // 16 scan8
     };
     Layout L{};
     size_t o = 0;
@@ -129,17 +78,8 @@ Layout session_layout(int N, int M_max, int K)
 
 }  // namespace
 
-struct mcs_ctx {
-    int device = 0;
-    uint64_t budget = 0;
-    uint64_t in_use = 0;
-    std::mutex mu;
-    std::map<int, Map *> maps;
-    std::map<int, Session *> sessions;
-    int next_id = 1;
-};
 
-namespace {
+namespace mcs {
 
 mcs_status set_device(mcs_ctx *ctx)
 {
@@ -245,7 +185,8 @@ mcs_status check_poses(const float *p, size_t n)
     for (size_t i = 0; i < n; ++i) {
         double qq = 0.0;
         for (int c = 0; c < 7; ++c) {
-            if (!std::isfinite(p[7 * i + c])) return fail(MCS_EINVAL, "pose %zu not finite", i);
+            if (!std::isfinite(p[7 * i + c]) || std::fabs(p[7 * i + c]) > 1e15f)
+                return fail(MCS_EINVAL, "pose %zu not finite or beyond 1e15", i);
             if (c >= 3) qq += (double)p[7 * i + c] * p[7 * i + c];
         }
         if (!(qq > 1e-20)) return fail(MCS_EINVAL, "pose %zu has a zero quaternion", i);
@@ -297,7 +238,46 @@ mcs_status validate_params(const Session *s, const mcs_step_params *p, int M)
     return MCS_OK;
 }
 
-// The step sequence on `st` with the scan already in s->scan3 (or scan_dev).
+// The device-side description of one step of session s.
+StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float *noise_dev,
+                   const mcs_step_params *p)
+{
+    const Map *m = s->map;
+    StepDesc d{};
+    d.cells = m->cells;
+    d.grid_stride = (int64_t)align_up((size_t)m->records * record_bytes(m->desc.dtype));
+    d.origins = m->origins_dev;
+    d.nx = m->desc.nx; d.ny = m->desc.ny; d.nz = m->desc.nz;
+    d.dtype = m->desc.dtype;
+    d.ox = m->desc.origin[0]; d.oy = m->desc.origin[1]; d.oz = m->desc.origin[2];
+    d.h = m->desc.res;
+    d.inv_h = 1.0f / m->desc.res;
+    d.K = s->K;
+    d.n_nb = s->K > 0 ? p->n_neighbors : 0;
+    d.pose = s->pose; d.pose_tmp = s->pose_tmp;
+    d.kf_pose = s->kf_pose; d.kf_pose_tmp = s->kf_pose_tmp;
+    d.loglik = s->loglik; d.grad = s->grad;
+    d.logw = s->logw; d.cdf_local = s->cdf_local; d.part = s->part;
+    d.counters = s->counters; d.parents = s->parents; d.neighbors = s->neighbors;
+    d.stats = s->stats;
+    d.N = s->N; d.M = M;
+    d.scan3 = scan3_dev; d.scan4 = s->scan4; d.scan8 = s->scan8;
+    d.noise = p->predict ? noise_dev : nullptr;
+    d.iters = p->iters;
+    d.post_eval = p->post_eval ? 1 : 0;
+    d.oob_skip = p->oob == MCS_OOB_SKIP;
+    d.predict = p->predict ? 1 : 0;
+    d.policy = p->resample;
+    d.alpha_t = p->alpha_t; d.alpha_r = p->alpha_r;
+    d.rho_max = p->rho_max; d.phi_max = p->phi_max;
+    d.eps = p->eps;
+    d.beta = (double)p->beta;
+    d.ess_frac = p->ess_frac;
+    d.u = p->u;
+    for (int c = 0; c < 7; ++c) d.dT[c] = p->delta_T[c];
+    return d;
+}
+
 // Events of the next profiled step (nullptr entries when not profiling).
 mcs_status prof_begin(Session *s, std::array<hipEvent_t, 5> *&ev)
 {
@@ -317,94 +297,26 @@ mcs_status prof_begin(Session *s, std::array<hipEvent_t, 5> *&ev)
         if (ev) HIP_TRY(hipEventRecord((*ev)[k], st), "hipEventRecord"); \
     } while (0)
 
+// The step sequence of one session on stream st.
 mcs_status enqueue_step(Session *s, const float *scan3_dev, int M, const float *noise_dev,
                         const mcs_step_params *p, hipStream_t st)
 {
+    const StepDesc d = make_desc(s, scan3_dev, M, noise_dev, p);
+    if (!eval_supported(d)) return fail(MCS_EINVAL, "map or neighbour count not supported");
     std::array<hipEvent_t, 5> *ev = nullptr;
     mcs_status ps = prof_begin(s, ev);
     if (ps != MCS_OK) return ps;
     if (ev) s->prof_evals += (int64_t)s->N * M * (p->iters + (p->post_eval ? 1 : 0)) *
                              (s->K > 0 ? p->n_neighbors : 1);
     PROF_MARK(0);
-    HIP_TRY(launch_pack_scan(scan3_dev, s->scan4, M, st), "pack scan");
-    if (p->predict) HIP_TRY(launch_predict(s->pose, s->N, p->delta_T, noise_dev, st), "predict");
+    HIP_TRY(launch_pack_predict(d, st), "pack/predict");
     PROF_MARK(1);
-    const Map *m = s->map;
-    if (s->K == 0) {
-        EvalArgs a{};
-        a.scan = s->scan4;
-        a.M = M;
-        a.grid.cells = m->cells;
-        a.grid.nx = m->desc.nx; a.grid.ny = m->desc.ny; a.grid.nz = m->desc.nz;
-        a.grid.dtype = m->desc.dtype;
-        a.grid.ox = m->desc.origin[0]; a.grid.oy = m->desc.origin[1]; a.grid.oz = m->desc.origin[2];
-        a.grid.inv_h = 1.0f / m->desc.res;
-        a.pose = s->pose;
-        a.loglik = s->loglik;
-        a.grad = s->grad;
-        a.N = s->N;
-        a.iters = p->iters;
-        a.post_eval = p->post_eval ? 1 : 0;
-        a.oob_skip = p->oob == MCS_OOB_SKIP;
-        a.alpha_t = p->alpha_t; a.alpha_r = p->alpha_r;
-        a.rho_max = p->rho_max; a.phi_max = p->phi_max;
-        a.eps = p->eps;
-        HIP_TRY(launch_eval_step(a, st), "eval_step");
-    } else {
-        KfEvalArgs a{};
-        a.scan = s->scan4;
-        a.M = M;
-        a.cells = m->cells;
-        a.grid_records = (int64_t)(align_up((size_t)m->records * record_bytes(m->desc.dtype)) /
-                                   record_bytes(m->desc.dtype));
-        a.origins = m->origins_dev;
-        a.nx = m->desc.nx; a.ny = m->desc.ny; a.nz = m->desc.nz; a.dtype = m->desc.dtype;
-        a.inv_h = 1.0f / m->desc.res;
-        a.K = s->K;
-        a.n_nb = p->n_neighbors;
-        a.pose = s->pose;
-        a.kf_pose = s->kf_pose;
-        a.loglik = s->loglik;
-        a.grad = s->grad;
-        a.neighbors = s->neighbors;
-        a.N = s->N;
-        a.iters = p->iters;
-        a.post_eval = p->post_eval ? 1 : 0;
-        a.oob_skip = p->oob == MCS_OOB_SKIP;
-        a.alpha_t = p->alpha_t; a.alpha_r = p->alpha_r;
-        a.rho_max = p->rho_max; a.phi_max = p->phi_max;
-        a.eps = p->eps;
-        HIP_TRY(launch_kf_eval_step(a, st), "kf_eval_step");
-    }
+    HIP_TRY(launch_eval(d, st), "eval");
+    if (s->K > 0) s->last_nb = p->n_neighbors;
     PROF_MARK(2);
-    WeightArgs w{};
-    w.logw = s->logw;
-    w.loglik = s->loglik;
-    w.N = s->N;
-    w.beta = (double)p->beta;
-    w.part = s->part;
-    w.counter = s->counters;
-    w.stats = s->stats;
-    w.policy = p->resample;
-    w.ess_frac = p->ess_frac;
-    w.pose = s->pose;
-    HIP_TRY(launch_weights(w, st), "weights");
+    HIP_TRY(launch_weights(d, st), "weights");
     PROF_MARK(3);
-    ResampleArgs r{};
-    r.logw = s->logw;
-    r.cdf_local = s->cdf_local;
-    r.part = s->part;
-    r.counter = s->counters + 1;
-    r.stats = s->stats;
-    r.N = s->N;
-    r.u = p->u;
-    r.parents = s->parents;
-    r.pose = s->pose;
-    r.pose_tmp = s->pose_tmp;
-    r.kf_pose = s->kf_pose;
-    r.kf_pose_tmp = s->kf_pose_tmp;
-    r.K = s->K;
-    HIP_TRY(launch_resample(r, st), "resample");
+    HIP_TRY(launch_resample(d, st), "resample");
     PROF_MARK(4);
     return MCS_OK;
 }
@@ -621,6 +533,7 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
     ss->parents = (int32_t *)(b + L.off[13]);
     ss->neighbors = (int32_t *)(b + L.off[14]);
     ss->stats = (StepStatsDev *)(b + L.off[15]);
+    ss->scan8 = (double4 *)(b + L.off[16]);
     e = hipMemsetAsync(ss->block, 0, L.total, ss->stream);
     if (e != hipSuccess) return undo(hip_fail(e, "hipMemset(session)"));
     // Initial state: poses, uniform log-weights, identity parents.
@@ -754,6 +667,27 @@ mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev,
     if ((st = set_device(ctx)) != MCS_OK) return st;
     hipStream_t hs = stream ? (hipStream_t)stream : s->stream;
     return enqueue_step(s, scan_dev, M, p->predict ? noise_dev : nullptr, p, hs);
+}
+
+mcs_status mcs_get_neighbors(mcs_ctx *ctx, int32_t sid, int32_t *out, int32_t *n_neighbors)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    if (s->K == 0) return fail(MCS_EINVAL, "session %d has no keyframe map", sid);
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (n_neighbors) *n_neighbors = s->last_nb;
+    if (out && s->last_nb > 0) {
+        const size_t N = s->N, nb = s->last_nb;
+        std::vector<int32_t> soa(nb * N);
+        HIP_TRY(hipMemcpy(soa.data(), s->neighbors, soa.size() * 4, hipMemcpyDeviceToHost),
+                "neighbors");
+        for (size_t i = 0; i < N; ++i)
+            for (size_t k = 0; k < nb; ++k) out[i * nb + k] = soa[k * N + i];
+    }
+    return MCS_OK;
 }
 
 mcs_status mcs_session_sync(mcs_ctx *ctx, int32_t sid)

@@ -325,3 +325,206 @@ def prediction_noise(N, frame, noise_sigma, seed):
     d[:, :3] = rng.normal(0.0, noise_sigma[0], (N, 3))
     d[:, 3:] = rng.normal(0.0, noise_sigma[1], (N, 3))
     return d
+
+
+# ---------------------------------------------------------------------------
+# keyframes: K local grids voxelised from keyframe scans, per-particle
+# keyframe poses
+# ---------------------------------------------------------------------------
+
+def keyframe_grid(points, grid_n, h, sigma, cutoff_sigmas=6.0):
+    """Local likelihood grid of one keyframe in its own frame.
+
+    G(c) = exp(-d_min^2 / 2 sigma^2), d_min the distance from voxel centre c to
+    the nearest keyframe point, and 0 beyond cutoff_sigmas * sigma.  The grid
+    is centred on the keyframe: origin = -grid_n h / 2 on every axis.
+    """
+    from scipy.spatial import cKDTree
+    half = 0.5 * grid_n * h
+    pts = np.asarray(points, np.float64)
+    pts = pts[np.all(np.abs(pts) < half + cutoff_sigmas * sigma, axis=1)]
+    G = np.zeros((grid_n, grid_n, grid_n), np.float32)
+    if pts.shape[0] == 0:
+        return G
+    rc = cutoff_sigmas * sigma
+    # Candidate voxels: those within rc of some point's voxel (dilation of the occupancy).
+    r = int(math.ceil(rc / h)) + 1
+    idx = np.floor((pts + half) / h).astype(np.int64)
+    occ = np.zeros((grid_n + 2 * r,) * 3, bool)
+    ii = np.clip(idx + r, 0, grid_n + 2 * r - 1)
+    occ[ii[:, 2], ii[:, 1], ii[:, 0]] = True
+    from scipy.ndimage import binary_dilation
+    cand = binary_dilation(occ, iterations=r)[r:r + grid_n, r:r + grid_n, r:r + grid_n]
+    kz, ky, kx = np.nonzero(cand)
+    centres = np.stack([kx, ky, kz], -1) * h - half + 0.5 * h
+    d, _ = cKDTree(pts).query(centres, distance_upper_bound=rc)
+    ok = np.isfinite(d)
+    with np.errstate(under="ignore"):
+        G[kz[ok], ky[ok], kx[ok]] = np.exp(-d[ok] ** 2 / (2.0 * sigma * sigma)).astype(np.float32)
+    return G
+
+
+def keyframes(N=50000, K=64, kf_points=16384, M_rings=32, n_az=64, grid_n=128, h=0.2,
+              sigma=0.1, n_nb=4, seed=1003, kf_drift=(0.05, 0.5), ambiguous=False,
+              grid_dtype=GRID_FP32, workers=8):
+    """Keyframe-map workload: K keyframes along a corridor trajectory.
+
+    Each keyframe scan (kf_points rays, 64 rings over [-15, 15] deg) is
+    voxelised into a local grid_n^3 grid at h in the keyframe frame.  The
+    current frame is the trajectory frame just after the last keyframe; its scan
+    has M_rings x n_az points.  Every particle carries its own pose per keyframe:
+    the true keyframe pose composed with N(0, drift) noise (metres, degrees).
+    With ambiguous=True the scene is a row of identical rooms (translated copies).
+    """
+    rng = np.random.default_rng(seed)
+    if ambiguous:
+        scene = repeated_rooms_scene(rng)
+        n_frames = 3 * K + 1
+        t_traj, q_traj = rooms_trajectory(scene, rng, n_frames)
+    else:
+        scene = corridor_scene(rng)
+        n_frames = 3 * K + 1
+        t_traj, q_traj = maze_trajectory(scene, rng, n_frames=n_frames)
+    kf_frames = np.arange(K) * 3
+    cur = n_frames - 1
+    n_kf_rings = 64
+    kf_az = max(1, kf_points // n_kf_rings)
+    els_kf = np.linspace(-15.0, 15.0, n_kf_rings)
+    from concurrent.futures import ThreadPoolExecutor
+
+    def kf_one(k):
+        f = kf_frames[k]
+        pts = lidar_scan(scene, t_traj[f], q_traj[f], els_kf, kf_az, 60.0, 0.02,
+                         np.random.default_rng([seed, 11, k]))
+        return keyframe_grid(pts, grid_n, h, sigma)
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        grids = np.stack(list(ex.map(kf_one, range(K))))
+    scan = lidar_scan(scene, t_traj[cur], q_traj[cur], np.linspace(-15.0, 15.0, M_rings), n_az,
+                      60.0, 0.02, np.random.default_rng([seed, 12]))
+    prng = np.random.default_rng(seed + 1)
+    poses = gaussian_particles(t_traj[cur], q_traj[cur], N, 0.5, 5.0, prng)
+    kf = np.empty((N, K, 7), np.float32)
+    for k in range(K):
+        f = kf_frames[k]
+        kf[:, k, :] = gaussian_particles(t_traj[f], q_traj[f], N, kf_drift[0], kf_drift[1], prng)
+    origin = -0.5 * grid_n * h
+    params = step_params(scan, h, sigma, iters=3)
+    params["n_neighbors"] = n_nb
+    return dict(
+        name="keyframes", grids=grids, dims=(grid_n,) * 3, origins=np.full((K, 3), origin),
+        h=h, sigma=sigma, grid_dtype=grid_dtype, scan=scan, poses=poses, kf_poses=kf,
+        logw=np.full(N, -math.log(N)), params=params, u=float(splitmix64_uniforms(seed + 2, 1)[0]),
+        t_traj=t_traj, q_traj=q_traj, kf_frames=kf_frames, cur=cur, scene=scene,
+    )
+
+
+def repeated_rooms_scene(rng, rooms=6, room=8.0, size_xy=102.4, size_z=25.6, floor_z=1.0,
+                         ceil_z=4.0, wall=0.3, door=1.6):
+    """A row of identical rooms (translated copies) joined by doors: an ambiguous map."""
+    lo, hi = [], []
+    hw = 0.5 * wall
+    y0, y1 = 40.0, 40.0 + room
+    x0 = 0.5 * (size_xy - rooms * room)
+    # Furniture of one room, copied into every room.
+    furn = []
+    for _ in range(5):
+        side = rng.uniform(0.5, 1.5, 3)
+        p = rng.uniform(1.5, room - 1.5, 2)
+        furn.append((p, side))
+    for r in range(rooms):
+        xa = x0 + r * room
+        # Long walls.
+        lo += [[xa - hw, y0 - hw, floor_z], [xa - hw, y1 - hw, floor_z]]
+        hi += [[xa + room + hw, y0 + hw, ceil_z], [xa + room + hw, y1 + hw, ceil_z]]
+        # Cross wall with a centred door (two slabs).
+        ym = 0.5 * (y0 + y1)
+        lo += [[xa - hw, y0 - hw, floor_z], [xa - hw, ym + 0.5 * door, floor_z]]
+        hi += [[xa + hw, ym - 0.5 * door, ceil_z], [xa + hw, y1 + hw, ceil_z]]
+        for p, side in furn:
+            lo.append([xa + p[0] - side[0] / 2, y0 + p[1] - side[1] / 2, floor_z])
+            hi.append([xa + p[0] + side[0] / 2, y0 + p[1] + side[1] / 2, floor_z + side[2]])
+    xe = x0 + rooms * room
+    lo.append([xe - hw, y0 - hw, floor_z])
+    hi.append([xe + hw, y1 + hw, ceil_z])
+    sc = Scene(lo, hi, [floor_z, ceil_z], [0.0, 0.0, 0.0], [size_xy, size_xy, size_z])
+    sc.rooms = dict(rooms=rooms, room=room, x0=x0, y0=y0, y1=y1)
+    return sc
+
+
+def rooms_trajectory(scene, rng, n_frames, z=2.5):
+    """Straight walk along the row of rooms through the doors, 0.5-1 m per frame."""
+    rm = scene.rooms
+    y = 0.5 * (rm["y0"] + rm["y1"])
+    x_start = rm["x0"] + 1.0
+    x_end = rm["x0"] + rm["rooms"] * rm["room"] - 1.0
+    steps = rng.uniform(0.5, 1.0, n_frames - 1)
+    x = x_start + np.concatenate([[0.0], np.cumsum(steps)])
+    # Walk back and forth along the row if the path is longer than the row.
+    span = x_end - x_start
+    ph = np.mod(x - x_start, 2 * span)
+    xx = x_start + np.where(ph < span, ph, 2 * span - ph)
+    yaw = np.where(ph < span, 0.0, np.pi)
+    t = np.stack([xx, np.full(n_frames, y), np.full(n_frames, z)], -1)
+    return t, geo.quat_yaw(yaw)
+
+
+# ---------------------------------------------------------------------------
+# serving: many concurrent sessions with their own maps
+# ---------------------------------------------------------------------------
+
+def serving_sessions(n_sessions=64, seed=1005, n_scans=8, n_lo=1000, n_hi=200000, m_lo=512,
+                     m_hi=4096, sizes=(128, 256, 512), nz=128, h=0.2, sigma=0.1):
+    """Per-session descriptions for the serving workload (maps are built lazily).
+
+    Session s: grid (nx, ny, nz) with nx, ny drawn from `sizes`, FP16 storage;
+    N = round(exp(U[ln n_lo, ln n_hi])); M = 64 * rings with rings ~ U{m_lo/64 .. m_hi/64};
+    n_scans distinct frames along a seeded maze trajectory, cycled.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n_sessions):
+        nx, ny = (int(v) for v in rng.choice(sizes, 2))
+        N = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        rings = int(rng.integers(m_lo // 64, m_hi // 64 + 1))
+        out.append(dict(session=s, dims=(nx, ny, nz), N=N, M=rings * 64, rings=rings,
+                        seed=seed * 100 + s, n_scans=n_scans, h=h, sigma=sigma))
+    return out
+
+
+def serving_session_inputs(desc):
+    """Map, scans, particles and step parameters of one serving session."""
+    nx, ny, nz = desc["dims"]
+    h, sigma = desc["h"], desc["sigma"]
+    rng = np.random.default_rng(desc["seed"])
+    cell = 5.0
+    cx, cy = max(2, int(nx * h // cell) - 1), max(2, int(ny * h // cell) - 1)
+    n_cells = min(cx, cy)
+    scene = corridor_scene(rng, cells=n_cells, cell=cell, size_xy=min(nx, ny) * h,
+                           size_z=nz * h, n_boxes=4 * n_cells)
+    scene.volume_hi = np.array([nx * h, ny * h, nz * h])
+    t_traj, q_traj = maze_trajectory(scene, rng, n_frames=desc["n_scans"] + 1)
+    els = np.linspace(-15.0, 15.0, desc["rings"])
+    scans = frame_scans(scene, t_traj[1:], q_traj[1:], els, 64, 60.0, 0.02, desc["seed"], workers=4)
+    grid = scene.likelihood_grid((nx, ny, nz), (0.0, 0.0, 0.0), h, sigma)
+    poses = gaussian_particles(t_traj[0], q_traj[0], desc["N"], 0.5, 5.0,
+                               np.random.default_rng(desc["seed"] + 1))
+    params = step_params(scans[0], h, sigma, iters=3)
+    params["ess_frac"] = 0.5
+    odo = np.zeros((desc["n_scans"], 7), np.float32)
+    for f in range(desc["n_scans"]):
+        dt, dq = relative_motion(t_traj[f], q_traj[f], t_traj[f + 1], q_traj[f + 1])
+        odo[f] = np.concatenate([dt, dq])
+    return dict(grid=grid, dims=(nx, ny, nz), origin=(0.0, 0.0, 0.0), h=h, scans=scans,
+                poses=poses, params=params, odometry=odo,
+                u=splitmix64_uniforms(desc["seed"] + 2, 4096))
+
+
+def poisson_arrivals(rate_hz, duration_s, rng):
+    """Arrival times of a Poisson process on [0, duration_s)."""
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= duration_s:
+            return np.array(out)
+        out.append(t)

@@ -78,6 +78,7 @@ def check_step(poses_in, grad_gpu, poses_gpu, params):
 def check_weights_resample(logw_in, loglik_gpu, beta, u, out, policy, ess_frac=0.5):
     """Weights and resampling, the oracle fed the GPU's likelihoods."""
     N = len(logw_in)
+    beta = float(np.float32(beta))       # the step parameters carry beta in FP32
     lw_ref, L, ess = oracle.weights(logw_in, loglik_gpu.astype(np.float64), beta)
     st = out["stats"]
     assert abs(st["lse"] - L) <= 1e-13 * max(1.0, abs(L)), (st["lse"], L)

@@ -60,9 +60,11 @@ def test_neighbours_are_nearest_by_translation_with_stable_ties():
     r = oracle.kf_evaluate(P["grids"], P["dims"], P["origins"], P["h"], 1e-3, P["scan"][:4],
                            P["poses"], P["kf"], n_nb=4)
     for i in range(40):
-        d = np.linalg.norm(P["kf"][i, :, :3].astype(np.float64) - P["poses"][i, :3].astype(np.float64),
-                           axis=1)
-        ref = np.argsort(d, kind="stable")[:4]
+        # FP32 squared distance, one rounding per operation (the kernel's precision).
+        dd = P["poses"][i, :3][None, :] - P["kf"][i, :, :3]
+        d2 = (dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]
+        assert d2.dtype == np.float32
+        ref = np.argsort(d2, kind="stable")[:4]
         assert list(r["neighbors"][i]) == list(ref)
 
 
