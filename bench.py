@@ -60,6 +60,177 @@ def run_cpu_baseline(c, frame, n_sample):
     return evals / dt, dt
 
 
+def _session_inputs(desc):
+    from synth import configs
+    x = configs.serving_session_inputs(desc)
+    x["grid"] = np.ascontiguousarray(x["grid"])
+    return desc, x
+
+
+def prepare_serving(args):
+    """Inputs of the serving sessions, built by worker processes before the GPU is touched."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    from synth import configs
+    descs = configs.serving_sessions(n_sessions=args.serving_sessions, n_scans=4)
+    t0 = time.perf_counter()
+    workers = max(1, min(8, cpu_cores() // 2))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        out = list(ex.map(_session_inputs, descs))
+    log("serving inputs: %d sessions built in %.1f s" % (len(out), time.perf_counter() - t0))
+    return out
+
+
+def run_serving(args, abi, torch, prepared):
+    """Many concurrent sessions with Poisson frame arrivals: batched server vs one at a time."""
+    from synth import configs
+    dev = torch.device("cuda:0")
+    ctx = abi.mcs_create(0)
+    sessions = []
+    t0 = time.perf_counter()
+    for desc, x in prepared:
+        mid = abi.mcs_init_map(ctx, abi.grid_desc(x["dims"], x["origin"], x["h"], abi.GRID_FP16),
+                               x["grid"])
+        N, M = desc["N"], desc["M"]
+        sid = abi.mcs_session_create(ctx, mid, x["poses"], M_max=M)
+        rng = np.random.default_rng(desc["seed"] + 9)
+        noise = (rng.normal(size=(x["scans"].shape[0], N, 6)) *
+                 [0.05, 0.05, 0.05, 0.017, 0.017, 0.017]).astype(np.float32)
+        sessions.append(dict(desc=desc, sid=sid, mid=mid, N=N, M=M, poses=x["poses"],
+                             params=x["params"], odo=x["odometry"], u=x["u"],
+                             scans=torch.from_numpy(x["scans"]).to(dev),
+                             noise=torch.from_numpy(noise).to(dev)))
+    torch.cuda.synchronize()
+    mem = abi.mcs_memory_in_use(ctx)
+    log("serving: %d sessions ready (%.1f s), %.2f GB resident, N mean %.0f, M mean %.0f" % (
+        len(sessions), time.perf_counter() - t0, mem / 1e9,
+        np.mean([s["N"] for s in sessions]), np.mean([s["M"] for s in sessions])))
+
+    rng = np.random.default_rng(4242)
+    arrivals = []
+    for k, s in enumerate(sessions):
+        for t in configs.poisson_arrivals(10.0 * args.serving_load, args.serving_seconds, rng):
+            arrivals.append((t, k))
+    arrivals.sort()
+    results = {}
+    for mode, name in ((abi.SERVE_BATCHED, "batched"), (abi.SERVE_SERIAL, "one_at_a_time")):
+        for s in sessions:
+            abi.mcs_set_particles(ctx, s["sid"], poses=s["poses"], logw=np.full(s["N"], -math.log(s["N"])))
+        torch.cuda.synchronize()
+        srv = abi.mcs_server_create(ctx, mode=mode, dtype=abi.GRID_FP16, max_batch=len(sessions))
+        counts = [0] * len(sessions)
+        ids = []
+        start = time.perf_counter()
+        for t, k in arrivals:
+            delay = start + t - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            s = sessions[k]
+            f = counts[k] % s["scans"].shape[0]
+            p = dict(s["params"], u=float(s["u"][counts[k] % len(s["u"])]), resample=abi.RESAMPLE_ESS,
+                     delta_T=s["odo"][f])
+            counts[k] += 1
+            ids.append(abi.mcs_server_submit(srv, s["sid"], s["scans"][f].data_ptr(), s["M"], p,
+                                             noise_dev_ptr=s["noise"][f].data_ptr()))
+        abi.mcs_server_drain(srv)
+        times = [abi.mcs_server_times(srv, r) for r in ids]
+        st = abi.mcs_server_stats_get(srv)
+        abi.mcs_server_destroy(srv)
+        lat = np.array([(t["done_ns"] - t["submit_ns"]) * 1e-6 for t in times])
+        span = (max(t["done_ns"] for t in times) - min(t["submit_ns"] for t in times)) * 1e-9
+        results[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                         "mean_ms": round(float(lat.mean()), 3),
+                         "frames": len(ids), "ticks": st["ticks"],
+                         "max_sessions_per_tick": st["max_batch_seen"],
+                         "evals_per_s": round(st["evals"] / span, 1)}
+        log("serving %s: %s" % (name, results[name]))
+    abi.mcs_destroy(ctx)
+    return {"sessions": len(sessions), "seconds": args.serving_seconds,
+            "arrival_hz_per_session": 10.0 * args.serving_load,
+            "resident_gb": round(mem / 1e9, 2), **results}
+
+
+def run_precision(abi):
+    """Errors of one box-room step (N = 1,024, M = 512) against the FP64 oracle, per grid dtype."""
+    import oracle
+    from synth import configs
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import quat_angle
+    c = configs.box_room()
+    N = c["poses"].shape[0]
+    beta = 0.002      # tempered so that resampling keeps many ancestors
+    out = {}
+    ctx = abi.mcs_create(0)
+    for dtype, name in ((abi.GRID_FP32, "fp32"), (abi.GRID_FP16, "fp16"), (abi.GRID_BF16, "bf16")):
+        g = {0: c["grid"], 1: oracle.quantize_fp16(c["grid"]), 2: oracle.quantize_bf16(c["grid"])}[dtype]
+        p = dict(c["params"], u=c["u"], beta=beta, resample=abi.RESAMPLE_ALWAYS)
+        mid = abi.mcs_init_map(ctx, abi.grid_desc(c["dims"], c["origin"], c["h"], dtype), c["grid"])
+        sid = abi.mcs_session_create(ctx, mid, c["poses"], M_max=512)
+        abi.mcs_filter_step(ctx, sid, c["scan"], p)
+        o = abi.mcs_get_particles(ctx, sid, N)
+        abi.mcs_session_destroy(ctx, sid)
+        abi.mcs_release_map(ctx, mid)
+        ref = oracle.evaluate(g, c["dims"], c["origin"], c["h"], p["eps"], c["scan"], c["poses"], delta=5e-4)
+        ref32 = oracle.evaluate(c["grid"], c["dims"], c["origin"], c["h"], p["eps"], c["scan"], c["poses"])
+        rel_l = np.abs(o["loglik"] - ref["loglik"]) / np.abs(ref["loglik"])
+        rel_g = np.max((np.abs(o["grad"] - ref["grad"]) - ref["amb_g"]) / ref["gabs"], axis=1)
+        stepped = oracle.step(c["poses"], ref["grad"], p["alpha_t"], p["alpha_r"], p["rho_max"], p["phi_max"])
+        anc = o["parents"]
+        dt = np.linalg.norm(o["poses"][:, :3] - stepped[anc, :3], axis=1)
+        da = quat_angle(o["poses"][:, 3:], stepped[anc, 3:])
+        lw, L, ess = oracle.weights(c["logw"], o["loglik"].astype(np.float64), float(np.float32(beta)))
+        a_ref, margin = oracle.resample(lw, p["u"])
+        mism = int(np.sum(a_ref != o["parents"]))
+        out[name] = {"loglik_rel_max": float("%.3g" % rel_l.max()),
+                     "grad_rel_max": float("%.3g" % max(0.0, rel_g.max())),
+                     "pose_err_m_max": float("%.3g" % dt.max()), "pose_err_rad_max": float("%.3g" % da.max()),
+                     "resample_mismatch": mism, "resample_near_ties": int(np.sum(margin < 1e-12)),
+                     "loglik_rel_vs_fp32_grid": float("%.3g" % (np.abs(o["loglik"] - ref32["loglik"]) /
+                                                               np.abs(ref32["loglik"])).max())}
+    abi.mcs_destroy(ctx)
+    return {"workload": "box_room N=1024 M=512, one step, beta=0.002", "by_grid_dtype": out,
+            "note": "grad_rel: max over particles and components of (|dg| - cell-face allowance) / "
+                    "sum_j |dl_j/dxi|; pose error: GPU step vs the oracle step from the oracle's gradient"}
+
+
+def run_keyframes(abi, steps=5):
+    """Keyframe-map step timing: K = 64 grids, N = 50,000, M = 2,048, 4 neighbours, 3 passes,
+    on a path that returns to its start, with the keyframes fixed and with the loop-gated
+    correction that propagates each step along the particle's keyframes."""
+    import torch
+    from synth import configs
+    c = configs.keyframes(N=50000, K=64, out_and_back=True)
+    K = c["grids"].shape[0]
+    ctx = abi.mcs_create(0)
+    descs = [abi.grid_desc(c["dims"], c["origins"][k], c["h"]) for k in range(K)]
+    mid = abi.mcs_load_keyframes(ctx, descs, [c["grids"][k] for k in range(K)])
+    N, M = c["poses"].shape[0], c["scan"].shape[0]
+    scan = torch.from_numpy(c["scan"]).to("cuda:0")
+    res = {"workload": "keyframes: K=64 local 128^3 grids, N=50000, M=2048, 4 neighbours, "
+                       "3 passes, out-and-back path (the current frame revisits the first keyframes)",
+           "note": "an evaluation is one (particle, point, neighbour) trilinear sample"}
+    for mode, name in ((abi.KF_FIXED, "fixed_keyframes"), (abi.KF_LOOP, "loop_update")):
+        sid = abi.mcs_session_create(ctx, mid, c["poses"], M_max=M, kf_poses=c["kf_poses"])
+        p = dict(c["params"], iters=3, u=c["u"], resample=abi.RESAMPLE_ESS, kf_update=mode)
+        abi.mcs_filter_step_dev(ctx, sid, scan.data_ptr(), M, p)
+        torch.cuda.synchronize()
+        abi.mcs_session_profile(ctx, sid, True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            abi.mcs_filter_step_dev(ctx, sid, scan.data_ptr(), M, p)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = abi.mcs_session_profile_read(ctx, sid)
+        abi.mcs_session_destroy(ctx, sid)
+        evals = N * M * 3 * p["n_neighbors"]
+        res[name] = {"ms_per_step": round(1e3 * wall / steps, 3),
+                     "eval_ms_per_step": round(prof["eval_ms"] / max(1, prof["steps"]), 3),
+                     "evals_per_s": round(evals * steps / wall, 1)}
+    abi.mcs_destroy(ctx)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,11 +240,31 @@ def main():
     ap.add_argument("--grid-dtype", type=int, default=0, help="0 FP32, 1 FP16, 2 BF16")
     ap.add_argument("--cpu-sample", type=int, default=100000,
                     help="particles in the one-frame oracle timing (0: skip)")
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
+                    help="length of the Poisson arrival schedule (0: skip serving)")
+    ap.add_argument("--serving-sessions", type=int, default=64)
+    ap.add_argument("--serving-load", type=float, default=1.0,
+                    help="multiplier on the 10 Hz per-session arrival rate")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="1: also report the precision table and the keyframe-map timing")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe_mb > 0:
+        import torch
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    prepared = prepare_serving(args) if args.serving_seconds > 0 else None
     import torch
 
     from paper_2504_18056_amd import abi
@@ -152,6 +343,18 @@ def main():
                "sample": "one corridors frame (prediction, 3 passes, weights, ESS resampling) "
                          "for %d particles x %d points; %.2f s wall" % (ns, M, dt)}
 
+    precision = keyframes = None
+    if args.extras:
+        log("precision table (box_room, fp32/fp16/bf16 grids)")
+        precision = run_precision(abi)
+        log("keyframe-map timing")
+        keyframes = run_keyframes(abi)
+        log("keyframes: %s" % keyframes)
+    serving = None
+    if args.serving_seconds > 0:
+        serving = run_serving(args, abi, torch, prepared)
+        del prepared
+
     dtype_name = {0: "fp32", 1: "fp32 (fp16 grid)", 2: "fp32 (bf16 grid)"}[args.grid_dtype]
     res = {
         "metric": METRIC,
@@ -173,6 +376,11 @@ def main():
         "stage_ms": stage_ms,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "ms_per_step_100k": round(1e3 * wall / args.steps, 4) if N == 100000 else None,
+        "p99_session_ms": serving["batched"]["p99_ms"] if serving else None,
+        "serving": serving,
+        "keyframes": keyframes,
+        "precision": precision,
     }
     print(json.dumps(res), flush=True)
 

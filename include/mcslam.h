@@ -90,6 +90,20 @@ typedef struct {
 #define MCS_OOB_FLOOR 0
 #define MCS_OOB_SKIP  1
 
+/* Keyframe maps: how a step corrects a particle's state (Sec. III-C.2).
+ * FIXED: every pass steps the current pose; keyframe poses never change.
+ * LOOP:  a particle whose neighbour keyframes include an old one (index below
+ *        K - n_recent; keyframes are numbered in time order) has detected a
+ *        loop; only such a particle is corrected: its current pose by the step
+ *        psi (Eq. 7) and each keyframe k from its oldest neighbour o to the
+ *        newest by psi_k = (d_k / d_t) psi, T_k <- T_k Exp(psi_k) (Eq. 8-10),
+ *        where d_k is the path length along the particle's keyframe
+ *        translations from o to k and d_t adds the segment from the newest
+ *        keyframe to the current translation before the step.  Keyframes older
+ *        than o do not move; when d_t = 0 none moves. */
+#define MCS_KF_FIXED 0
+#define MCS_KF_LOOP  1
+
 typedef struct {
     int32_t iters;          /* gradient passes per step, >= 1 */
     float alpha_t;          /* translation gain a_t (m per unit gradient) */
@@ -108,6 +122,10 @@ typedef struct {
     int32_t predict;        /* 1: apply Eq. 1 with delta_T (and noise) first */
     float delta_T[7];       /* odometry dT as a pose row */
     int32_t n_neighbors;    /* keyframe maps: neighbour keyframes per particle */
+    int32_t kf_update;      /* keyframe maps: MCS_KF_FIXED or MCS_KF_LOOP */
+    int32_t n_recent;       /* MCS_KF_LOOP: the newest n_recent keyframes are not old
+                               (with n_recent < n_neighbors every particle loops;
+                               n_recent = n_neighbors is the natural choice) */
 } mcs_step_params;
 
 typedef struct {

@@ -66,6 +66,9 @@ def lib():
                                      _fp, i32, i32, f64, _dp, _dp, _opt("d"), _opt("d"),
                                      _opt("d"), _opt("i"), _opt("i"), i32]
         L.oracle_kf_eval.restype = i32
+        L.oracle_kf_loop_update.argtypes = [_fp, _fp, _dp, _ip, i32, i32, i32, i32, f64, f64, f64,
+                                            f64, _dp, _dp, _ip, _opt("d")]
+        L.oracle_kf_loop_update.restype = i32
         L.oracle_filter_step.argtypes = [_fp, i32, i32, i32, _dp, f64, _fp, i32, _fp, _dp, i32,
                                          i32, f64, f64, f64, f64, f64, f64, i32, i32, i32, f64,
                                          f64, _opt("d"), _opt("f"), _dp, _dp, _dp, _dp, _ip, _dp,
@@ -222,6 +225,27 @@ def kf_evaluate(grids, dims, origins, h, eps, scan, poses, kf_poses, n_nb=4, oob
                                 float(delta), ll, gr, ga, al, ag, na, nb, int(nthreads)),
            "oracle_kf_eval")
     return dict(loglik=ll, grad=gr, gabs=ga, amb_l=al, amb_g=ag, n_amb=na, neighbors=nb)
+
+
+def kf_loop_update(poses, kf_poses, grad, neighbors, params, n_recent=3):
+    """Loop-gated correction of the current pose and the keyframe poses of each
+    particle (Sec. III-C.2, Eq. 5-10, with the gradient step in place of the
+    Gauss-Newton solve).  Returns poses (N, 7), kf_poses (N, K, 7), loop (N: the
+    oldest neighbour when a loop is detected, else -1) and psi (N, 6)."""
+    poses = _f32(poses).reshape(-1, 7)
+    N = poses.shape[0]
+    kf = _f32(kf_poses).reshape(N, -1, 7)
+    K = kf.shape[1]
+    nb = np.ascontiguousarray(neighbors, dtype=np.int32).reshape(N, -1)
+    n_nb = nb.shape[1]
+    out_p, out_k = np.empty((N, 7)), np.empty((N, K, 7))
+    loop, psi = np.empty(N, np.int32), np.empty((N, 6))
+    p = params
+    _check(lib().oracle_kf_loop_update(poses, kf, _f64(grad).reshape(-1), nb, N, K, n_nb,
+                                       int(n_recent), p["alpha_t"], p["alpha_r"], p["rho_max"],
+                                       p["phi_max"], out_p, out_k, loop, psi),
+           "oracle_kf_loop_update")
+    return dict(poses=out_p, kf_poses=out_k, loop=loop, psi=psi)
 
 
 POLICY_NEVER, POLICY_ALWAYS, POLICY_ESS = 0, 1, 2

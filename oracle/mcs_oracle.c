@@ -473,15 +473,21 @@ static void eval_pose(const grid_t *g, double eps, int oob_skip, const float *sc
 
 /* Gradient-guided step: psi = [a_t g_rho; a_r g_phi], each block scaled down
  * to its norm bound when longer, then T <- T Exp(psi) (Eq. 7). */
-static void step_pose(const double pose[7], const double g[6], double a_t, double a_r,
-                      double rho_max, double phi_max, double out[7])
+static void step_vector(const double g[6], double a_t, double a_r, double rho_max,
+                        double phi_max, double psi[6])
 {
-    double psi[6];
     for (int c = 0; c < 3; ++c) { psi[c] = a_t * g[c]; psi[3 + c] = a_r * g[3 + c]; }
     double nr = sqrt(psi[0] * psi[0] + psi[1] * psi[1] + psi[2] * psi[2]);
     double np = sqrt(psi[3] * psi[3] + psi[4] * psi[4] + psi[5] * psi[5]);
     if (nr > rho_max) for (int c = 0; c < 3; ++c) psi[c] *= rho_max / nr;
     if (np > phi_max) for (int c = 3; c < 6; ++c) psi[c] *= phi_max / np;
+}
+
+static void step_pose(const double pose[7], const double g[6], double a_t, double a_r,
+                      double rho_max, double phi_max, double out[7])
+{
+    double psi[6];
+    step_vector(g, a_t, a_r, rho_max, phi_max, psi);
     pose_right_exp(pose, psi, out);
 }
 
@@ -724,6 +730,78 @@ int oracle_kf_eval(const float *grids, int K, int nx, int ny, int nz, const doub
         if (n_amb) n_amb[i] = o.n_amb;
         if (nbp != nb) free(nbp);
     }
+    return 0;
+}
+
+/* Loop-gated state update of the keyframe filter (Sec. III-C.2).
+ *
+ * A particle detects a loop when one of its neighbour keyframes is old: its
+ * index (keyframes are numbered in time order) lies below K - n_recent.  Only
+ * then is its state corrected: the current pose by the step psi of its
+ * gradient, T <- T Exp(psi) (Eq. 5-7 with the gradient step in place of the
+ * Gauss-Newton solve), and every keyframe k from the oldest neighbour o up to
+ * the newest by the discounted step psi_k = (d_k / d_t) psi,
+ * T_k <- T_k Exp(psi_k) (Eq. 8 and 10).  The path lengths (Eq. 9) run along the
+ * particle's own trajectory sampled at its keyframe poses:
+ * d_k = sum_{m=o}^{k-1} |t_{m+1} - t_m| and d_t = d_{K-1} + |t - t_{K-1}|
+ * with t the particle's current translation before the update.  Keyframes
+ * older than o, and every pose of a particle without a loop, are unchanged.
+ * When d_t = 0 no keyframe moves.
+ * Inputs: poses (N, 7), kf_poses (N, K, 7), grad (N, 6), neighbors (N, n_nb).
+ * Outputs: poses_out (N, 7), kf_out (N, K, 7), loop (N; the oldest neighbour o
+ * when a loop is detected, else -1), psi (N, 6; may be NULL). */
+int oracle_kf_loop_update(const float *poses, const float *kf_poses, const double *grad,
+                          const int *neighbors, int N, int K, int n_nb, int n_recent,
+                          double a_t, double a_r, double rho_max, double phi_max,
+                          double *poses_out, double *kf_out, int *loop, double *psi_out)
+{
+    if (N < 0 || K <= 0 || n_nb <= 0 || n_nb > K) return -1;
+    double *d = (double *)malloc(sizeof(double) * (size_t)K);
+    if (!d) return -2;
+    for (int i = 0; i < N; ++i) {
+        const float *kf = kf_poses + (size_t)7 * K * i;
+        double *ko = kf_out + (size_t)7 * K * i;
+        double pose[7], psi[6];
+        pose_from_float(poses + 7 * (size_t)i, pose);
+        for (int k = 0; k < K; ++k) pose_from_float(kf + 7 * (size_t)k, ko + 7 * (size_t)k);
+        step_vector(grad + 6 * (size_t)i, a_t, a_r, rho_max, phi_max, psi);
+        if (psi_out) memcpy(psi_out + 6 * (size_t)i, psi, sizeof psi);
+        int o = K;
+        for (int s = 0; s < n_nb; ++s) {
+            int k = neighbors[(size_t)n_nb * i + s];
+            if (k < o) o = k;
+        }
+        if (o >= K - n_recent) {
+            loop[i] = -1;
+            memcpy(poses_out + 7 * (size_t)i, pose, sizeof pose);
+            continue;
+        }
+        loop[i] = o;
+        pose_right_exp(pose, psi, poses_out + 7 * (size_t)i);
+        d[o] = 0.0;
+        for (int k = o + 1; k < K; ++k) {
+            double s2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double e = (double)kf[7 * (size_t)k + a] - (double)kf[7 * (size_t)(k - 1) + a];
+                s2 += e * e;
+            }
+            d[k] = d[k - 1] + sqrt(s2);
+        }
+        double s2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double e = pose[a] - (double)kf[7 * (size_t)(K - 1) + a];
+            s2 += e * e;
+        }
+        double dt = d[K - 1] + sqrt(s2);
+        if (!(dt > 0.0)) continue;
+        for (int k = o; k < K; ++k) {
+            double pk[6], prev[7];
+            for (int c = 0; c < 6; ++c) pk[c] = (d[k] / dt) * psi[c];
+            memcpy(prev, ko + 7 * (size_t)k, sizeof prev);
+            pose_right_exp(prev, pk, ko + 7 * (size_t)k);
+        }
+    }
+    free(d);
     return 0;
 }
 

@@ -18,6 +18,7 @@ MCS_OK, MCS_EINVAL, MCS_ENOMEM, MCS_EBUDGET, MCS_ENOTFOUND, MCS_EDEVICE, MCS_EBU
 GRID_FP32, GRID_FP16, GRID_BF16 = 0, 1, 2
 RESAMPLE_NEVER, RESAMPLE_ALWAYS, RESAMPLE_ESS = 0, 1, 2
 OOB_FLOOR, OOB_SKIP = 0, 1
+KF_FIXED, KF_LOOP = 0, 1
 
 _STATUS_NAMES = {0: "MCS_OK", -1: "MCS_EINVAL", -2: "MCS_ENOMEM", -3: "MCS_EBUDGET",
                  -4: "MCS_ENOTFOUND", -5: "MCS_EDEVICE", -6: "MCS_EBUSY"}
@@ -39,7 +40,8 @@ class StepParams(C.Structure):
                 ("rho_max", C.c_float), ("phi_max", C.c_float), ("eps", C.c_float),
                 ("beta", C.c_float), ("oob", C.c_int32), ("post_eval", C.c_int32),
                 ("resample", C.c_int32), ("ess_frac", C.c_double), ("u", C.c_double),
-                ("predict", C.c_int32), ("delta_T", C.c_float * 7), ("n_neighbors", C.c_int32)]
+                ("predict", C.c_int32), ("delta_T", C.c_float * 7), ("n_neighbors", C.c_int32),
+                ("kf_update", C.c_int32), ("n_recent", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -52,6 +54,18 @@ class Profile(C.Structure):
     _fields_ = [("predict_ms", C.c_double), ("eval_ms", C.c_double), ("weights_ms", C.c_double),
                 ("resample_ms", C.c_double), ("steps", C.c_int64), ("evals", C.c_int64)]
 
+
+class RequestTimes(C.Structure):
+    _fields_ = [("submit_ns", C.c_int64), ("launch_ns", C.c_int64), ("done_ns", C.c_int64),
+                ("session_id", C.c_int32), ("tick", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("requests", C.c_int64), ("ticks", C.c_int64), ("evals", C.c_int64),
+                ("max_batch_seen", C.c_int32), ("pad", C.c_int32)]
+
+
+SERVE_BATCHED, SERVE_SERIAL = 0, 1
 
 _lib = None
 
@@ -88,6 +102,12 @@ def lib():
             "mcs_session_sync": (i32, [vp, i32]),
             "mcs_session_stream": (i32, [vp, i32, P(vp)]),
             "mcs_get_neighbors": (i32, [vp, i32, vp, P(i32)]),
+            "mcs_server_create": (i32, [vp, i32, i32, i32, i32, i32, P(vp)]),
+            "mcs_server_destroy": (i32, [vp]),
+            "mcs_server_submit": (i32, [vp, i32, vp, i32, vp, P(StepParams), P(C.c_int64)]),
+            "mcs_server_drain": (i32, [vp]),
+            "mcs_server_times": (i32, [vp, C.c_int64, P(RequestTimes)]),
+            "mcs_server_stats_get": (i32, [vp, P(ServerStats)]),
             "mcs_session_profile": (i32, [vp, i32, i32]),
             "mcs_session_profile_read": (i32, [vp, i32, P(Profile)]),
         }
@@ -220,6 +240,8 @@ def step_params(d):
     for c in range(7):
         p.delta_T[c] = float(dT[c])
     p.n_neighbors = int(d.get("n_neighbors", 4))
+    p.kf_update = int(d.get("kf_update", KF_FIXED))
+    p.n_recent = int(d.get("n_recent", p.n_neighbors))
     return p
 
 
@@ -285,3 +307,44 @@ def mcs_get_neighbors(ctx, sid, N, n_nb):
     if k.value != n_nb:
         raise McsError(MCS_EINVAL, "session used %d neighbours, asked for %d" % (k.value, n_nb))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+
+def mcs_server_create(ctx, mode=SERVE_BATCHED, dtype=GRID_FP16, oob=OOB_FLOOR, max_batch=64,
+                      max_items=0):
+    s = C.c_void_p()
+    _check(lib().mcs_server_create(ctx, int(mode), int(dtype), int(oob), int(max_batch),
+                                   int(max_items), C.byref(s)))
+    return s
+
+
+def mcs_server_destroy(srv):
+    _check(lib().mcs_server_destroy(srv))
+
+
+def mcs_server_submit(srv, sid, scan_dev_ptr, M, params, noise_dev_ptr=None):
+    p = params if isinstance(params, StepParams) else step_params(params)
+    rid = C.c_int64()
+    _check(lib().mcs_server_submit(srv, int(sid), C.c_void_p(int(scan_dev_ptr)), int(M),
+                                   None if noise_dev_ptr is None else C.c_void_p(int(noise_dev_ptr)),
+                                   C.byref(p), C.byref(rid)))
+    return rid.value
+
+
+def mcs_server_drain(srv):
+    _check(lib().mcs_server_drain(srv))
+
+
+def mcs_server_times(srv, rid):
+    t = RequestTimes()
+    _check(lib().mcs_server_times(srv, C.c_int64(int(rid)), C.byref(t)))
+    return {f: getattr(t, f) for f, _ in RequestTimes._fields_}
+
+
+def mcs_server_stats_get(srv):
+    s = ServerStats()
+    _check(lib().mcs_server_stats_get(srv, C.byref(s)))
+    return {f: getattr(s, f) for f, _ in ServerStats._fields_ if f != "pad"}

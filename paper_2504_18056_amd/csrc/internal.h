@@ -57,6 +57,8 @@ struct StepDesc {
     float alpha_t, alpha_r, rho_max, phi_max, eps;
     double beta, ess_frac, u;
     float dT[7];
+    int32_t kf_loop;         // keyframe maps: loop-gated correction with propagation
+    int32_t n_recent;        // with kf_loop: neighbours with index >= K - n_recent are recent
     int32_t pad;
 };
 

@@ -212,11 +212,12 @@ __device__ __forceinline__ void store_pose_d(const double td[3], const double qd
 // of psi = [a_t g_rho; a_r g_phi] is scaled down to its bound, then
 // T <- T Exp(psi).  FP32: the increment is at most a decimetre, so t + dt is
 // rounded once at t's own precision.
-__device__ __forceinline__ void take_step(float t[3], float q[4], const float g[6], float alpha_t,
-                                          float alpha_r, float rho_max, float phi_max)
+// psi = [a_t g_rho; a_r g_phi], each block scaled down to its norm bound.
+__device__ __forceinline__ void step_vector(const float g[6], float alpha_t, float alpha_r,
+                                            float rho_max, float phi_max, float rho[3], float phi[3])
 {
-    float rho[3] = {alpha_t * g[0], alpha_t * g[1], alpha_t * g[2]};
-    float phi[3] = {alpha_r * g[3], alpha_r * g[4], alpha_r * g[5]};
+    rho[0] = alpha_t * g[0]; rho[1] = alpha_t * g[1]; rho[2] = alpha_t * g[2];
+    phi[0] = alpha_r * g[3]; phi[1] = alpha_r * g[4]; phi[2] = alpha_r * g[5];
     const float nr = sqrtf(rho[0] * rho[0] + rho[1] * rho[1] + rho[2] * rho[2]);
     const float np = sqrtf(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
     if (nr > rho_max) {
@@ -227,6 +228,13 @@ __device__ __forceinline__ void take_step(float t[3], float q[4], const float g[
         const float k = phi_max / np;
         phi[0] *= k; phi[1] *= k; phi[2] *= k;
     }
+}
+
+__device__ __forceinline__ void take_step(float t[3], float q[4], const float g[6], float alpha_t,
+                                          float alpha_r, float rho_max, float phi_max)
+{
+    float rho[3], phi[3];
+    step_vector(g, alpha_t, alpha_r, rho_max, phi_max, rho, phi);
     right_exp(t, q, rho, phi);
 }
 
@@ -366,19 +374,36 @@ __device__ __forceinline__ void trilinear(const Cell<DT> &cell, float fx, float 
 {
     float c[8];
     decode<DT>(cell, c);
-    // Along x on the four y/z edges.
+    // Corner records: lerps along x on the four y/z edges, then y, then z.
     const float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
     const float e00 = fmaf(fx, d00, c[0]), e10 = fmaf(fx, d10, c[2]);
     const float e01 = fmaf(fx, d01, c[4]), e11 = fmaf(fx, d11, c[6]);
-    // Along y.
     const float gy0 = e10 - e00, gy1 = e11 - e01;
     const float f0 = fmaf(fy, gy0, e00), f1 = fmaf(fy, gy1, e01);
-    // Along z.
     gz = f1 - f0;
     G = fmaf(fz, gz, f0);
     gy = fmaf(fz, gy1 - gy0, gy0);
     const float dx0 = fmaf(fy, d10 - d00, d00), dx1 = fmaf(fy, d11 - d01, d01);
     gx = fmaf(fz, dx1 - dx0, dx0);
+}
+
+// FP32 grids store each cell as the coefficients of its trilinear polynomial
+//   G(x, y, z) = a0 + a1 x + a2 y + a3 z + a4 xy + a5 xz + a6 yz + a7 xyz
+// (x, y, z the fractions in the cell), so value and gradient take 11 FMAs.
+template <>
+__device__ __forceinline__ void trilinear<0>(const Cell<0> &cell, float fx, float fy, float fz,
+                                             float &G, float &gx, float &gy, float &gz)
+{
+    const float a0 = cell.a.x, a1 = cell.a.y, a2 = cell.a.z, a3 = cell.a.w;
+    const float a4 = cell.b.x, a5 = cell.b.y, a6 = cell.b.z, a7 = cell.b.w;
+    const float p = fmaf(a6, fy, a3);      // dG/dz at x = 0
+    const float q = fmaf(a7, fy, a5);      // d2G/dxdz
+    const float r = fmaf(a4, fy, a1);      // dG/dx at z = 0
+    const float s = fmaf(a2, fy, a0);      // G at x = z = 0
+    gz = fmaf(q, fx, p);
+    gx = fmaf(q, fz, r);
+    G = fmaf(gz, fz, fmaf(r, fx, s));
+    gy = fmaf(fmaf(a7, fx, a6), fz, fmaf(a4, fx, a2));
 }
 
 // Gradient sums of one point given 1/(G + eps).
@@ -578,10 +603,14 @@ __device__ __forceinline__ void load_tile_pose(const StepDesc &d, int i, int lan
 }
 
 // Reduce the W partial sums (fixed order), store l and g, take the step.
+// With s_upd (keyframe maps, loop-gated correction) only lanes with s_loop >= 0
+// step, and each of them leaves psi (rows 0-5) and its translation before the
+// step (rows 6-8) in s_upd for the keyframe propagation.
 template <int W>
 __device__ __forceinline__ void tile_epilogue(const StepDesc &d, int i, int lane, int pass,
                                               const double (*s_l)[64], const float (*s_g)[W][64],
-                                              float (*s_pose)[64])
+                                              float (*s_pose)[64], const int *s_loop = nullptr,
+                                              float (*s_upd)[64] = nullptr)
 {
     double l = 0.0;
     float s[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
@@ -604,8 +633,21 @@ __device__ __forceinline__ void tile_epilogue(const StepDesc &d, int i, int lane
         if (stepping)
             for (int c = 0; c < 6; ++c) d.grad[c * N + i] = gr[c];
     }
-    if (stepping) {
+    if (stepping && s_upd) {
+        if (s_loop[lane] >= 0) {
+            float rho[3], phi[3];
+            step_vector(gr, d.alpha_t, d.alpha_r, d.rho_max, d.phi_max, rho, phi);
+            for (int c = 0; c < 3; ++c) {
+                s_upd[c][lane] = rho[c];
+                s_upd[3 + c][lane] = phi[c];
+                s_upd[6 + c][lane] = t[c];
+            }
+            right_exp(t, q, rho, phi);
+        }
+    } else if (stepping) {
         take_step(t, q, gr, d.alpha_t, d.alpha_r, d.rho_max, d.phi_max);
+    }
+    if (stepping) {
         s_pose[0][lane] = t[0]; s_pose[1][lane] = t[1]; s_pose[2][lane] = t[2];
         s_pose[3][lane] = q[0]; s_pose[4][lane] = q[1]; s_pose[5][lane] = q[2]; s_pose[6][lane] = q[3];
     }
@@ -710,6 +752,67 @@ __device__ __forceinline__ void load_cell_g<2>(uint64_t addr, Cell<2> &c)
     c.a = *reinterpret_cast<const u4v *>(addr);
 }
 
+// |a - b| with every operation rounded on its own (no contraction), so that
+// the path lengths below do not depend on how a loop body is compiled.
+__device__ __forceinline__ float seg_len(float ax, float ay, float az, float bx, float by, float bz)
+{
+    return __fsqrt_rn(dist2_rn(ax, ay, az, bx, by, bz));
+}
+
+// Keyframe propagation of the loop-gated correction (Eq. 8-10) for the tile's
+// particles: keyframe k in (o, K) moves by psi_k = (d_k / d_t) psi, where d_k
+// is the path length along the particle's keyframe translations from its
+// oldest neighbour o to k and d_t = d_{K-1} + |t_pre - t_{K-1}|.  The keyframes
+// (o, K) are split into W contiguous chunks, one per wave.  Phase 1 (reads
+// only) gives each wave d_t and the path length and translation just before
+// its chunk; after the barrier, phase 2 rewrites the chunk.  The sum runs in k
+// order in both phases, so d_k does not depend on W.
+template <int W>
+__device__ __forceinline__ void kf_propagate(const StepDesc &d, int i, int lane, int wave,
+                                             const int *s_loop, const float (*s_upd)[64])
+{
+    const int N = d.N, K = d.K;
+    const int o = s_loop[lane];
+    const bool act = o >= 0 && i < N;
+    float *kp = d.kf_pose;
+    const size_t col = act ? (size_t)i : 0;
+    const int len = K - 1 - o;
+    const int chunk = (len + W - 1) / W;
+    const int ka = o + 1 + wave * chunk;
+    const int kb = min(K, ka + chunk);
+    float dt = 0.0f, da = 0.0f, ax = 0.0f, ay = 0.0f, az = 0.0f;
+    if (act) {
+        float px = kp[((size_t)o * 7) * N + col], py = kp[((size_t)o * 7 + 1) * N + col],
+              pz = kp[((size_t)o * 7 + 2) * N + col];
+        float acc = 0.0f;
+        ax = px; ay = py; az = pz;
+        for (int k = o + 1; k < K; ++k) {
+            if (k == ka) { da = acc; ax = px; ay = py; az = pz; }
+            const size_t r = (size_t)k * 7 * N + col;
+            const float x = kp[r], y = kp[r + N], z = kp[r + 2 * N];
+            acc = __fadd_rn(acc, seg_len(x, y, z, px, py, pz));
+            px = x; py = y; pz = z;
+        }
+        dt = __fadd_rn(acc, seg_len(s_upd[6][lane], s_upd[7][lane], s_upd[8][lane], px, py, pz));
+    }
+    __syncthreads();
+    if (act && dt > 0.0f) {
+        for (int k = ka; k < kb; ++k) {
+            const size_t r = (size_t)k * 7 * N + col;
+            float t[3] = {kp[r], kp[r + N], kp[r + 2 * N]};
+            float q[4] = {kp[r + 3 * N], kp[r + 4 * N], kp[r + 5 * N], kp[r + 6 * N]};
+            da = __fadd_rn(da, seg_len(t[0], t[1], t[2], ax, ay, az));
+            ax = t[0]; ay = t[1]; az = t[2];
+            const float ratio = __fdiv_rn(da, dt);
+            const float rho[3] = {ratio * s_upd[0][lane], ratio * s_upd[1][lane], ratio * s_upd[2][lane]};
+            const float phi[3] = {ratio * s_upd[3][lane], ratio * s_upd[4][lane], ratio * s_upd[5][lane]};
+            right_exp(t, q, rho, phi);
+            kp[r] = t[0]; kp[r + N] = t[1]; kp[r + 2 * N] = t[2];
+            kp[r + 3 * N] = q[0]; kp[r + 4 * N] = q[1]; kp[r + 5 * N] = q[2]; kp[r + 6 * N] = q[3];
+        }
+    }
+}
+
 template <int DT, bool SKIP, int W>
 __device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
 {
@@ -718,6 +821,8 @@ __device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
     __shared__ float s_pose[7][64];
     __shared__ float s_aff[kKfMaxNb][15][64];   // per neighbour: A' (9), b_frac (3), b_int (3)
     __shared__ int s_nb[kKfMaxNb][64];
+    __shared__ int s_loop[64];                  // oldest neighbour when a loop is detected, else -1
+    __shared__ float s_upd[9][64];              // psi and the translation before the step
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -756,6 +861,10 @@ __device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
         for (int s = 0; s < kKfMaxNb; ++s) s_nb[s][lane] = bk[s] < K ? bk[s] : 0;
         if (i < N)
             for (int s = 0; s < n_nb; ++s) d.neighbors[(size_t)s * N + i] = s_nb[s][lane];
+        // Loop detection (Sec. III-C.2): an old keyframe among the neighbours.
+        int o = K;
+        for (int s = 0; s < n_nb; ++s) o = min(o, s_nb[s][lane]);
+        s_loop[lane] = (d.kf_loop && o < K - d.n_recent) ? o : -1;
     }
     const int chunk = (d.M + W - 1) / W;
     const int j0 = min(d.M, wave * chunk);
@@ -845,8 +954,17 @@ __device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
         s_l[wave][lane] = l;
         for (int c = 0; c < 6; ++c) s_g[c][wave][lane] = g[c];
         __syncthreads();
-        if (wave == 0) tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose);
+        if (wave == 0) {
+            if (d.kf_loop)
+                tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose, s_loop, s_upd);
+            else
+                tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose);
+        }
         __syncthreads();
+        if (d.kf_loop && pass < d.iters) {
+            kf_propagate<W>(d, i, lane, wave, s_loop, s_upd);
+            __syncthreads();
+        }
     }
     if (wave == 0) store_tile_pose(d, i, lane, s_pose);
     __syncthreads();
@@ -938,9 +1056,18 @@ __global__ void k_build_cells(const float *__restrict__ grid, void *__restrict__
         c[s] = grid[(size_t)(i + a) + (size_t)nx * ((size_t)(j + b) + (size_t)ny * (k + cc))];
     }
     if (dtype == 0) {
+        // Coefficients of the cell's trilinear polynomial (slot s = a + 2b + 4c
+        // holds corner (a, b, c)), in FP64 and rounded once.
+        const double v000 = c[0], v100 = c[1], v010 = c[2], v110 = c[3];
+        const double v001 = c[4], v101 = c[5], v011 = c[6], v111 = c[7];
+        const double a0 = v000, a1 = v100 - v000, a2 = v010 - v000, a3 = v001 - v000;
+        const double a4 = v110 - v100 - v010 + v000;
+        const double a5 = v101 - v100 - v001 + v000;
+        const double a6 = v011 - v010 - v001 + v000;
+        const double a7 = v111 - v110 - v101 - v011 + v100 + v010 + v001 - v000;
         float4 *o = reinterpret_cast<float4 *>(cells) + 2 * r;
-        o[0] = make_float4(c[0], c[1], c[2], c[3]);
-        o[1] = make_float4(c[4], c[5], c[6], c[7]);
+        o[0] = make_float4((float)a0, (float)a1, (float)a2, (float)a3);
+        o[1] = make_float4((float)a4, (float)a5, (float)a6, (float)a7);
     } else if (dtype == 1) {
         reinterpret_cast<uint4 *>(cells)[r] =
             make_uint4(pack_f16(c[0], c[1]), pack_f16(c[2], c[3]), pack_f16(c[4], c[5]),

@@ -235,6 +235,12 @@ mcs_status validate_params(const Session *s, const mcs_step_params *p, int M)
     if (s->K > 0 && (p->n_neighbors < 1 || p->n_neighbors > std::min(s->K, kMaxNeighbors)))
         return fail(MCS_EINVAL, "n_neighbors=%d outside [1, %d]", p->n_neighbors,
                     std::min(s->K, kMaxNeighbors));
+    if (p->kf_update != MCS_KF_FIXED && p->kf_update != MCS_KF_LOOP)
+        return fail(MCS_EINVAL, "bad kf_update mode");
+    if (p->kf_update == MCS_KF_LOOP && s->K == 0)
+        return fail(MCS_EINVAL, "MCS_KF_LOOP needs a keyframe map");
+    if (p->kf_update == MCS_KF_LOOP && p->n_recent < 0)
+        return fail(MCS_EINVAL, "n_recent=%d must be >= 0", p->n_recent);
     return MCS_OK;
 }
 
@@ -254,6 +260,8 @@ StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float 
     d.inv_h = 1.0f / m->desc.res;
     d.K = s->K;
     d.n_nb = s->K > 0 ? p->n_neighbors : 0;
+    d.kf_loop = s->K > 0 && p->kf_update == MCS_KF_LOOP;
+    d.n_recent = p->n_recent;
     d.pose = s->pose; d.pose_tmp = s->pose_tmp;
     d.kf_pose = s->kf_pose; d.kf_pose_tmp = s->kf_pose_tmp;
     d.loglik = s->loglik; d.grad = s->grad;

@@ -51,7 +51,9 @@ struct TableBuf {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
+    hipStream_t stream = nullptr;     // ticks of this buffer run here
     std::vector<int64_t> reqs;        // requests of the tick in flight
+    std::unordered_set<int32_t> sessions;   // their sessions
     bool busy = false;
 };
 
@@ -102,15 +104,16 @@ mcs_status alloc_tables(mcs_server *s, TableBuf &b)
     b.counts_d = (int32_t *)(d + o); b.counts_h = (int32_t *)(h + o); o += n_counts;
     b.heads_d = (unsigned int *)(d + o);
     HIP_TRY(hipEventCreateWithFlags(&b.done, hipEventDisableTiming), "hipEventCreate");
+    HIP_TRY(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking), "hipStreamCreate");
     if (s->mode == MCS_SERVE_BATCHED) {
         BatchTables t{};
         t.descs = b.descs_d;
         for (int k = 0; k < kNumKinds; ++k) t.items[k] = b.items_d[k];
         t.counts = b.counts_d;
         t.heads = b.heads_d;
-        HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal), "capture begin");
-        hipError_t e = launch_batch(t, s->dtype, s->oob == MCS_OOB_SKIP, s->stream);
-        hipError_t e2 = hipStreamEndCapture(s->stream, &b.graph);
+        HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal), "capture begin");
+        hipError_t e = launch_batch(t, s->dtype, s->oob == MCS_OOB_SKIP, b.stream);
+        hipError_t e2 = hipStreamEndCapture(b.stream, &b.graph);
         if (e != hipSuccess) return hip_fail(e, "capture launch");
         if (e2 != hipSuccess) return hip_fail(e2, "capture end");
         HIP_TRY(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
@@ -123,6 +126,7 @@ void free_tables(TableBuf &b)
     if (b.exec) (void)hipGraphExecDestroy(b.exec);
     if (b.graph) (void)hipGraphDestroy(b.graph);
     if (b.done) (void)hipEventDestroy(b.done);
+    if (b.stream) (void)hipStreamDestroy(b.stream);
     if (b.dev) (void)hipFree(b.dev);
     if (b.host) (void)hipHostFree(b.host);
     b = TableBuf{};
@@ -150,13 +154,14 @@ void finish_tick(mcs_server *s, TableBuf &b)
         s->completed++;
     }
     b.reqs.clear();
+    b.sessions.clear();
     b.busy = false;
     s->cv_done.notify_all();
 }
 
 // Build and launch one tick from the pending queue (mutex held by caller on
 // entry; released while touching the device).  Returns false if nothing ran.
-bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b)
+bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b, TableBuf &other)
 {
     // Pick at most one pending frame per session, oldest first.
     std::vector<int64_t> take;
@@ -176,6 +181,12 @@ bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b)
     int used = 0;
     const int64_t t_launch = now_ns();
     std::vector<int64_t> run;
+    // A session still running in the other buffer's tick orders this tick
+    // after it; otherwise the two ticks may overlap on the device.
+    bool depends = false;
+    if (other.busy)
+        for (auto &r : rq) depends = depends || other.sessions.count(r.session_id) > 0;
+    std::unordered_set<int32_t> tick_sessions;
     for (auto &r : rq) {
         Session *ss = find_session(s->ctx, r.session_id);
         if (!ss) continue;   // validated at submission; a destroyed session is skipped
@@ -195,22 +206,25 @@ bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b)
             for (int q = 0; q < need[k]; ++q) b.items_h[k][counts[k]++] = make_int2(used, q);
         ++used;
         run.push_back(r.id);
+        tick_sessions.insert(r.session_id);
     }
     for (int k = 0; k < kNumKinds; ++k) b.counts_h[k] = counts[k];
     hipError_t e = hipSuccess;
     if (used > 0) {
+        if (depends) e = hipStreamWaitEvent(b.stream, other.done, 0);
         // Copy only the used parts of the tables.
-        e = hipMemcpyAsync(b.descs_d, b.descs_h, used * sizeof(StepDesc), hipMemcpyHostToDevice,
-                           s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b.descs_d, b.descs_h, used * sizeof(StepDesc), hipMemcpyHostToDevice,
+                               b.stream);
         for (int k = 0; k < kNumKinds && e == hipSuccess; ++k)
             if (counts[k] > 0)
                 e = hipMemcpyAsync(b.items_d[k], b.items_h[k], counts[k] * sizeof(int2),
-                                   hipMemcpyHostToDevice, s->stream);
+                                   hipMemcpyHostToDevice, b.stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(b.counts_d, b.counts_h, kNumKinds * sizeof(int32_t),
-                               hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess) e = hipGraphLaunch(b.exec, s->stream);
-        if (e == hipSuccess) e = hipEventRecord(b.done, s->stream);
+                               hipMemcpyHostToDevice, b.stream);
+        if (e == hipSuccess) e = hipGraphLaunch(b.exec, b.stream);
+        if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
     }
     lk.lock();
     if (e != hipSuccess) {
@@ -229,6 +243,7 @@ bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b)
         r.t.tick = (int32_t)s->ticks;
     }
     b.reqs = run;
+    b.sessions = tick_sessions;
     b.busy = true;
     s->ticks++;
     if (used > s->max_batch_seen) s->max_batch_seen = used;
@@ -269,41 +284,40 @@ void worker_main(mcs_server *s)
     (void)hipSetDevice(s->ctx->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        const bool any_busy = s->buf[0].busy || s->buf[1].busy;
-        if (s->pending.empty() && !any_busy) {
-            if (s->stop) break;
-            s->cv_work.wait(lk);
-            continue;
-        }
         if (s->mode == MCS_SERVE_SERIAL) {
+            if (s->pending.empty()) {
+                if (s->stop) break;
+                s->cv_work.wait(lk);
+                continue;
+            }
             run_serial(s, lk);
             continue;
         }
-        // Queue a new tick into the free buffer, if any.
-        TableBuf &nb = s->buf[s->next_buf];
+        // Retire finished ticks without blocking.
+        for (auto &b : s->buf) {
+            if (!b.busy) continue;
+            const hipError_t q = hipEventQuery(b.done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) set_error(s, hip_fail(q, "server tick"));
+            lk.unlock();
+            finish_tick(s, b);
+            lk.lock();
+        }
+        // Queue a tick into a free buffer (ticks alternate between the two).
         bool launched = false;
+        TableBuf &nb = s->buf[s->next_buf];
         if (!nb.busy && !s->pending.empty()) {
-            launched = launch_tick(s, lk, nb);
+            launched = launch_tick(s, lk, nb, s->buf[s->next_buf ^ 1]);
             if (launched) s->next_buf ^= 1;
         }
-        // Retire the oldest tick: wait when both buffers are busy or when no
-        // new work could be queued.
-        TableBuf &old = s->buf[s->next_buf];
-        if (old.busy && (s->buf[0].busy && s->buf[1].busy || !launched)) {
-            lk.unlock();
-            hipError_t e = hipEventSynchronize(old.done);
-            if (e != hipSuccess) set_error(s, hip_fail(e, "server tick wait"));
-            finish_tick(s, old);
-            lk.lock();
-        } else if (!launched && !old.busy) {
-            // Nothing runs and nothing could be queued (pending work does not fit).
-            TableBuf &other = s->buf[s->next_buf ^ 1];
-            if (other.busy) {
-                lk.unlock();
-                (void)hipEventSynchronize(other.done);
-                finish_tick(s, other);
-                lk.lock();
-            }
+        if (launched) continue;
+        const bool any_busy = s->buf[0].busy || s->buf[1].busy;
+        if (!any_busy && s->pending.empty()) {
+            if (s->stop) break;
+            s->cv_work.wait(lk);
+        } else {
+            // Work in flight: wake on a new submission or after a short poll interval.
+            s->cv_work.wait_for(lk, std::chrono::microseconds(20));
         }
     }
 }
@@ -370,7 +384,7 @@ mcs_status mcs_server_destroy(mcs_server *s)
     }
     s->worker.join();
     (void)hipSetDevice(s->ctx->device);
-    (void)hipStreamSynchronize(s->stream);
+    (void)hipDeviceSynchronize();
     for (auto &b : s->buf) free_tables(b);
     (void)hipStreamDestroy(s->stream);
     delete s;
@@ -391,6 +405,8 @@ mcs_status mcs_server_submit(mcs_server *s, int32_t sid, const float *scan_dev, 
         return fail(MCS_EINVAL, "out-of-grid rule differs from the server's");
     StepDesc probe = make_desc(ss, scan_dev, M, noise_dev, p);
     if (!eval_supported(probe)) return fail(MCS_EINVAL, "map not supported");
+    if (weight_blocks(ss->N) > s->max_items || scan_blocks(M) > s->max_items)
+        return fail(MCS_EINVAL, "session work exceeds the server's per-tick work lists");
     Request r{};
     r.session_id = sid;
     r.scan = scan_dev;

@@ -366,7 +366,7 @@ def keyframe_grid(points, grid_n, h, sigma, cutoff_sigmas=6.0):
 
 def keyframes(N=50000, K=64, kf_points=16384, M_rings=32, n_az=64, grid_n=128, h=0.2,
               sigma=0.1, n_nb=4, seed=1003, kf_drift=(0.05, 0.5), ambiguous=False,
-              grid_dtype=GRID_FP32, workers=8):
+              out_and_back=False, grid_dtype=GRID_FP32, workers=8):
     """Keyframe-map workload: K keyframes along a corridor trajectory.
 
     Each keyframe scan (kf_points rays, 64 rings over [-15, 15] deg) is
@@ -375,6 +375,9 @@ def keyframes(N=50000, K=64, kf_points=16384, M_rings=32, n_az=64, grid_n=128, h
     has M_rings x n_az points.  Every particle carries its own pose per keyframe:
     the true keyframe pose composed with N(0, drift) noise (metres, degrees).
     With ambiguous=True the scene is a row of identical rooms (translated copies).
+    With out_and_back=True the path turns round half way and retraces itself, so
+    the current frame is back at the start: its neighbour keyframes include the
+    oldest ones (a loop) as well as the newest.
     """
     rng = np.random.default_rng(seed)
     if ambiguous:
@@ -385,6 +388,12 @@ def keyframes(N=50000, K=64, kf_points=16384, M_rings=32, n_az=64, grid_n=128, h
         scene = corridor_scene(rng)
         n_frames = 3 * K + 1
         t_traj, q_traj = maze_trajectory(scene, rng, n_frames=n_frames)
+    if out_and_back:
+        half = (n_frames + 1) // 2
+        t_traj = np.concatenate([t_traj[:half], t_traj[:n_frames - half][::-1]])
+        flip = geo.quat_yaw(np.full(n_frames - half, math.pi))
+        q_back = np.stack([geo.quat_mul(q, flip[0]) for q in q_traj[:n_frames - half][::-1]])
+        q_traj = np.concatenate([q_traj[:half], q_back])
     kf_frames = np.arange(K) * 3
     cur = n_frames - 1
     n_kf_rings = 64

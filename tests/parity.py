@@ -102,3 +102,28 @@ def check_weights_resample(logw_in, loglik_gpu, beta, u, out, policy, ess_frac=0
         assert np.array_equal(out["parents"], np.arange(N))
         assert np.allclose(out["logw"], lw_ref, rtol=0, atol=1e-13 * max(1.0, abs(L)))
     return dict(lse=L, ess=ess, ties=n_tie)
+
+
+def check_loop_update(poses_in, kf_in, out, params, n_recent):
+    """Loop-gated correction (Eq. 5-10), the oracle fed the GPU's gradient and
+    neighbours: loop flags exact; untouched poses bit-exact; moved poses within
+    the step tolerances.  Returns the oracle's result."""
+    ref = oracle.kf_loop_update(poses_in, kf_in, out["grad"].astype(np.float64), out["neighbors"],
+                                params, n_recent=n_recent)
+    loop = ref["loop"] >= 0
+    P, KP = out["poses"], out["kf_poses"]
+    # Not corrected: the translation is untouched, the quaternion only renormalised.
+    assert np.array_equal(P[~loop, :3], poses_in[~loop, :3]), "a particle without a loop moved"
+    assert np.all(quat_angle(P[~loop, 3:], poses_in[~loop, 3:]) <= 1e-6)
+    assert np.array_equal(KP[~loop], kf_in[~loop]), "keyframes of a particle without a loop moved"
+    N, K = KP.shape[:2]
+    o = np.where(loop, ref["loop"], K)
+    before = np.arange(K)[None, :] <= o[:, None]
+    assert np.array_equal(KP[before], kf_in[before]), "a keyframe at or before the oldest neighbour moved"
+    for got, want in ((P[loop], ref["poses"][loop]), (KP[loop].reshape(-1, 7), ref["kf_poses"][loop].reshape(-1, 7))):
+        dt = np.abs(got[:, :3].astype(np.float64) - want[:, :3])
+        tol = 4 * ulp32(want[:, :3]) + 2e-7
+        assert np.all(dt <= tol), "translation off by %g (tol %g)" % (dt.max(), tol.max())
+        ang = quat_angle(got[:, 3:], want[:, 3:])
+        assert np.all(ang <= 2e-6), "rotation off by %g rad" % ang.max()
+    return ref

@@ -15,7 +15,7 @@ import oracle
 from paper_2504_18056_amd import abi
 from synth import configs
 
-from parity import DELTA, check_step, check_weights_resample, quat_angle
+from parity import DELTA, check_loop_update, check_step, check_weights_resample, quat_angle
 
 pytestmark = pytest.mark.gpu
 
@@ -106,3 +106,60 @@ def test_ambiguous_rooms_keep_several_modes(ctx):
     out = kf_step(ctx, c, p)
     check_kf(c, out, p, idx=np.arange(0, 4000, 40))
     assert math.isfinite(out["stats"]["ess"])
+
+
+def test_loop_closure_out_and_back(ctx):
+    """The path returns to its start: every particle sees the oldest keyframes,
+    corrects its pose and propagates the step along its keyframes (Eq. 8-10)."""
+    c = configs.keyframes(N=700, K=16, kf_points=4096, seed=35, out_and_back=True)
+    p = dict(c["params"], iters=1, u=0.3, beta=0.01, resample=abi.RESAMPLE_NEVER,
+             kf_update=abi.KF_LOOP, n_recent=4)
+    out = kf_step(ctx, c, p)
+    check_kf(c, out, p)
+    ref = check_loop_update(c["poses"], c["kf_poses"], out, p, n_recent=4)
+    assert np.all(ref["loop"] >= 0)
+    moved = np.abs(out["kf_poses"][:, 1:, :3] - c["kf_poses"][:, 1:, :3]).max()
+    assert moved > 1e-3
+
+
+def test_loop_gate_mixed_particles(ctx):
+    """Particles whose keyframe estimate of an old keyframe sits next to them
+    detect a loop; the others keep their state untouched."""
+    c = configs.keyframes(N=333, K=12, kf_points=4096, seed=36)
+    kf = c["kf_poses"].copy()
+    poses = c["poses"]
+    sel = np.arange(0, 333, 3)
+    kf[sel, 2, :3] = poses[sel, :3] + np.float32(0.3)
+    p = dict(c["params"], iters=1, u=0.6, beta=0.01, resample=abi.RESAMPLE_NEVER,
+             kf_update=abi.KF_LOOP, n_recent=4)
+    out = kf_step(ctx, c, p, kf=kf)
+    check_kf(c, out, p, kf=kf)
+    ref = check_loop_update(poses, kf, out, p, n_recent=4)
+    loop = ref["loop"] >= 0
+    assert loop[sel].all() and 0 < (~loop).sum()
+    # More than W keyframes per particle to update exercises every wave's chunk.
+    assert np.all(ref["loop"][sel] == 2)
+
+
+def test_loop_update_is_deterministic_and_resampling_carries_it(ctx):
+    c = configs.keyframes(N=500, K=16, kf_points=4096, seed=37, out_and_back=True)
+    p = dict(c["params"], iters=2, u=0.45, beta=0.01, resample=abi.RESAMPLE_ALWAYS,
+             kf_update=abi.KF_LOOP, n_recent=4)
+    a = kf_step(ctx, c, p)
+    b = kf_step(ctx, c, p)
+    for k in ("poses", "kf_poses", "loglik", "grad", "parents", "logw"):
+        assert np.array_equal(a[k], b[k]), k
+    check_weights_resample(c["logw"], a["loglik"], 0.01, p["u"], a, abi.RESAMPLE_ALWAYS)
+
+
+def test_loop_mode_rejected_without_keyframes(ctx):
+    c = configs.box_room(N=64)
+    mid = abi.mcs_init_map(ctx, abi.grid_desc(c["dims"], c["origin"], c["h"]), c["grid"])
+    sid = abi.mcs_session_create(ctx, mid, c["poses"], M_max=c["scan"].shape[0])
+    try:
+        with pytest.raises(abi.McsError) as e:
+            abi.mcs_filter_step(ctx, sid, c["scan"], dict(c["params"], kf_update=abi.KF_LOOP))
+        assert e.value.status == abi.MCS_EINVAL
+    finally:
+        abi.mcs_session_destroy(ctx, sid)
+        abi.mcs_release_map(ctx, mid)
