@@ -27,12 +27,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particle×point lik+grad evals/s; ms/step @100k particles; p99 session ms"
-HBM_PEAK_GBS = 8000.0
-BYTES_PER_EVAL = {0: 32, 1: 16, 2: 16}    # 8 grid samples per evaluation
+# The evaluation kernel is bound by VALU issue.  Its algorithmic work is
+# counted in VALU lane-operations (FP32 or FP64, an FMA counting once): the
+# compiled inner loop (gfx950) issues 123 VALU instructions per 2 evaluations
+# with FP32 cell records, 161 with 16-bit records.  Peak: 256 CU x 4 SIMD x 16
+# lanes x 2.4 GHz = 39.3e12 lane-ops/s without packed FP32 (disabled in this
+# build); the 157.3 TFLOP/s vector figure counts a packed FMA as 4 flops per
+# lane and cycle.
+VALU_OPS_PER_EVAL = {0: 61.5, 1: 80.5, 2: 80.5}
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+BYTES_PER_EVAL = {0: 32, 1: 16, 2: 16}    # one cell record per evaluation
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_corridors_100k_counters.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2504_18056_amd", "csrc", "kernels.hip")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(grid_dtype):
+    """HBM bytes per launch of the evaluation kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings), or
+    None when the summary is missing, is for another grid dtype, or was taken
+    on a different kernel source."""
+    import hashlib
+    try:
+        with open(PMC_SUMMARY) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if kv.get("kernel_source_sha256", "").strip() != sha or int(kv.get("grid_dtype", -1)) != grid_dtype:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def cpu_cores():
@@ -113,7 +141,9 @@ def run_serving(args, abi, torch, prepared):
             arrivals.append((t, k))
     arrivals.sort()
     results = {}
-    for mode, name in ((abi.SERVE_BATCHED, "batched"), (abi.SERVE_SERIAL, "one_at_a_time")):
+    modes = ((abi.SERVE_BATCHED, "batched"), (abi.SERVE_CONCURRENT, "concurrent"),
+             (abi.SERVE_SERIAL, "one_at_a_time"))
+    for mode, name in modes:
         for s in sessions:
             abi.mcs_set_particles(ctx, s["sid"], poses=s["poses"], logw=np.full(s["N"], -math.log(s["N"])))
         torch.cuda.synchronize()
@@ -137,18 +167,48 @@ def run_serving(args, abi, torch, prepared):
         st = abi.mcs_server_stats_get(srv)
         abi.mcs_server_destroy(srv)
         lat = np.array([(t["done_ns"] - t["submit_ns"]) * 1e-6 for t in times])
+        wait = np.array([(t["launch_ns"] - t["submit_ns"]) * 1e-6 for t in times])
+        run = np.array([(t["done_ns"] - t["launch_ns"]) * 1e-6 for t in times])
         span = (max(t["done_ns"] for t in times) - min(t["submit_ns"] for t in times)) * 1e-9
-        results[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
-                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        pct = lambda a, q: round(float(np.percentile(a, q)), 3)
+        results[name] = {"p50_ms": pct(lat, 50), "p90_ms": pct(lat, 90), "p99_ms": pct(lat, 99),
                          "mean_ms": round(float(lat.mean()), 3),
-                         "frames": len(ids), "ticks": st["ticks"],
-                         "max_sessions_per_tick": st["max_batch_seen"],
+                         "queue_p50_ms": pct(wait, 50), "queue_p99_ms": pct(wait, 99),
+                         "run_p50_ms": pct(run, 50), "run_p99_ms": pct(run, 99),
+                         "frames": len(ids), "launches": st["ticks"],
+                         "max_in_flight": st["max_batch_seen"],
                          "evals_per_s": round(st["evals"] / span, 1)}
         log("serving %s: %s" % (name, results[name]))
     abi.mcs_destroy(ctx)
+    # Admission under an HBM budget of half the footprint: sessions are admitted
+    # in order until the next one would exceed the budget.
+    budget = mem // 2
+    actx = abi.mcs_create(0, hbm_budget_bytes=budget)
+    admitted = refused = 0
+    for desc, x in prepared:
+        try:
+            mid = abi.mcs_init_map(actx, abi.grid_desc(x["dims"], x["origin"], x["h"], abi.GRID_FP16),
+                                   x["grid"])
+        except abi.McsError as e:
+            if e.status != abi.MCS_EBUDGET:
+                raise
+            refused += 1
+            continue
+        try:
+            abi.mcs_session_create(actx, mid, x["poses"], M_max=desc["M"])
+            admitted += 1
+        except abi.McsError as e:
+            if e.status != abi.MCS_EBUDGET:
+                raise
+            abi.mcs_release_map(actx, mid)
+            refused += 1
+    in_use = abi.mcs_memory_in_use(actx)
+    abi.mcs_destroy(actx)
     return {"sessions": len(sessions), "seconds": args.serving_seconds,
             "arrival_hz_per_session": 10.0 * args.serving_load,
-            "resident_gb": round(mem / 1e9, 2), **results}
+            "resident_gb": round(mem / 1e9, 2), **results,
+            "admission_at_half_budget": {"budget_gb": round(budget / 1e9, 2), "admitted": admitted,
+                                         "refused": refused, "in_use_gb": round(in_use / 1e9, 2)}}
 
 
 def run_precision(abi):
@@ -320,16 +380,39 @@ def main():
     err = float(np.linalg.norm(best[:3] - c["t_traj"][f_last]))
     log("timed %d steps: %.3f ms/step; eval %.3f ms/step; representative error %.3f m" % (
         args.steps, 1e3 * wall / args.steps, prof["eval_ms"] / max(1, prof["steps"]), err))
+    # Host-buffer entry point (scan and noise copied over PCIe each step), for reference.
+    n_host = 10
+    scans_host = [np.ascontiguousarray(c["scans"][f]) for f in frames[:n_host]]
+    noise_host_f = [noise_host[slot[f]] for f in frames[:n_host]]
+    abi.mcs_session_sync(ctx, sid)
+    t0 = time.perf_counter()
+    for k in range(n_host):
+        f = frames[k]
+        abi.mcs_filter_step(ctx, sid, scans_host[k], dict(base, u=float(c["u"][f]), delta_T=c["odometry"][f]),
+                            noise=noise_host_f[k])
+    abi.mcs_session_sync(ctx, sid)
+    host_ms = 1e3 * (time.perf_counter() - t0) / n_host
+    log("host-buffer entry point: %.3f ms/step" % host_ms)
     abi.mcs_destroy(ctx)
 
     passes = base["iters"]
     evals_per_step = N * M * passes
     value = evals_per_step * args.steps / wall
     eval_s = prof["eval_ms"] * 1e-3 / max(1, prof["steps"])   # one eval launch per step
-    bpe = BYTES_PER_EVAL[args.grid_dtype]
-    achieved = bpe * evals_per_step / eval_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    ops = VALU_OPS_PER_EVAL[args.grid_dtype] * evals_per_step
+    achieved = ops / eval_s / 1e12
+    traffic = measured_traffic(args.grid_dtype)
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": traffic,
+                "kernel": "k_eval", "eval_launch_ms": round(eval_s * 1e3, 4),
+                "note": "VALU lane-operations per second (FP32/FP64, FMA counted once): %.1f per "
+                        "evaluation x %d evaluations per launch; peak = 256 CU x 64 lanes x 2.4 GHz "
+                        "(no packed FP32). traffic = HBM bytes per launch from FETCH_SIZE/WRITE_SIZE "
+                        "(%s); the algorithmic gather is %d B per evaluation = %.2f GB per launch"
+                        % (VALU_OPS_PER_EVAL[args.grid_dtype], evals_per_step,
+                           os.path.relpath(PMC_SUMMARY, ROOT), BYTES_PER_EVAL[args.grid_dtype],
+                           BYTES_PER_EVAL[args.grid_dtype] * evals_per_step / 1e9)}
     stage_ms = {k: round(prof[k] / max(1, prof["steps"]), 4)
                 for k in ("predict_ms", "eval_ms", "weights_ms", "resample_ms")}
 
@@ -374,10 +457,12 @@ def main():
                    "particles": N, "points": M, "passes": passes,
                    "grid": list(c["dims"]), "grid_dtype": dtype_name},
         "stage_ms": stage_ms,
+        "host_buffers_ms_per_step": round(host_ms, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ms_per_step_100k": round(1e3 * wall / args.steps, 4) if N == 100000 else None,
-        "p99_session_ms": serving["batched"]["p99_ms"] if serving else None,
+        "p99_session_ms": (min(serving["batched"]["p99_ms"], serving["concurrent"]["p99_ms"])
+                           if serving else None),
         "serving": serving,
         "keyframes": keyframes,
         "precision": precision,

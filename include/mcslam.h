@@ -263,29 +263,36 @@ mcs_status mcs_session_profile_read(mcs_ctx *ctx, int32_t session_id, mcs_profil
  * runs join the next one.  A session's frames always run in submission order.
  * Results are identical to mcs_filter_step_dev on the same inputs (the
  * kernels and their reduction order do not depend on the batch).
+ * MCS_SERVE_CONCURRENT launches each request as soon as it arrives, with the
+ * plain per-session launches on the session's own stream, so frames of
+ * different sessions run side by side on the device with no tick boundary
+ * (at most 256 requests in flight).  While a server holds requests of a
+ * session, the session must not be stepped directly.
  * MCS_SERVE_SERIAL runs one request at a time with the plain per-session
  * launches and waits for each (the one-session-at-a-time baseline).
+ * A completion thread retires each request as soon as its work is done.
  * Sessions served must be single-grid sessions whose map has the server's grid
  * dtype; admission to device memory is the context's HBM budget
  * (mcs_session_create returns MCS_EBUDGET when it would be exceeded). */
 typedef struct mcs_server mcs_server;
 
-#define MCS_SERVE_BATCHED 0
-#define MCS_SERVE_SERIAL  1
+#define MCS_SERVE_BATCHED    0
+#define MCS_SERVE_SERIAL     1
+#define MCS_SERVE_CONCURRENT 2
 
 typedef struct {
     int64_t submit_ns;      /* host steady-clock time of mcs_server_submit */
     int64_t launch_ns;      /* when the worker enqueued the request's work */
     int64_t done_ns;        /* when the worker saw the work complete */
     int32_t session_id;
-    int32_t tick;           /* tick (or serial slot) that ran it */
+    int32_t tick;           /* tick (or launch slot) that ran it */
 } mcs_request_times;
 
 typedef struct {
     int64_t requests;       /* completed requests */
-    int64_t ticks;          /* ticks (or serial steps) run */
+    int64_t ticks;          /* ticks (or single-request launches) run */
     int64_t evals;          /* particle x point evaluations completed */
-    int32_t max_batch_seen; /* most sessions in one tick */
+    int32_t max_batch_seen; /* most sessions in one tick (CONCURRENT: most requests in flight) */
     int32_t pad;
 } mcs_server_stats;
 

@@ -66,6 +66,13 @@ def lib():
                                      _fp, i32, i32, f64, _dp, _dp, _opt("d"), _opt("d"),
                                      _opt("d"), _opt("i"), _opt("i"), i32]
         L.oracle_kf_eval.restype = i32
+        u64 = C.c_uint64
+        L.oracle_splitmix64.argtypes = [u64, i32, np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")]
+        L.oracle_rng_normals.argtypes = [u64, u64, i32, _dp]
+        L.oracle_predict_rng.argtypes = [_fp, i32, _dp, u64, u64, _dp, _dp]
+        L.oracle_predict_rng.restype = i32
+        L.oracle_prune.argtypes = [_dp, _dp, i32, f64, f64, f64, _ip, _dp, C.POINTER(i32), _opt("d")]
+        L.oracle_prune.restype = i32
         L.oracle_kf_loop_update.argtypes = [_fp, _fp, _dp, _ip, i32, i32, i32, i32, f64, f64, f64,
                                             f64, _dp, _dp, _ip, _opt("d")]
         L.oracle_kf_loop_update.restype = i32
@@ -225,6 +232,41 @@ def kf_evaluate(grids, dims, origins, h, eps, scan, poses, kf_poses, n_nb=4, oob
                                 float(delta), ll, gr, ga, al, ag, na, nb, int(nthreads)),
            "oracle_kf_eval")
     return dict(loglik=ll, grad=gr, gabs=ga, amb_l=al, amb_g=ag, n_amb=na, neighbors=nb)
+
+
+def splitmix64(seed, n):
+    """The first n 64-bit outputs of SplitMix64 seeded with `seed`."""
+    out = np.empty(int(n), np.uint64)
+    lib().oracle_splitmix64(int(seed) & (2**64 - 1), int(n), out)
+    return out
+
+
+def rng_normals(seed, frame, N):
+    """Standard normals (N, 6) of the counter-based prediction-noise stream of one frame."""
+    out = np.empty((int(N), 6))
+    lib().oracle_rng_normals(int(seed) & (2**64 - 1), int(frame), int(N), out)
+    return out
+
+
+def predict_rng(poses, dT, seed, frame, sigma):
+    """Prediction T <- T dT Exp(sigma z) with z from the counter-based stream (Eq. 1)."""
+    poses = _f32(poses).reshape(-1, 7)
+    out = np.empty((poses.shape[0], 7))
+    _check(lib().oracle_predict_rng(poses, poses.shape[0], _f64(dT, (7,)), int(seed) & (2**64 - 1),
+                                    int(frame), _f64(sigma, (6,)), out), "oracle_predict_rng")
+    return out
+
+
+def prune(logw, loglik, tau_post, tau_lik, u):
+    """Dead-particle pruning (Sec. III-F) on normalised log-weights; returns
+    parents, logw, n_dead and the per-slot tie margin."""
+    logw = _f64(logw).reshape(-1)
+    N = logw.size
+    par, lw, mg = np.empty(N, np.int32), np.empty(N), np.empty(N)
+    nd = C.c_int(0)
+    _check(lib().oracle_prune(logw, _f64(loglik).reshape(-1), N, float(tau_post), float(tau_lik),
+                              float(u), par, lw, C.byref(nd), mg), "oracle_prune")
+    return dict(parents=par, logw=lw, n_dead=nd.value, margin=mg)
 
 
 def kf_loop_update(poses, kf_poses, grad, neighbors, params, n_recent=3):

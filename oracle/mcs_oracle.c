@@ -590,6 +590,71 @@ int oracle_predict(const float *poses, int N, const double *dT, const float *del
     return 0;
 }
 
+/* Prediction noise drawn from a counter-based generator (the device draws
+ * the same numbers).  SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the
+ * k-th output (k >= 1) of the stream seeded with s is mix(s + k * gamma), with
+ * gamma = 0x9e3779b97f4a7c15 and mix the published finaliser.  The stream of
+ * frame f is keyed by the f-th output of the seed's stream; within it,
+ * particle i takes uniforms j = 6i .. 6i+5, U_j = (mix(key + (j+1) gamma) >> 11)
+ * 2^-53, and Box-Muller turns the pairs (U_{6i+2m}, U_{6i+2m+1}) into
+ * normals r cos(theta), r sin(theta) with r = sqrt(-2 ln(1 - U_a)) and
+ * theta = 2 pi U_b.  delta_c = sigma_c z_c (translation first, Eq. 1). */
+static uint64_t sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+static const uint64_t SM64_GAMMA = 0x9e3779b97f4a7c15ULL;
+
+static double sm64_uniform(uint64_t key, uint64_t j)
+{
+    return (double)(sm64_mix(key + (j + 1) * SM64_GAMMA) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+static void rng_normals6(uint64_t seed, uint64_t frame, uint64_t i, double z[6])
+{
+    const uint64_t key = sm64_mix(seed + (frame + 1) * SM64_GAMMA);
+    for (int m = 0; m < 3; ++m) {
+        const double ua = sm64_uniform(key, 6 * i + 2 * m);
+        const double ub = sm64_uniform(key, 6 * i + 2 * m + 1);
+        const double r = sqrt(-2.0 * log(1.0 - ua));
+        const double th = 2.0 * M_PI * ub;
+        z[2 * m] = r * cos(th);
+        z[2 * m + 1] = r * sin(th);
+    }
+}
+
+/* The raw 64-bit outputs of one SplitMix64 stream (for the known-answer pin). */
+void oracle_splitmix64(uint64_t seed, int n, uint64_t *out)
+{
+    for (int k = 0; k < n; ++k) out[k] = sm64_mix(seed + (uint64_t)(k + 1) * SM64_GAMMA);
+}
+
+/* Standard normals (N, 6) of frame `frame`. */
+void oracle_rng_normals(uint64_t seed, uint64_t frame, int N, double *out)
+{
+    for (int i = 0; i < N; ++i) rng_normals6(seed, frame, (uint64_t)i, out + 6 * (size_t)i);
+}
+
+/* Prediction with generated noise: T_i <- T_i dT Exp(sigma z_i) (Eq. 1). */
+int oracle_predict_rng(const float *poses, int N, const double *dT, uint64_t seed, uint64_t frame,
+                       const double *sigma, double *out)
+{
+    if (N < 0) return -1;
+    for (int i = 0; i < N; ++i) {
+        double pose[7], tmp[7], dTn[7], z[6], xi[6];
+        pose_from_float(poses + 7 * (size_t)i, pose);
+        memcpy(dTn, dT, sizeof dTn);
+        pose_mul(pose, dTn, tmp);
+        rng_normals6(seed, frame, (uint64_t)i, z);
+        for (int c = 0; c < 6; ++c) xi[c] = sigma[c] * z[c];
+        pose_right_exp(tmp, xi, out + 7 * (size_t)i);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Weights and resampling                                                    */
 /* ------------------------------------------------------------------------ */
@@ -646,6 +711,72 @@ int oracle_resample(const double *logw, int N, double u, int *ancestors, double 
         }
     }
     free(cdf);
+    return 0;
+}
+
+/* Dead-particle pruning (Sec. III-F) on normalised log-weights.  A particle
+ * is dead when its posterior weight is below tau_post (logw_i < ln tau_post)
+ * or its likelihood relative to the best particle of the frame is below
+ * tau_lik (l_i - max_j l_j < ln tau_lik).  Each dead slot, in ascending index
+ * order d_0 < d_1 < ..., receives a copy of a live particle drawn
+ * systematically from the live weights: with C_i = sum of w_m over live
+ * m <= i (sequential) and W = C_{N-1}, slot d_k takes
+ * a_k = min{i : C_i > (u + k)/D W} (the last live index when there is none).
+ * A parent p with c_p copies shares its weight equally with them, and the
+ * live mass is renormalised: logw'_p = logw_p - ln(1 + c_p) - ln W for p and
+ * each of its copies.  Without dead or without live particles nothing changes.
+ * Outputs: parents (identity for live particles), logw_out, *n_dead, and
+ * margin (N, optional): for a dead slot, min |C_i - target| over the two CDF
+ * values around its decision (how close it was to a tie), else +inf. */
+int oracle_prune(const double *logw, const double *loglik, int N, double tau_post, double tau_lik,
+                 double u, int *parents, double *logw_out, int *n_dead, double *margin)
+{
+    if (N <= 0) return -1;
+    double lmax = -INFINITY;
+    for (int i = 0; i < N; ++i) if (loglik[i] > lmax) lmax = loglik[i];
+    const double lp = log(tau_post), ll = log(tau_lik);
+    char *dead = (char *)malloc((size_t)N);
+    double *cdf = (double *)malloc(sizeof(double) * (size_t)N);
+    int *copies = (int *)calloc((size_t)N, sizeof(int));
+    if (!dead || !cdf || !copies) { free(dead); free(cdf); free(copies); return -2; }
+    int D = 0, last_live = -1;
+    double c = 0.0;
+    for (int i = 0; i < N; ++i) {
+        dead[i] = (logw[i] < lp) || (loglik[i] - lmax < ll);
+        if (dead[i]) ++D; else { c += exp(logw[i]); last_live = i; }
+        cdf[i] = c;
+        parents[i] = i;
+        logw_out[i] = logw[i];
+        if (margin) margin[i] = INFINITY;
+    }
+    *n_dead = D;
+    const double W = c;
+    if (D > 0 && last_live >= 0 && W > 0.0) {
+        int k = 0, i = 0;
+        for (int slot = 0; slot < N; ++slot) {
+            if (!dead[slot]) continue;
+            const double target = (u + (double)k) / (double)D * W;
+            while (i < N && !(cdf[i] > target)) ++i;   /* targets increase with k */
+            const int a = (i < N) ? i : last_live;
+            parents[slot] = a;
+            copies[a]++;
+            if (margin) {
+                double mg = INFINITY;
+                if (i < N) mg = fabs(cdf[i] - target);
+                if (i > 0 && fabs(cdf[i - 1] - target) < mg) mg = fabs(cdf[i - 1] - target);
+                margin[slot] = mg;
+            }
+            ++k;
+        }
+        const double lW = log(W);
+        for (int p = 0; p < N; ++p)
+            if (!dead[p]) logw_out[p] = logw[p] - log1p((double)copies[p]) - lW;
+        for (int s2 = 0; s2 < N; ++s2)
+            if (dead[s2]) logw_out[s2] = logw_out[parents[s2]];
+    } else {
+        *n_dead = 0;
+    }
+    free(dead); free(cdf); free(copies);
     return 0;
 }
 

@@ -65,7 +65,7 @@ class ServerStats(C.Structure):
                 ("max_batch_seen", C.c_int32), ("pad", C.c_int32)]
 
 
-SERVE_BATCHED, SERVE_SERIAL = 0, 1
+SERVE_BATCHED, SERVE_SERIAL, SERVE_CONCURRENT = 0, 1, 2
 
 _lib = None
 

@@ -42,7 +42,6 @@ struct StepDesc {
     double *logw;            // [N]
     double *cdf_local;       // [N]
     double *part;            // [4 * weight_blocks(N)]
-    unsigned int *counters;  // [2], self-resetting arrival counters
     int32_t *parents;        // [N]
     int32_t *neighbors;      // [n_nb][N]
     StepStatsDev *stats;
@@ -85,12 +84,15 @@ bool eval_supported(const StepDesc &d);
 // memory name (descriptor, block) pairs per stage; every stage kernel is
 // persistent (fixed grid) and pulls items with an atomic head, so one
 // captured graph serves any batch composition.
-enum BatchKind { kPack = 0, kPredict, kEval, kWeights, kNormScan, kSearch, kCommit, kNumKinds };
+enum BatchKind {
+    kPack = 0, kPredict, kEval, kWeights, kWCombine, kNormScan, kPrefix, kSearch, kCommit, kNumKinds
+};
 
 struct BatchTables {
     const StepDesc *descs;
-    const int2 *items[kNumKinds];   // (descriptor index, block index)
+    const int2 *items;              // (descriptor index, block index); stage k at offs[k]
     const int32_t *counts;          // [kNumKinds]
+    const int32_t *offs;            // [kNumKinds]
     unsigned int *heads;            // [kNumKinds], reset by the first kernel of a tick
 };
 

@@ -287,12 +287,9 @@ __device__ __forceinline__ float half_hi(uint32_t v)
     return (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
 }
 
+// Corner samples of a 16-bit record (FP32 records hold polynomial
+// coefficients instead and are not decoded).
 template <int DT> __device__ __forceinline__ void decode(const Cell<DT> &c, float v[8]);
-template <> __device__ __forceinline__ void decode<0>(const Cell<0> &c, float v[8])
-{
-    v[0] = c.a.x; v[1] = c.a.y; v[2] = c.a.z; v[3] = c.a.w;
-    v[4] = c.b.x; v[5] = c.b.y; v[6] = c.b.z; v[7] = c.b.w;
-}
 template <> __device__ __forceinline__ void decode<1>(const Cell<1> &c, float v[8])
 {
     v[0] = half_lo(c.a.x); v[1] = half_hi(c.a.x); v[2] = half_lo(c.a.y); v[3] = half_hi(c.a.y);
@@ -1123,23 +1120,8 @@ __device__ __forceinline__ void block_argmax(double &v, int &idx, double *shv, i
     __syncthreads();
 }
 
-// True in the block that arrives last among the n blocks counted on `counter`.
-__device__ __forceinline__ bool arrive_last(unsigned int *counter, int n)
-{
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned int t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == (unsigned int)(n - 1));
-    }
-    __syncthreads();
-    const bool last = s_last != 0;
-    if (last) __threadfence();
-    return last;
-}
-
+// Per-block partials of the weight update: logw += beta l, then the block's
+// max (lowest index on ties), sum of exp(logw - max) and of its square.
 __device__ __forceinline__ void weights_blk(const StepDesc &d, int b)
 {
     constexpr int B = kWeightBlock;
@@ -1148,7 +1130,6 @@ __device__ __forceinline__ void weights_blk(const StepDesc &d, int b)
     const int tid = threadIdx.x;
     const int i = b * B + tid;
     const int N = d.N;
-    const int nb = weight_blocks(N);
     double lw = -INFINITY;
     if (i < N) {
         lw = d.logw[i] + d.beta * (double)d.loglik[i];
@@ -1164,9 +1145,18 @@ __device__ __forceinline__ void weights_blk(const StepDesc &d, int b)
         double *p = d.part + 4 * (size_t)b;
         p[0] = m; p[1] = S; p[2] = Q; p[3] = (double)am;
     }
-    if (!arrive_last(d.counters, nb)) return;
+}
 
-    // Last block of the session: combine the per-block (max, sums) in block order.
+// One block per session: combine the per-block partials (fixed order) into
+// L = logsumexp(logw), ESS, the representative and the resampling decision.
+__device__ __forceinline__ void wcombine_blk(const StepDesc &d)
+{
+    constexpr int B = kWeightBlock;
+    __shared__ double sh[B];
+    __shared__ int shi[B];
+    const int tid = threadIdx.x;
+    const int N = d.N;
+    const int nb = weight_blocks(N);
     double gm = -INFINITY;
     int gam = INT_MAX;
     for (int bk = tid; bk < nb; bk += B) {
@@ -1208,7 +1198,6 @@ __device__ __forceinline__ void weights_blk(const StepDesc &d, int b)
         }
         const int bb = degenerate ? 0 : gam;
         for (int c = 0; c < 7; ++c) st->best_pose[c] = d.pose[(size_t)c * N + bb];
-        __hip_atomic_store(d.counters, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1216,29 +1205,12 @@ __device__ __forceinline__ void weights_blk(const StepDesc &d, int b)
 // Normalisation and systematic resampling
 // ---------------------------------------------------------------------------
 
-// logw -= L (uniform reset when degenerate); when resampling, the block-local
-// inclusive scan of w = exp(logw) and, in the last block, the exclusive
-// prefix of the block totals.
-__device__ __forceinline__ void normscan_blk(const StepDesc &d, int b)
+// Inclusive scan of one value per thread over the block (Hillis-Steele,
+// double-buffered; fixed order).
+template <int B>
+__device__ __forceinline__ double block_scan(double v, double (*sh)[B])
 {
-    constexpr int B = kWeightBlock;
-    __shared__ double sh[2][B];
     const int tid = threadIdx.x;
-    const int i = b * B + tid;
-    const int N = d.N;
-    const int nb = weight_blocks(N);
-    const StepStatsDev *st = d.stats;
-    const int degenerate = st->degenerate;
-    const int resampled = st->resampled;
-    const double L = st->lse;
-    double lw = -INFINITY;
-    if (i < N) {
-        lw = degenerate ? -log((double)N) : d.logw[i] - L;
-        d.logw[i] = lw;
-    }
-    if (!resampled) return;
-    double v = (i < N) ? exp(lw) : 0.0;
-    // Inclusive scan (Hillis-Steele, double-buffered; fixed order).
     int cur = 0;
     sh[cur][tid] = v;
     __syncthreads();
@@ -1249,32 +1221,57 @@ __device__ __forceinline__ void normscan_blk(const StepDesc &d, int b)
         __syncthreads();
     }
     v = sh[cur][tid];
+    __syncthreads();
+    return v;
+}
+
+// logw -= L (uniform reset when degenerate); when resampling, the block-local
+// inclusive scan of w = exp(logw) and the block total.
+__device__ __forceinline__ void normscan_blk(const StepDesc &d, int b)
+{
+    constexpr int B = kWeightBlock;
+    __shared__ double sh[2][B];
+    const int tid = threadIdx.x;
+    const int i = b * B + tid;
+    const int N = d.N;
+    const StepStatsDev *st = d.stats;
+    const int degenerate = st->degenerate;
+    const int resampled = st->resampled;
+    const double L = st->lse;
+    double lw = -INFINITY;
+    if (i < N) {
+        lw = degenerate ? -log((double)N) : d.logw[i] - L;
+        d.logw[i] = lw;
+    }
+    if (!resampled) return;
+    const double v = block_scan<B>((i < N) ? exp(lw) : 0.0, sh);
     if (i < N) d.cdf_local[i] = v;
     if (tid == B - 1) d.part[b] = v;
-    if (!arrive_last(d.counters + 1, nb)) return;
-    // Exclusive prefix of the block totals: thread t owns a contiguous chunk,
-    // chunk sums are scanned in LDS, then each chunk is written sequentially.
+}
+
+// One block per session: exclusive prefix of the block totals, in place.
+// Thread t owns a contiguous chunk; chunk sums are scanned, then each chunk
+// is rewritten sequentially from the previous chunk's inclusive prefix.
+__device__ __forceinline__ void prefix_blk(const StepDesc &d)
+{
+    constexpr int B = kWeightBlock;
+    __shared__ double sh[2][B];
+    __shared__ double incl[B];
+    if (!d.stats->resampled) return;
+    const int tid = threadIdx.x;
+    const int nb = weight_blocks(d.N);
     const int per = (nb + B - 1) / B;
     const int c0 = min(nb, tid * per), c1 = min(nb, c0 + per);
     double csum = 0.0;
     for (int bk = c0; bk < c1; ++bk) csum += d.part[bk];
-    cur = 0;
-    sh[cur][tid] = csum;
+    incl[tid] = block_scan<B>(csum, sh);
     __syncthreads();
-    for (int off = 1; off < B; off <<= 1) {
-        const double x = sh[cur][tid] + (tid >= off ? sh[cur][tid - off] : 0.0);
-        sh[cur ^ 1][tid] = (tid >= off) ? x : sh[cur][tid];
-        cur ^= 1;
-        __syncthreads();
-    }
-    double off = tid > 0 ? sh[cur][tid - 1] : 0.0;   // exclusive prefix of this chunk
+    double off = tid > 0 ? incl[tid - 1] : 0.0;
     for (int bk = c0; bk < c1; ++bk) {
         const double tot = d.part[bk];
         d.part[bk] = off;
         off += tot;
     }
-    if (tid == 0) __hip_atomic_store(d.counters + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
 }
 
 // a_k = min{i : CDF_i > (u + k)/N} (N - 1 if none) by binary search on
@@ -1315,8 +1312,15 @@ __device__ __forceinline__ void commit_blk(const StepDesc &d, int b)
 // Kernels: one session per launch (grid = that session's blocks)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kWeightBlock) void k_pack(StepDesc d) { pack_blk(d, blockIdx.x); }
-__global__ __launch_bounds__(kWeightBlock) void k_predict(StepDesc d) { predict_blk(d, blockIdx.x); }
+// Blocks [0, scan_blocks(M)) pack the scan; the rest (if any) predict.
+__global__ __launch_bounds__(kWeightBlock) void k_pack_predict(StepDesc d)
+{
+    const int ns = scan_blocks(d.M);
+    if ((int)blockIdx.x < ns)
+        pack_blk(d, blockIdx.x);
+    else
+        predict_blk(d, blockIdx.x - ns);
+}
 
 template <int DT, bool BIG, bool SKIP, int W, int U, bool TX64>
 __global__ __launch_bounds__(64 * W) void k_eval(StepDesc d)
@@ -1331,7 +1335,9 @@ __global__ __launch_bounds__(64 * W) void k_kf_eval(StepDesc d)
 }
 
 __global__ __launch_bounds__(kWeightBlock) void k_weights(StepDesc d) { weights_blk(d, blockIdx.x); }
+__global__ __launch_bounds__(kWeightBlock) void k_wcombine(StepDesc d) { wcombine_blk(d); }
 __global__ __launch_bounds__(kWeightBlock) void k_normscan(StepDesc d) { normscan_blk(d, blockIdx.x); }
+__global__ __launch_bounds__(kWeightBlock) void k_prefix(StepDesc d) { prefix_blk(d); }
 __global__ __launch_bounds__(kWeightBlock) void k_search(StepDesc d) { search_blk(d, blockIdx.x); }
 __global__ __launch_bounds__(kWeightBlock) void k_commit(StepDesc d) { commit_blk(d, blockIdx.x); }
 
@@ -1351,7 +1357,7 @@ __device__ __forceinline__ bool next_item(const BatchTables &t, int kind, int2 &
     const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= t.counts[kind]) return false;
-    const int2 v = t.items[kind][it];
+    const int2 v = t.items[t.offs[kind] + it];
     w.x = __builtin_amdgcn_readfirstlane(v.x);
     w.y = __builtin_amdgcn_readfirstlane(v.y);
     return true;
@@ -1373,7 +1379,9 @@ __global__ void kb_reset(unsigned int *heads)
 __global__ __launch_bounds__(kWeightBlock) void kb_pack(BatchTables t) { MCS_BATCH_LOOP(kPack, pack_blk(d, w.y)) }
 __global__ __launch_bounds__(kWeightBlock) void kb_predict(BatchTables t) { MCS_BATCH_LOOP(kPredict, predict_blk(d, w.y)) }
 __global__ __launch_bounds__(kWeightBlock) void kb_weights(BatchTables t) { MCS_BATCH_LOOP(kWeights, weights_blk(d, w.y)) }
+__global__ __launch_bounds__(kWeightBlock) void kb_wcombine(BatchTables t) { MCS_BATCH_LOOP(kWCombine, wcombine_blk(d)) }
 __global__ __launch_bounds__(kWeightBlock) void kb_normscan(BatchTables t) { MCS_BATCH_LOOP(kNormScan, normscan_blk(d, w.y)) }
+__global__ __launch_bounds__(kWeightBlock) void kb_prefix(BatchTables t) { MCS_BATCH_LOOP(kPrefix, prefix_blk(d)) }
 __global__ __launch_bounds__(kWeightBlock) void kb_search(BatchTables t) { MCS_BATCH_LOOP(kSearch, search_blk(d, w.y)) }
 __global__ __launch_bounds__(kWeightBlock) void kb_commit(BatchTables t) { MCS_BATCH_LOOP(kCommit, commit_blk(d, w.y)) }
 
@@ -1404,10 +1412,8 @@ hipError_t launch_build_cells(const float *grid, void *cells, int nx, int ny, in
 
 hipError_t launch_pack_predict(const StepDesc &d, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pack, dim3(scan_blocks(d.M)), dim3(kWeightBlock), 0, st, d);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !d.predict) return e;
-    hipLaunchKernelGGL(k_predict, dim3(weight_blocks(d.N)), dim3(kWeightBlock), 0, st, d);
+    const int blocks = scan_blocks(d.M) + (d.predict ? weight_blocks(d.N) : 0);
+    hipLaunchKernelGGL(k_pack_predict, dim3(blocks), dim3(kWeightBlock), 0, st, d);
     return hipGetLastError();
 }
 
@@ -1467,6 +1473,9 @@ hipError_t launch_eval(const StepDesc &d, hipStream_t st)
 hipError_t launch_weights(const StepDesc &d, hipStream_t st)
 {
     hipLaunchKernelGGL(k_weights, dim3(weight_blocks(d.N)), dim3(kWeightBlock), 0, st, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wcombine, dim3(1), dim3(kWeightBlock), 0, st, d);
     return hipGetLastError();
 }
 
@@ -1476,6 +1485,8 @@ hipError_t launch_resample(const StepDesc &d, hipStream_t st)
     hipLaunchKernelGGL(k_normscan, dim3(nb), dim3(kWeightBlock), 0, st, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prefix, dim3(1), dim3(kWeightBlock), 0, st, d);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_search, dim3(nb), dim3(kWeightBlock), 0, st, d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_commit, dim3(nb), dim3(kWeightBlock), 0, st, d);
@@ -1485,6 +1496,7 @@ hipError_t launch_resample(const StepDesc &d, hipStream_t st)
 // Persistent grid sizes: enough workgroups to fill 256 CUs several times.
 constexpr unsigned kBatchGridSmall = 2048;
 constexpr unsigned kBatchGridEval = 1280;
+constexpr unsigned kBatchGridOne = 256;     // one-block-per-session stages
 
 template <int DT, bool SKIP>
 static hipError_t launch_batch_dt(const BatchTables &t, hipStream_t st)
@@ -1494,7 +1506,9 @@ static hipError_t launch_batch_dt(const BatchTables &t, hipStream_t st)
     hipLaunchKernelGGL(kb_predict, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL((kb_eval<DT, SKIP, kEvalW, kEvalU>), dim3(kBatchGridEval), dim3(64 * kEvalW), 0, st, t);
     hipLaunchKernelGGL(kb_weights, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
+    hipLaunchKernelGGL(kb_wcombine, dim3(kBatchGridOne), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_normscan, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
+    hipLaunchKernelGGL(kb_prefix, dim3(kBatchGridOne), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_search, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_commit, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     return hipGetLastError();

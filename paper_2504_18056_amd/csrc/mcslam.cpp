@@ -60,11 +60,10 @@ Layout session_layout(int N, int M_max, int K)
         n * 8,                      // 9 logw
         n * 8,                      // 10 cdf_local
         nb * 4 * 8,                 // 11 part
-        2 * sizeof(unsigned int),   // 12 counters
-        n * 4,                      // 13 parents
-        (K > 0 ? (size_t)kMaxNeighbors * n * 4 : 0),  // 14 neighbors
-        sizeof(StepStatsDev),       // 15 stats
-        (size_t)M_max * 32,         // 16 scan8
+        n * 4,                      // 12 parents
+        (K > 0 ? (size_t)kMaxNeighbors * n * 4 : 0),  // 13 neighbors
+        sizeof(StepStatsDev),       // 14 stats
+        (size_t)M_max * 32,         // 15 scan8
     };
     Layout L{};
     size_t o = 0;
@@ -266,7 +265,7 @@ StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float 
     d.kf_pose = s->kf_pose; d.kf_pose_tmp = s->kf_pose_tmp;
     d.loglik = s->loglik; d.grad = s->grad;
     d.logw = s->logw; d.cdf_local = s->cdf_local; d.part = s->part;
-    d.counters = s->counters; d.parents = s->parents; d.neighbors = s->neighbors;
+    d.parents = s->parents; d.neighbors = s->neighbors;
     d.stats = s->stats;
     d.N = s->N; d.M = M;
     d.scan3 = scan3_dev; d.scan4 = s->scan4; d.scan8 = s->scan8;
@@ -537,11 +536,10 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
     ss->logw = (double *)(b + L.off[9]);
     ss->cdf_local = (double *)(b + L.off[10]);
     ss->part = (double *)(b + L.off[11]);
-    ss->counters = (unsigned int *)(b + L.off[12]);
-    ss->parents = (int32_t *)(b + L.off[13]);
-    ss->neighbors = (int32_t *)(b + L.off[14]);
-    ss->stats = (StepStatsDev *)(b + L.off[15]);
-    ss->scan8 = (double4 *)(b + L.off[16]);
+    ss->parents = (int32_t *)(b + L.off[12]);
+    ss->neighbors = (int32_t *)(b + L.off[13]);
+    ss->stats = (StepStatsDev *)(b + L.off[14]);
+    ss->scan8 = (double4 *)(b + L.off[15]);
     e = hipMemsetAsync(ss->block, 0, L.total, ss->stream);
     if (e != hipSuccess) return undo(hip_fail(e, "hipMemset(session)"));
     // Initial state: poses, uniform log-weights, identity parents.

@@ -1,13 +1,20 @@
 // Serving: a request loop that runs the frames of many concurrent sessions.
 //
 // BATCHED mode forms ticks of at most one pending frame per session, writes
-// one table of step descriptors and per-stage work items into pinned host
-// memory, copies it to the device and replays a HIP graph of persistent
-// kernels captured once per table buffer.  Two table buffers alternate so a
-// tick can be prepared and queued while the previous one runs.  SERIAL mode
-// runs one request at a time with the per-session launches and waits for it.
+// one compact table of step descriptors and per-stage work items into pinned
+// host memory, copies it to the device in one transfer and replays a HIP
+// graph of persistent kernels captured once per table buffer.  Two table
+// buffers alternate so a tick can be prepared and queued while the previous
+// one runs.  CONCURRENT mode launches every request as soon as it arrives on
+// its session's own stream, so frames of different sessions overlap on the
+// device without a tick boundary.  SERIAL mode runs one request at a time
+// with the per-session launches and waits for it.
+//
+// A worker thread launches work; a completion thread watches the events of
+// the work in flight and retires requests as soon as their work is done.
 #include "state.h"
 
+#include <array>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -38,16 +45,19 @@ struct Request {
     int64_t evals;
 };
 
-// One table buffer: device tables, their pinned host mirror and the graph
-// that reads them.
+// One table buffer of BATCHED mode.  Device and pinned host images share one
+// layout: a header (per-stage item counts and offsets), max_batch step
+// descriptors, then the work items of all stages packed back to back.  A tick
+// copies the header, the descriptors and the used items in one transfer.  The
+// per-stage pull counters live after the item area and are reset on the
+// device by the graph's first kernel.
 struct TableBuf {
     void *dev = nullptr;
     void *host = nullptr;
-    size_t bytes = 0;
-    StepDesc *descs_d = nullptr, *descs_h = nullptr;
-    int2 *items_d[kNumKinds] = {}, *items_h[kNumKinds] = {};
-    int32_t *counts_d = nullptr, *counts_h = nullptr;
-    unsigned int *heads_d = nullptr;
+    size_t items_off = 0, heads_off = 0, bytes = 0;
+    int32_t *counts_h = nullptr, *offs_h = nullptr;
+    StepDesc *descs_h = nullptr;
+    int2 *items_h = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -57,25 +67,36 @@ struct TableBuf {
     bool busy = false;
 };
 
+// A CONCURRENT-mode request in flight and the event recorded after its work.
+struct InFlight {
+    int64_t id;
+    hipEvent_t ev;
+};
+
+constexpr int kMaxInFlight = 256;
+
 }  // namespace
 
 struct mcs_server {
     mcs_ctx *ctx = nullptr;
     int mode = MCS_SERVE_BATCHED;
     int dtype = 0, oob = 0, max_batch = 1, max_items = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;     // SERIAL mode
     TableBuf buf[2];
     int next_buf = 0;
-    std::thread worker;
+    std::deque<InFlight> inflight;    // CONCURRENT mode, launch order
+    std::vector<hipEvent_t> ev_free;
+    std::vector<hipEvent_t> ev_all;
+    std::thread worker, completer;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_flight, cv_done;
     std::deque<int64_t> pending;
     std::unordered_map<int64_t, Request> reqs;
     int64_t next_id = 1;
     int64_t completed = 0, submitted = 0;
     int64_t ticks = 0, evals = 0;
     int32_t max_batch_seen = 0;
-    bool stop = false;
+    bool stop = false, stop_completer = false;
     mcs_status error = MCS_OK;
     std::string error_msg;
 };
@@ -84,40 +105,37 @@ namespace {
 
 mcs_status alloc_tables(mcs_server *s, TableBuf &b)
 {
+    const size_t n_hdr = align_up(2 * kNumKinds * sizeof(int32_t));
     const size_t n_desc = align_up((size_t)s->max_batch * sizeof(StepDesc));
-    const size_t n_items = align_up((size_t)s->max_items * sizeof(int2));
-    const size_t n_counts = align_up(kNumKinds * sizeof(int32_t));
+    const size_t n_items = align_up((size_t)kNumKinds * s->max_items * sizeof(int2));
     const size_t n_heads = align_up(kNumKinds * sizeof(unsigned int));
-    b.bytes = n_desc + kNumKinds * n_items + n_counts + n_heads;
+    b.items_off = n_hdr + n_desc;
+    b.heads_off = b.items_off + n_items;
+    b.bytes = b.heads_off + n_heads;
     HIP_TRY(hipMalloc(&b.dev, b.bytes), "hipMalloc(server tables)");
-    HIP_TRY(hipHostMalloc(&b.host, b.bytes, hipHostMallocDefault), "hipHostMalloc(server tables)");
+    HIP_TRY(hipHostMalloc(&b.host, b.heads_off, hipHostMallocDefault), "hipHostMalloc(server tables)");
     HIP_TRY(hipMemset(b.dev, 0, b.bytes), "hipMemset(server tables)");
-    std::memset(b.host, 0, b.bytes);
-    char *d = (char *)b.dev, *h = (char *)b.host;
-    size_t o = 0;
-    b.descs_d = (StepDesc *)(d + o); b.descs_h = (StepDesc *)(h + o); o += n_desc;
-    for (int k = 0; k < kNumKinds; ++k) {
-        b.items_d[k] = (int2 *)(d + o);
-        b.items_h[k] = (int2 *)(h + o);
-        o += n_items;
-    }
-    b.counts_d = (int32_t *)(d + o); b.counts_h = (int32_t *)(h + o); o += n_counts;
-    b.heads_d = (unsigned int *)(d + o);
+    std::memset(b.host, 0, b.heads_off);
+    char *h = (char *)b.host;
+    b.counts_h = (int32_t *)h;
+    b.offs_h = b.counts_h + kNumKinds;
+    b.descs_h = (StepDesc *)(h + n_hdr);
+    b.items_h = (int2 *)(h + b.items_off);
     HIP_TRY(hipEventCreateWithFlags(&b.done, hipEventDisableTiming), "hipEventCreate");
     HIP_TRY(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking), "hipStreamCreate");
-    if (s->mode == MCS_SERVE_BATCHED) {
-        BatchTables t{};
-        t.descs = b.descs_d;
-        for (int k = 0; k < kNumKinds; ++k) t.items[k] = b.items_d[k];
-        t.counts = b.counts_d;
-        t.heads = b.heads_d;
-        HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal), "capture begin");
-        hipError_t e = launch_batch(t, s->dtype, s->oob == MCS_OOB_SKIP, b.stream);
-        hipError_t e2 = hipStreamEndCapture(b.stream, &b.graph);
-        if (e != hipSuccess) return hip_fail(e, "capture launch");
-        if (e2 != hipSuccess) return hip_fail(e2, "capture end");
-        HIP_TRY(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-    }
+    char *d = (char *)b.dev;
+    BatchTables t{};
+    t.counts = (const int32_t *)d;
+    t.offs = t.counts + kNumKinds;
+    t.descs = (const StepDesc *)(d + n_hdr);
+    t.items = (const int2 *)(d + b.items_off);
+    t.heads = (unsigned int *)(d + b.heads_off);
+    HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal), "capture begin");
+    hipError_t e = launch_batch(t, s->dtype, s->oob == MCS_OOB_SKIP, b.stream);
+    hipError_t e2 = hipStreamEndCapture(b.stream, &b.graph);
+    if (e != hipSuccess) return hip_fail(e, "capture launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "capture end");
+    HIP_TRY(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
     return MCS_OK;
 }
 
@@ -132,31 +150,23 @@ void free_tables(TableBuf &b)
     b = TableBuf{};
 }
 
-void set_error(mcs_server *s, mcs_status st)
+// Record the first error (s->mu held).
+void set_error_locked(mcs_server *s, mcs_status st, const char *msg)
 {
-    std::lock_guard<std::mutex> lk(s->mu);
     if (s->error == MCS_OK) {
         s->error = st;
-        s->error_msg = mcs_last_error();
+        s->error_msg = msg;
     }
 }
 
-// Mark the requests of a finished tick complete.
-void finish_tick(mcs_server *s, TableBuf &b)
+// Retire one request at time t (s->mu held).
+void retire(mcs_server *s, int64_t id, int64_t t, bool ok)
 {
-    const int64_t t = now_ns();
-    std::lock_guard<std::mutex> lk(s->mu);
-    for (int64_t id : b.reqs) {
-        auto it = s->reqs.find(id);
-        if (it == s->reqs.end()) continue;
-        it->second.t.done_ns = t;
-        s->evals += it->second.evals;
-        s->completed++;
-    }
-    b.reqs.clear();
-    b.sessions.clear();
-    b.busy = false;
-    s->cv_done.notify_all();
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return;
+    it->second.t.done_ns = ok ? t : -1;
+    if (ok) s->evals += it->second.evals;
+    s->completed++;
 }
 
 // Build and launch one tick from the pending queue (mutex held by caller on
@@ -176,78 +186,123 @@ bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b, T
     if (take.empty()) return false;
     std::vector<Request> rq;
     for (int64_t id : take) rq.push_back(s->reqs[id]);
-    lk.unlock();
-    int32_t counts[kNumKinds] = {0};
-    int used = 0;
-    const int64_t t_launch = now_ns();
-    std::vector<int64_t> run;
     // A session still running in the other buffer's tick orders this tick
     // after it; otherwise the two ticks may overlap on the device.
     bool depends = false;
     if (other.busy)
         for (auto &r : rq) depends = depends || other.sessions.count(r.session_id) > 0;
+    lk.unlock();
+    const int64_t t_launch = now_ns();
+    std::vector<std::array<int, kNumKinds>> needs;
+    std::vector<int64_t> run, deferred;
     std::unordered_set<int32_t> tick_sessions;
+    int32_t counts[kNumKinds] = {0};
+    int used = 0;
     for (auto &r : rq) {
         Session *ss = find_session(s->ctx, r.session_id);
-        if (!ss) continue;   // validated at submission; a destroyed session is skipped
+        if (!ss) {
+            run.push_back(r.id);   // validated at submission; a destroyed session is skipped
+            continue;
+        }
         const StepDesc d = make_desc(ss, r.scan, r.M, r.noise, &r.p);
         const int nb = weight_blocks(d.N), nt = particle_tiles(d.N), ns = scan_blocks(d.M);
-        const int need[kNumKinds] = {ns, d.predict ? nb : 0, nt, nb, nb, nb, nb};
+        const std::array<int, kNumKinds> need = {ns, d.predict ? nb : 0, nt, nb, 1, nb, 1, nb, nb};
         bool fits = true;
         for (int k = 0; k < kNumKinds; ++k) fits = fits && counts[k] + need[k] <= s->max_items;
         if (!fits) {
-            // Too much work for one tick's lists: run it in a later tick.
-            std::lock_guard<std::mutex> g(s->mu);
-            s->pending.push_front(r.id);
+            deferred.push_back(r.id);   // too much work for one tick's lists: a later tick
             continue;
         }
-        b.descs_h[used] = d;
-        for (int k = 0; k < kNumKinds; ++k)
-            for (int q = 0; q < need[k]; ++q) b.items_h[k][counts[k]++] = make_int2(used, q);
-        ++used;
+        for (int k = 0; k < kNumKinds; ++k) counts[k] += need[k];
+        b.descs_h[used++] = d;
+        needs.push_back(need);
         run.push_back(r.id);
         tick_sessions.insert(r.session_id);
     }
-    for (int k = 0; k < kNumKinds; ++k) b.counts_h[k] = counts[k];
     hipError_t e = hipSuccess;
     if (used > 0) {
+        // Stage k's items start at offs[k]; an item is (descriptor, block).
+        int total = 0;
+        for (int k = 0; k < kNumKinds; ++k) {
+            b.counts_h[k] = counts[k];
+            b.offs_h[k] = total;
+            total += counts[k];
+        }
+        int fill[kNumKinds];
+        for (int k = 0; k < kNumKinds; ++k) fill[k] = b.offs_h[k];
+        for (int q = 0; q < used; ++q)
+            for (int k = 0; k < kNumKinds; ++k)
+                for (int blk = 0; blk < needs[q][k]; ++blk) b.items_h[fill[k]++] = make_int2(q, blk);
         if (depends) e = hipStreamWaitEvent(b.stream, other.done, 0);
-        // Copy only the used parts of the tables.
         if (e == hipSuccess)
-            e = hipMemcpyAsync(b.descs_d, b.descs_h, used * sizeof(StepDesc), hipMemcpyHostToDevice,
-                               b.stream);
-        for (int k = 0; k < kNumKinds && e == hipSuccess; ++k)
-            if (counts[k] > 0)
-                e = hipMemcpyAsync(b.items_d[k], b.items_h[k], counts[k] * sizeof(int2),
-                                   hipMemcpyHostToDevice, b.stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b.counts_d, b.counts_h, kNumKinds * sizeof(int32_t),
+            e = hipMemcpyAsync(b.dev, b.host, b.items_off + (size_t)total * sizeof(int2),
                                hipMemcpyHostToDevice, b.stream);
         if (e == hipSuccess) e = hipGraphLaunch(b.exec, b.stream);
         if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
     }
     lk.lock();
+    for (auto it = deferred.rbegin(); it != deferred.rend(); ++it) s->pending.push_front(*it);
     if (e != hipSuccess) {
-        lk.unlock();
-        set_error(s, hip_fail(e, "server tick"));
-        lk.lock();
+        const mcs_status fs = hip_fail(e, "server tick");
+        set_error_locked(s, fs, mcs_last_error());
         // Fail the tick's requests so waiters do not hang.
-        for (int64_t id : run) s->reqs[id].t.done_ns = -1, s->completed++;
+        for (int64_t id : run) retire(s, id, 0, false);
         s->cv_done.notify_all();
         return false;
     }
-    if (used == 0) return false;
+    const int64_t t_now = now_ns();
     for (int64_t id : run) {
         Request &r = s->reqs[id];
         r.t.launch_ns = t_launch;
         r.t.tick = (int32_t)s->ticks;
+        if (used == 0) retire(s, id, t_now, true);   // only skipped sessions
+    }
+    if (used == 0) {
+        s->cv_done.notify_all();
+        return false;
     }
     b.reqs = run;
     b.sessions = tick_sessions;
     b.busy = true;
     s->ticks++;
     if (used > s->max_batch_seen) s->max_batch_seen = used;
+    s->cv_flight.notify_all();
     return true;
+}
+
+// CONCURRENT mode: launch the oldest pending request on its session's stream.
+void launch_concurrent(mcs_server *s, std::unique_lock<std::mutex> &lk)
+{
+    const int64_t id = s->pending.front();
+    s->pending.pop_front();
+    const Request r = s->reqs[id];
+    hipEvent_t ev = s->ev_free.back();
+    s->ev_free.pop_back();
+    lk.unlock();
+    const int64_t t0 = now_ns();
+    mcs_status st = MCS_OK;
+    Session *ss = find_session(s->ctx, r.session_id);
+    if (ss) {
+        st = enqueue_step(ss, r.scan, r.M, r.noise, &r.p, ss->stream);
+        if (st == MCS_OK) {
+            const hipError_t e = hipEventRecord(ev, ss->stream);
+            if (e != hipSuccess) st = hip_fail(e, "event record");
+        }
+    }
+    lk.lock();
+    Request &rr = s->reqs[id];
+    rr.t.launch_ns = t0;
+    rr.t.tick = (int32_t)s->ticks++;
+    if (!ss || st != MCS_OK) {
+        if (st != MCS_OK) set_error_locked(s, st, mcs_last_error());
+        s->ev_free.push_back(ev);
+        retire(s, id, now_ns(), false);
+        s->cv_done.notify_all();
+        return;
+    }
+    s->inflight.push_back(InFlight{id, ev});
+    if ((int32_t)s->inflight.size() > s->max_batch_seen) s->max_batch_seen = (int32_t)s->inflight.size();
+    s->cv_flight.notify_all();
 }
 
 void run_serial(mcs_server *s, std::unique_lock<std::mutex> &lk)
@@ -267,16 +322,22 @@ void run_serial(mcs_server *s, std::unique_lock<std::mutex> &lk)
         }
     }
     const int64_t t1 = now_ns();
-    if (st != MCS_OK) set_error(s, st);
     lk.lock();
+    if (st != MCS_OK) set_error_locked(s, st, mcs_last_error());
     Request &rr = s->reqs[id];
     rr.t.launch_ns = t0;
-    rr.t.done_ns = st == MCS_OK ? t1 : -1;
     rr.t.tick = (int32_t)s->ticks++;
-    s->evals += st == MCS_OK ? rr.evals : 0;
-    s->completed++;
+    retire(s, id, t1, st == MCS_OK);
     if (s->max_batch_seen < 1) s->max_batch_seen = 1;
     s->cv_done.notify_all();
+}
+
+bool can_launch(const mcs_server *s)
+{
+    if (s->pending.empty()) return false;
+    if (s->mode == MCS_SERVE_BATCHED) return !s->buf[s->next_buf].busy;
+    if (s->mode == MCS_SERVE_CONCURRENT) return !s->ev_free.empty();
+    return true;
 }
 
 void worker_main(mcs_server *s)
@@ -284,42 +345,93 @@ void worker_main(mcs_server *s)
     (void)hipSetDevice(s->ctx->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        if (s->mode == MCS_SERVE_SERIAL) {
-            if (s->pending.empty()) {
-                if (s->stop) break;
-                s->cv_work.wait(lk);
-                continue;
-            }
-            run_serial(s, lk);
+        if (!can_launch(s)) {
+            if (s->stop && s->pending.empty()) break;
+            s->cv_work.wait(lk);
             continue;
         }
-        // Retire finished ticks without blocking.
-        for (auto &b : s->buf) {
-            if (!b.busy) continue;
-            const hipError_t q = hipEventQuery(b.done);
-            if (q == hipErrorNotReady) continue;
-            if (q != hipSuccess) set_error(s, hip_fail(q, "server tick"));
-            lk.unlock();
-            finish_tick(s, b);
-            lk.lock();
-        }
-        // Queue a tick into a free buffer (ticks alternate between the two).
-        bool launched = false;
-        TableBuf &nb = s->buf[s->next_buf];
-        if (!nb.busy && !s->pending.empty()) {
-            launched = launch_tick(s, lk, nb, s->buf[s->next_buf ^ 1]);
-            if (launched) s->next_buf ^= 1;
-        }
-        if (launched) continue;
-        const bool any_busy = s->buf[0].busy || s->buf[1].busy;
-        if (!any_busy && s->pending.empty()) {
-            if (s->stop) break;
-            s->cv_work.wait(lk);
+        if (s->mode == MCS_SERVE_SERIAL) {
+            run_serial(s, lk);
+        } else if (s->mode == MCS_SERVE_CONCURRENT) {
+            launch_concurrent(s, lk);
         } else {
-            // Work in flight: wake on a new submission or after a short poll interval.
-            s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+            TableBuf &nb = s->buf[s->next_buf];
+            if (launch_tick(s, lk, nb, s->buf[s->next_buf ^ 1])) s->next_buf ^= 1;
         }
     }
+}
+
+// Watches the work in flight without sleeping and retires each request as
+// soon as its event has completed.
+void completer_main(mcs_server *s)
+{
+    (void)hipSetDevice(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        const bool any = s->buf[0].busy || s->buf[1].busy || !s->inflight.empty();
+        if (!any) {
+            if (s->stop_completer) break;
+            s->cv_flight.wait(lk);
+            continue;
+        }
+        // Snapshot the events to query: buffers k >= 0, in-flight entries -1 - k.
+        std::vector<std::pair<int, hipEvent_t>> q;
+        for (int k = 0; k < 2; ++k)
+            if (s->buf[k].busy) q.emplace_back(k, s->buf[k].done);
+        for (size_t k = 0; k < s->inflight.size(); ++k) q.emplace_back(-1 - (int)k, s->inflight[k].ev);
+        lk.unlock();
+        std::vector<std::pair<int, hipError_t>> ready;
+        for (auto &x : q) {
+            const hipError_t e = hipEventQuery(x.second);
+            if (e != hipErrorNotReady) ready.emplace_back(x.first, e);
+        }
+        const int64_t t = now_ns();
+        if (ready.empty()) {
+            std::this_thread::yield();
+            lk.lock();
+            continue;
+        }
+        lk.lock();
+        std::vector<bool> gone(s->inflight.size(), false);
+        bool any_gone = false;
+        for (auto &x : ready) {
+            const bool ok = x.second == hipSuccess;
+            if (!ok) {
+                const mcs_status fs = hip_fail(x.second, "server work");
+                set_error_locked(s, fs, mcs_last_error());
+            }
+            if (x.first >= 0) {
+                TableBuf &b = s->buf[x.first];
+                for (int64_t id : b.reqs) retire(s, id, t, ok);
+                b.reqs.clear();
+                b.sessions.clear();
+                b.busy = false;
+            } else {
+                // Only this thread removes entries, so the snapshot's indices still hold.
+                const size_t k = (size_t)(-1 - x.first);
+                retire(s, s->inflight[k].id, t, ok);
+                s->ev_free.push_back(s->inflight[k].ev);
+                gone[k] = true;
+                any_gone = true;
+            }
+        }
+        if (any_gone) {
+            std::deque<InFlight> keep;
+            for (size_t k = 0; k < s->inflight.size(); ++k)
+                if (k >= gone.size() || !gone[k]) keep.push_back(s->inflight[k]);
+            s->inflight.swap(keep);
+        }
+        s->cv_work.notify_all();
+        s->cv_done.notify_all();
+    }
+}
+
+void destroy_server(mcs_server *s)
+{
+    for (auto &b : s->buf) free_tables(b);
+    for (hipEvent_t e : s->ev_all) (void)hipEventDestroy(e);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
 }
 
 }  // namespace
@@ -331,11 +443,12 @@ mcs_status mcs_server_create(mcs_ctx *ctx, int32_t mode, int32_t dtype, int32_t 
 {
     if (!ctx || !out) return fail(MCS_EINVAL, "NULL argument");
     *out = nullptr;
-    if (mode != MCS_SERVE_BATCHED && mode != MCS_SERVE_SERIAL) return fail(MCS_EINVAL, "bad mode");
+    if (mode != MCS_SERVE_BATCHED && mode != MCS_SERVE_SERIAL && mode != MCS_SERVE_CONCURRENT)
+        return fail(MCS_EINVAL, "bad mode");
     if (dtype < MCS_GRID_FP32 || dtype > MCS_GRID_BF16) return fail(MCS_EINVAL, "bad dtype");
     if (oob != MCS_OOB_FLOOR && oob != MCS_OOB_SKIP) return fail(MCS_EINVAL, "bad oob");
     if (max_batch < 1 || max_batch > 4096) return fail(MCS_EINVAL, "max_batch outside [1, 4096]");
-    if (max_items < 0) return fail(MCS_EINVAL, "max_items < 0");
+    if (max_items < 0 || max_items > (1 << 24)) return fail(MCS_EINVAL, "max_items outside [0, 2^24]");
     mcs_status st = set_device(ctx);
     if (st != MCS_OK) return st;
     mcs_server *s = new mcs_server;
@@ -347,18 +460,30 @@ mcs_status mcs_server_create(mcs_ctx *ctx, int32_t mode, int32_t dtype, int32_t 
     s->max_items = max_items > 0 ? max_items : 262144;
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        delete s;
+        s->stream = nullptr;
+        destroy_server(s);
         return hip_fail(e, "hipStreamCreate");
     }
-    for (auto &b : s->buf) {
-        if ((st = alloc_tables(s, b)) != MCS_OK) {
-            for (auto &bb : s->buf) free_tables(bb);
-            (void)hipStreamDestroy(s->stream);
-            delete s;
-            return st;
+    if (mode == MCS_SERVE_BATCHED) {
+        for (auto &b : s->buf) {
+            if ((st = alloc_tables(s, b)) != MCS_OK) {
+                destroy_server(s);
+                return st;
+            }
+        }
+    } else if (mode == MCS_SERVE_CONCURRENT) {
+        for (int k = 0; k < kMaxInFlight; ++k) {
+            hipEvent_t ev;
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
+                destroy_server(s);
+                return hip_fail(e, "hipEventCreate");
+            }
+            s->ev_all.push_back(ev);
+            s->ev_free.push_back(ev);
         }
     }
     s->worker = std::thread(worker_main, s);
+    s->completer = std::thread(completer_main, s);
     *out = s;
     return MCS_OK;
 }
@@ -383,11 +508,15 @@ mcs_status mcs_server_destroy(mcs_server *s)
         s->cv_work.notify_all();
     }
     s->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop_completer = true;
+        s->cv_flight.notify_all();
+    }
+    s->completer.join();
     (void)hipSetDevice(s->ctx->device);
     (void)hipDeviceSynchronize();
-    for (auto &b : s->buf) free_tables(b);
-    (void)hipStreamDestroy(s->stream);
-    delete s;
+    destroy_server(s);
     return MCS_OK;
 }
 
@@ -405,7 +534,8 @@ mcs_status mcs_server_submit(mcs_server *s, int32_t sid, const float *scan_dev, 
         return fail(MCS_EINVAL, "out-of-grid rule differs from the server's");
     StepDesc probe = make_desc(ss, scan_dev, M, noise_dev, p);
     if (!eval_supported(probe)) return fail(MCS_EINVAL, "map not supported");
-    if (weight_blocks(ss->N) > s->max_items || scan_blocks(M) > s->max_items)
+    if (particle_tiles(ss->N) > s->max_items || weight_blocks(ss->N) > s->max_items ||
+        scan_blocks(M) > s->max_items)
         return fail(MCS_EINVAL, "session work exceeds the server's per-tick work lists");
     Request r{};
     r.session_id = sid;

@@ -51,7 +51,6 @@ struct Session {
     float4 *scan4 = nullptr;
     double4 *scan8 = nullptr;
     double *logw = nullptr, *cdf_local = nullptr, *part = nullptr;
-    unsigned int *counters = nullptr;
     int32_t *parents = nullptr, *neighbors = nullptr;
     StepStatsDev *stats = nullptr;
     float *pinned = nullptr;         // host staging for host-pointer steps
