@@ -85,6 +85,22 @@ typedef struct {
 #define MCS_RESAMPLE_NEVER  0
 #define MCS_RESAMPLE_ALWAYS 1
 #define MCS_RESAMPLE_ESS    2   /* when ESS < ess_frac * N (strict) */
+/* Dead-particle pruning (Sec. III-F) instead of resampling: a particle is dead
+ * when its normalised weight is below prune_post or its likelihood relative
+ * to the frame's best, exp(l_i - max l), is below prune_lik.  Each dead slot,
+ * in index order, receives a copy (pose and keyframe poses) of a live
+ * particle drawn systematically with offset u from the live weights; a
+ * parent's weight is shared equally with its copies and the live mass is
+ * renormalised.  Live particles keep their state and relative weights. */
+#define MCS_RESAMPLE_PRUNE  3
+
+/* Prediction noise: from the noise pointer (or none), or drawn on the device
+ * (Eq. 1) from a counter-based SplitMix64 stream with Box-Muller normals:
+ * the stream of frame f is keyed by the f-th output of SplitMix64(rng_seed);
+ * particle i takes its uniforms 6i .. 6i+5, U = (x >> 11) 2^-53, in pairs
+ * (U_a, U_b) -> sqrt(-2 ln(1 - U_a)) (cos, sin)(2 pi U_b); delta_c = sigma_c z_c. */
+#define MCS_NOISE_INPUT  0
+#define MCS_NOISE_DEVICE 1
 
 /* Points outside the grid: ln(eps) (FLOOR) or no contribution (SKIP). */
 #define MCS_OOB_FLOOR 0
@@ -126,6 +142,12 @@ typedef struct {
     int32_t n_recent;       /* MCS_KF_LOOP: the newest n_recent keyframes are not old
                                (with n_recent < n_neighbors every particle loops;
                                n_recent = n_neighbors is the natural choice) */
+    int32_t noise_mode;     /* MCS_NOISE_* (used when predict is set) */
+    uint64_t rng_seed;      /* MCS_NOISE_DEVICE: stream seed */
+    uint64_t rng_frame;     /* MCS_NOISE_DEVICE: frame counter */
+    float noise_sigma[6];   /* MCS_NOISE_DEVICE: standard deviations [rho (m); phi (rad)] */
+    float prune_post;       /* MCS_RESAMPLE_PRUNE: weight threshold (e.g. 1e-8), > 0 */
+    float prune_lik;        /* MCS_RESAMPLE_PRUNE: likelihood-ratio threshold (e.g. 1e-16), > 0 */
 } mcs_step_params;
 
 typedef struct {
@@ -135,7 +157,7 @@ typedef struct {
     int32_t best;           /* index (before resampling) of the largest weight, lowest on ties */
     float best_pose[7];     /* that particle's pose after the step (the representative) */
     int32_t degenerate;     /* 1 when no log-weight was finite: weights reset to uniform */
-    int32_t pad;
+    int32_t pruned;         /* MCS_RESAMPLE_PRUNE: dead particles respawned in this step */
 } mcs_step_stats;
 
 /* Library version string. */

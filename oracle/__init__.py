@@ -73,6 +73,12 @@ def lib():
         L.oracle_predict_rng.restype = i32
         L.oracle_prune.argtypes = [_dp, _dp, i32, f64, f64, f64, _ip, _dp, C.POINTER(i32), _opt("d")]
         L.oracle_prune.restype = i32
+        L.oracle_gicp_eval.argtypes = [_fp, i32, i32, i32, i32, _dp, f64, _fp, _fp, i32, _fp, _fp, i32,
+                                       i32, f64, _dp, _dp, _dp, _opt("d"), _opt("d"), _opt("i"),
+                                       _opt("i"), _opt("i"), i32]
+        L.oracle_gicp_eval.restype = i32
+        L.oracle_gn_step.argtypes = [_fp, _dp, _dp, i32, f64, f64, _dp, _opt("d")]
+        L.oracle_gn_step.restype = i32
         L.oracle_kf_loop_update.argtypes = [_fp, _fp, _dp, _ip, i32, i32, i32, i32, f64, f64, f64,
                                             f64, _dp, _dp, _ip, _opt("d")]
         L.oracle_kf_loop_update.restype = i32
@@ -267,6 +273,40 @@ def prune(logw, loglik, tau_post, tau_lik, u):
     _check(lib().oracle_prune(logw, _f64(loglik).reshape(-1), N, float(tau_post), float(tau_lik),
                               float(u), par, lw, C.byref(nd), mg), "oracle_prune")
     return dict(parents=par, logw=lw, n_dead=nd.value, margin=mg)
+
+
+def gicp_evaluate(vox, dims, origins, vs, mu, cov, poses, kf_poses, n_nb=4, delta=0.0, nthreads=0):
+    """GICP likelihood (Eq. 2-4) over the n_nb nearest keyframes with voxel
+    correspondences, and the Gauss-Newton system of Eq. 6: H (N, 21) upper
+    triangle row-major, b (N, 6).  vox (K, nz, ny, nx, 12) voxel Gaussians in
+    each keyframe's frame, origins (K, 3), voxel edge vs; scan means mu (M, 3)
+    and covariances cov (M, 6: xx xy xz yy yz zz)."""
+    nx, ny, nz = (int(v) for v in dims)
+    v = _f32(vox).reshape(-1)
+    K = v.size // (nx * ny * nz * 12)
+    mu = _f32(mu).reshape(-1, 3)
+    cov = _f32(cov).reshape(-1, 6)
+    poses = _f32(poses).reshape(-1, 7)
+    N = poses.shape[0]
+    kf = _f32(kf_poses).reshape(N, K, 7)
+    ll, H, b = np.empty(N), np.empty((N, 21)), np.empty((N, 6))
+    ha, ba = np.empty((N, 21)), np.empty((N, 6))
+    nb = np.empty((N, n_nb), np.int32)
+    nc, na = np.empty(N, np.int32), np.empty(N, np.int32)
+    _check(lib().oracle_gicp_eval(v, K, nx, ny, nz, _f64(origins).reshape(-1), float(vs), mu, cov,
+                                  mu.shape[0], poses, kf, N, int(n_nb), float(delta), ll, H, b, ha, ba,
+                                  nb, nc, na, int(nthreads)), "oracle_gicp_eval")
+    return dict(loglik=ll, H=H, b=b, habs=ha, babs=ba, neighbors=nb, n_corr=nc, n_amb=na)
+
+
+def gn_step(poses, H, b, rho_max, phi_max):
+    """Gauss-Newton step psi = -H^-1 b (Eq. 5), clamped, T <- T Exp(psi) (Eq. 7)."""
+    poses = _f32(poses).reshape(-1, 7)
+    N = poses.shape[0]
+    out, psi = np.empty((N, 7)), np.empty((N, 6))
+    _check(lib().oracle_gn_step(poses, _f64(H).reshape(-1), _f64(b).reshape(-1), N, float(rho_max),
+                                float(phi_max), out, psi), "oracle_gn_step")
+    return out, psi
 
 
 def kf_loop_update(poses, kf_poses, grad, neighbors, params, n_recent=3):

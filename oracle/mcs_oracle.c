@@ -937,6 +937,268 @@ int oracle_kf_loop_update(const float *poses, const float *kf_poses, const doubl
 }
 
 /* ------------------------------------------------------------------------ */
+/* GICP likelihood and Gauss-Newton step (Sec. III-C, Eq. 2-7)                */
+/* ------------------------------------------------------------------------ */
+
+/* A keyframe voxel map: nx*ny*nz voxels of edge vs, voxel (i, j, k) covering
+ * [o + (i, j, k) vs, o + (i+1, j+1, k+1) vs) in the keyframe's frame, x
+ * fastest.  Each voxel holds 12 floats: mean (3), point count, covariance
+ * (xx xy xz yy yz zz), 2 unused.  A voxel with count 0 is empty. */
+typedef struct {
+    const float *vox;
+    int nx, ny, nz;
+    double o[3];
+    double vs;
+} voxmap_t;
+
+/* The voxel holding x: 1 and its Gaussian, or 0 when x is outside the map or
+ * the voxel is empty.  *amb is set when a coordinate lies within delta voxels
+ * of a face (the voxel choice is then a near-tie between two voxels). */
+static int vox_lookup(const voxmap_t *m, const double x[3], double delta, double mu[3],
+                      double S[6], int *amb)
+{
+    const int n[3] = {m->nx, m->ny, m->nz};
+    int i[3];
+    for (int a = 0; a < 3; ++a) {
+        const double u = (x[a] - m->o[a]) / m->vs;
+        const double f = floor(u);
+        if (u - f < delta || f + 1.0 - u < delta) *amb = 1;
+        if (!(f >= 0.0 && f < (double)n[a])) return 0;
+        i[a] = (int)f;
+    }
+    const float *r = m->vox + 12 * ((size_t)i[0] + (size_t)m->nx * ((size_t)i[1] + (size_t)m->ny * i[2]));
+    if (!(r[3] > 0.0f)) return 0;
+    for (int a = 0; a < 3; ++a) mu[a] = r[a];
+    for (int a = 0; a < 6; ++a) S[a] = r[4 + a];
+    return 1;
+}
+
+/* Symmetric 3x3 (xx xy xz yy yz zz) to full and back. */
+static void sym_full(const double s[6], double F[9])
+{
+    F[0] = s[0]; F[1] = s[1]; F[2] = s[2];
+    F[3] = s[1]; F[4] = s[3]; F[5] = s[4];
+    F[6] = s[2]; F[7] = s[4]; F[8] = s[5];
+}
+
+/* Inverse of a symmetric positive definite 3x3 by the adjugate. */
+static int inv3(const double A[9], double I[9])
+{
+    const double c00 = A[4] * A[8] - A[5] * A[7];
+    const double c01 = A[5] * A[6] - A[3] * A[8];
+    const double c02 = A[3] * A[7] - A[4] * A[6];
+    const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    if (!(det > 0.0)) return 0;
+    const double id = 1.0 / det;
+    I[0] = c00 * id; I[1] = (A[2] * A[7] - A[1] * A[8]) * id; I[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+    I[3] = c01 * id; I[4] = (A[0] * A[8] - A[2] * A[6]) * id; I[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+    I[6] = c02 * id; I[7] = (A[1] * A[6] - A[0] * A[7]) * id; I[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+    return 1;
+}
+
+/* Index of H[r][c] (r <= c) in the 21-entry upper triangle, row-major. */
+static int tri(int r, int c) { return r * 6 - r * (r - 1) / 2 + (c - r); }
+
+typedef struct {
+    double ll, H[21], b[6], habs[21], babs[6];
+    int n_corr, n_amb;
+} gicp_out;
+
+/* Terms of the scan against one keyframe under the relative pose (R', t')
+ * = T_k^-1 T (Eq. 4), accumulated into o.  With x = R' mu + t' and the
+ * voxel Gaussian (mu', S') of x, the residual e = mu' - x and
+ * Omega = (S' + R' Sigma R'^T)^-1 (Eq. 4; rotation only) are taken in the
+ * scan's frame: e_s = R'^T e, Omega_s = R'^T Omega R' = (R'^T S' R' + Sigma)^-1.
+ * Per point: l += -e^T Omega e, and with the Jacobian of e under T Exp(xi),
+ * J_s = [-I, [mu]x], H += J_s^T Omega_s J_s and b += J_s^T Omega_s e_s
+ * (Eq. 6). */
+static void gicp_terms(const voxmap_t *m, const double R[9], const double t[3], const float *mu_s,
+                       const float *cov_s, int M, double delta, gicp_out *o)
+{
+    for (int j = 0; j < M; ++j) {
+        const double p[3] = {mu_s[3 * j], mu_s[3 * j + 1], mu_s[3 * j + 2]};
+        double x[3], mv[3], Sv[6];
+        mat3_vec(R, p, x);
+        for (int a = 0; a < 3; ++a) x[a] += t[a];
+        int amb = 0;
+        const int hit = vox_lookup(m, x, delta, mv, Sv, &amb);
+        o->n_amb += amb;
+        if (!hit) continue;
+        double d[3], es[3], Sf[9], T1[9], Ss[9], C[9], Om[9];
+        for (int a = 0; a < 3; ++a) d[a] = mv[a] - t[a];
+        mat3T_vec(R, d, es);
+        for (int a = 0; a < 3; ++a) es[a] -= p[a];
+        sym_full(Sv, Sf);
+        /* Ss = R^T Sf R */
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += Sf[3 * r + k] * R[3 * k + c];
+                T1[3 * r + c] = acc;
+            }
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += R[3 * k + r] * T1[3 * k + c];
+                Ss[3 * r + c] = acc;
+            }
+        double Cs[6] = {cov_s[6 * j], cov_s[6 * j + 1], cov_s[6 * j + 2],
+                        cov_s[6 * j + 3], cov_s[6 * j + 4], cov_s[6 * j + 5]};
+        double Cf[9];
+        sym_full(Cs, Cf);
+        for (int a = 0; a < 9; ++a) C[a] = Ss[a] + Cf[a];
+        if (!inv3(C, Om)) continue;
+        double w[3];
+        mat3_vec(Om, es, w);
+        const double q = es[0] * w[0] + es[1] * w[1] + es[2] * w[2];
+        o->ll -= q;
+        o->n_corr++;
+        /* J_s = [-I, [p]x]: column c of [p]x is p x e_c. */
+        double J[3][6];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) J[r][c] = (r == c) ? -1.0 : 0.0;
+        const double K[9] = {0.0, -p[2], p[1], p[2], 0.0, -p[0], -p[1], p[0], 0.0};
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) J[r][3 + c] = K[3 * r + c];
+        double OJ[3][6];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 6; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += Om[3 * r + k] * J[k][c];
+                OJ[r][c] = acc;
+            }
+        for (int r = 0; r < 6; ++r) {
+            double bb = 0.0;
+            for (int k = 0; k < 3; ++k) bb += J[k][r] * w[k];
+            o->b[r] += bb;
+            o->babs[r] += fabs(bb);
+            for (int c = r; c < 6; ++c) {
+                double hh = 0.0;
+                for (int k = 0; k < 3; ++k) hh += J[k][r] * OJ[k][c];
+                o->H[tri(r, c)] += hh;
+                o->habs[tri(r, c)] += fabs(hh);
+            }
+        }
+    }
+}
+
+/* GICP likelihood (Eq. 2-4) of each particle summed over its n_nb neighbour
+ * keyframes (chosen as for the grid likelihood), with the Gauss-Newton
+ * system H (21, upper triangle row-major) and b (6) of Eq. 6.  vox holds the
+ * K voxel maps back to back (each nx*ny*nz*12 floats), origins (K, 3) in each
+ * keyframe's frame; scan means (M, 3) and covariances (M, 6).  n_corr counts
+ * the points with a correspondence, n_amb those within delta of a voxel face. */
+int oracle_gicp_eval(const float *vox, int K, int nx, int ny, int nz, const double *origins,
+                     double vs, const float *mu, const float *cov, int M, const float *poses,
+                     const float *kf_poses, int N, int n_nb, double delta, double *loglik,
+                     double *H, double *b, double *habs, double *babs, int *neighbors, int *n_corr,
+                     int *n_amb, int nthreads)
+{
+    if (K <= 0 || n_nb <= 0 || n_nb > K || N < 0 || M < 0) return -1;
+    const size_t vsz = (size_t)nx * ny * nz * 12;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < N; ++i) {
+        double pose[7], R[9];
+        pose_from_float(poses + 7 * (size_t)i, pose);
+        double qq[4] = {pose[3], pose[4], pose[5], pose[6]};
+        quat_to_rot(qq, R);
+        const float *kf = kf_poses + (size_t)7 * K * i;
+        int nb[64];
+        int *nbp = (n_nb <= 64) ? nb : (int *)malloc(sizeof(int) * (size_t)n_nb);
+        select_neighbors(poses + 7 * (size_t)i, kf, K, n_nb, nbp);
+        gicp_out o;
+        memset(&o, 0, sizeof o);
+        for (int s = 0; s < n_nb; ++s) {
+            const int k = nbp[s];
+            if (neighbors) neighbors[(size_t)n_nb * i + s] = k;
+            double kp[7], Rk[9], Rr[9], dt[3], tr[3];
+            pose_from_float(kf + 7 * (size_t)k, kp);
+            double qk[4] = {kp[3], kp[4], kp[5], kp[6]};
+            quat_to_rot(qk, Rk);
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    double acc = 0.0;
+                    for (int m2 = 0; m2 < 3; ++m2) acc += Rk[3 * m2 + r] * R[3 * m2 + c];
+                    Rr[3 * r + c] = acc;
+                }
+            for (int a = 0; a < 3; ++a) dt[a] = pose[a] - kp[a];
+            mat3T_vec(Rk, dt, tr);
+            voxmap_t m;
+            m.vox = vox + vsz * (size_t)k;
+            m.nx = nx; m.ny = ny; m.nz = nz;
+            for (int a = 0; a < 3; ++a) m.o[a] = origins[3 * (size_t)k + a];
+            m.vs = vs;
+            gicp_terms(&m, Rr, tr, mu, cov, M, delta, &o);
+        }
+        loglik[i] = o.ll;
+        for (int c = 0; c < 21; ++c) H[21 * (size_t)i + c] = o.H[c];
+        for (int c = 0; c < 6; ++c) b[6 * (size_t)i + c] = o.b[c];
+        if (habs) for (int c = 0; c < 21; ++c) habs[21 * (size_t)i + c] = o.habs[c];
+        if (babs) for (int c = 0; c < 6; ++c) babs[6 * (size_t)i + c] = o.babs[c];
+        if (n_corr) n_corr[i] = o.n_corr;
+        if (n_amb) n_amb[i] = o.n_amb;
+        if (nbp != nb) free(nbp);
+    }
+    return 0;
+}
+
+/* Gauss-Newton step (Eq. 5 and 7): psi = -H^-1 b minimises the quadratic
+ * model of sum e^T Omega e (with J the derivative of e, the paper's
+ * psi = H^-1 b holds for J taken as -de/dT).  H is solved by Cholesky; when
+ * it is not positive definite (pivot <= 1e-12 of its largest diagonal entry)
+ * the pose is left as it is.  Each block of psi is clamped as for the
+ * gradient step, then T <- T Exp(psi).  Outputs poses (N, 7) and psi (N, 6). */
+int oracle_gn_step(const float *poses, const double *H, const double *b, int N, double rho_max,
+                   double phi_max, double *out, double *psi_out)
+{
+    if (N < 0) return -1;
+    for (int i = 0; i < N; ++i) {
+        double pose[7], A[6][6], L[6][6], y[6], x[6];
+        pose_from_float(poses + 7 * (size_t)i, pose);
+        const double *h = H + 21 * (size_t)i;
+        double dmax = 0.0;
+        for (int r = 0; r < 6; ++r)
+            for (int c = r; c < 6; ++c) A[r][c] = A[c][r] = h[tri(r, c)];
+        for (int r = 0; r < 6; ++r) if (A[r][r] > dmax) dmax = A[r][r];
+        int ok = dmax > 0.0;
+        memset(L, 0, sizeof L);
+        for (int c = 0; c < 6 && ok; ++c) {
+            double sdiag = A[c][c];
+            for (int k = 0; k < c; ++k) sdiag -= L[c][k] * L[c][k];
+            if (!(sdiag > 1e-12 * dmax)) { ok = 0; break; }
+            L[c][c] = sqrt(sdiag);
+            for (int r = c + 1; r < 6; ++r) {
+                double sv = A[r][c];
+                for (int k = 0; k < c; ++k) sv -= L[r][k] * L[c][k];
+                L[r][c] = sv / L[c][c];
+            }
+        }
+        double ps[6] = {0, 0, 0, 0, 0, 0};
+        if (ok) {
+            for (int r = 0; r < 6; ++r) {
+                double sv = -b[6 * (size_t)i + r];
+                for (int k = 0; k < r; ++k) sv -= L[r][k] * y[k];
+                y[r] = sv / L[r][r];
+            }
+            for (int r = 5; r >= 0; --r) {
+                double sv = y[r];
+                for (int k = r + 1; k < 6; ++k) sv -= L[k][r] * x[k];
+                x[r] = sv / L[r][r];
+            }
+            memcpy(ps, x, sizeof ps);
+            const double nr = sqrt(ps[0] * ps[0] + ps[1] * ps[1] + ps[2] * ps[2]);
+            const double np = sqrt(ps[3] * ps[3] + ps[4] * ps[4] + ps[5] * ps[5]);
+            if (nr > rho_max) for (int c = 0; c < 3; ++c) ps[c] *= rho_max / nr;
+            if (np > phi_max) for (int c = 3; c < 6; ++c) ps[c] *= phi_max / np;
+        }
+        if (psi_out) memcpy(psi_out + 6 * (size_t)i, ps, sizeof ps);
+        pose_right_exp(pose, ps, out + 7 * (size_t)i);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole filter step                                                          */
 /* ------------------------------------------------------------------------ */
 

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libmcslam.so")
 MCS_OK, MCS_EINVAL, MCS_ENOMEM, MCS_EBUDGET, MCS_ENOTFOUND, MCS_EDEVICE, MCS_EBUSY = \
     0, -1, -2, -3, -4, -5, -6
 GRID_FP32, GRID_FP16, GRID_BF16 = 0, 1, 2
-RESAMPLE_NEVER, RESAMPLE_ALWAYS, RESAMPLE_ESS = 0, 1, 2
+RESAMPLE_NEVER, RESAMPLE_ALWAYS, RESAMPLE_ESS, RESAMPLE_PRUNE = 0, 1, 2, 3
+NOISE_INPUT, NOISE_DEVICE = 0, 1
 OOB_FLOOR, OOB_SKIP = 0, 1
 KF_FIXED, KF_LOOP = 0, 1
 
@@ -41,13 +42,15 @@ class StepParams(C.Structure):
                 ("beta", C.c_float), ("oob", C.c_int32), ("post_eval", C.c_int32),
                 ("resample", C.c_int32), ("ess_frac", C.c_double), ("u", C.c_double),
                 ("predict", C.c_int32), ("delta_T", C.c_float * 7), ("n_neighbors", C.c_int32),
-                ("kf_update", C.c_int32), ("n_recent", C.c_int32)]
+                ("kf_update", C.c_int32), ("n_recent", C.c_int32), ("noise_mode", C.c_int32),
+                ("rng_seed", C.c_uint64), ("rng_frame", C.c_uint64), ("noise_sigma", C.c_float * 6),
+                ("prune_post", C.c_float), ("prune_lik", C.c_float)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("lse", C.c_double), ("ess", C.c_double), ("resampled", C.c_int32),
                 ("best", C.c_int32), ("best_pose", C.c_float * 7), ("degenerate", C.c_int32),
-                ("pad", C.c_int32)]
+                ("pruned", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -242,6 +245,14 @@ def step_params(d):
     p.n_neighbors = int(d.get("n_neighbors", 4))
     p.kf_update = int(d.get("kf_update", KF_FIXED))
     p.n_recent = int(d.get("n_recent", p.n_neighbors))
+    p.noise_mode = int(d.get("noise_mode", NOISE_INPUT))
+    p.rng_seed = int(d.get("rng_seed", 0)) & (2**64 - 1)
+    p.rng_frame = int(d.get("rng_frame", 0)) & (2**64 - 1)
+    sig = d.get("noise_sigma", (0.0,) * 6)
+    for c in range(6):
+        p.noise_sigma[c] = float(sig[c])
+    p.prune_post = float(d.get("prune_post", 1e-8))
+    p.prune_lik = float(d.get("prune_lik", 1e-16))
     return p
 
 
@@ -276,7 +287,7 @@ def mcs_get_particles(ctx, sid, N, K=0, poses=True, logw=True, parents=True, log
     if stats:
         out["stats"] = dict(lse=st.lse, ess=st.ess, resampled=bool(st.resampled), best=st.best,
                             best_pose=np.array(st.best_pose[:], np.float32),
-                            degenerate=bool(st.degenerate))
+                            degenerate=bool(st.degenerate), pruned=int(st.pruned))
     return out
 
 

@@ -15,7 +15,13 @@ struct StepStatsDev {
     int32_t best;
     float best_pose[7];
     int32_t degenerate;
-    int32_t pad;
+    int32_t pruned;          // dead particles respawned (pruning policy)
+    // Device-only: shared between the stages of one step.
+    int32_t prune;           // the pruning stages run in this step
+    double lmax;             // max_i l_i
+    double live_mass;        // W, sum of the live weights
+    int32_t last_live;       // largest live index
+    int32_t pad2;
 };
 
 // One session's filter step as every kernel sees it.  The grid is stored
@@ -41,7 +47,8 @@ struct StepDesc {
     float *grad;             // [6][N]
     double *logw;            // [N]
     double *cdf_local;       // [N]
-    double *part;            // [4 * weight_blocks(N)]
+    double *part;            // [kPartPerBlock * weight_blocks(N)]
+    int32_t *copies;         // [N], pruning: copies drawn of each particle
     int32_t *parents;        // [N]
     int32_t *neighbors;      // [n_nb][N]
     StepStatsDev *stats;
@@ -58,10 +65,14 @@ struct StepDesc {
     float dT[7];
     int32_t kf_loop;         // keyframe maps: loop-gated correction with propagation
     int32_t n_recent;        // with kf_loop: neighbours with index >= K - n_recent are recent
-    int32_t pad;
+    int32_t noise_rng;       // prediction noise drawn on the device
+    uint64_t rng_seed, rng_frame;
+    float noise_sigma[6];
+    double ln_prune_post, ln_prune_lik;   // pruning thresholds, natural log
 };
 
 constexpr int kWeightBlock = 256;
+constexpr int kPartPerBlock = 6;   // doubles of per-block partials
 constexpr int kParticleTile = 64;
 constexpr int kKfMaxNb = 8;
 
@@ -82,10 +93,11 @@ bool eval_supported(const StepDesc &d);
 
 // Batched steps of many sessions (the serving path).  Work lists in device
 // memory name (descriptor, block) pairs per stage; every stage kernel is
-// persistent (fixed grid) and pulls items with an atomic head, so one
-// captured graph serves any batch composition.
+// persistent (fixed grid) and strides over its list, so one captured graph
+// serves any batch composition.
 enum BatchKind {
-    kPack = 0, kPredict, kEval, kWeights, kWCombine, kNormScan, kPrefix, kSearch, kCommit, kNumKinds
+    kPack = 0, kPredict, kEval, kWeights, kWCombine, kNormScan, kPrefix, kSearch, kCommit, kFill,
+    kNumKinds
 };
 
 struct BatchTables {
@@ -93,7 +105,6 @@ struct BatchTables {
     const int2 *items;              // (descriptor index, block index); stage k at offs[k]
     const int32_t *counts;          // [kNumKinds]
     const int32_t *offs;            // [kNumKinds]
-    unsigned int *heads;            // [kNumKinds], reset by the first kernel of a tick
 };
 
 // Enqueue one tick of every stage for single-grid sessions of one grid dtype

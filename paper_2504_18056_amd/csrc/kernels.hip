@@ -761,49 +761,79 @@ __device__ __forceinline__ float seg_len(float ax, float ay, float az, float bx,
 // is the path length along the particle's keyframe translations from its
 // oldest neighbour o to k and d_t = d_{K-1} + |t_pre - t_{K-1}|.  The keyframes
 // (o, K) are split into W contiguous chunks, one per wave.  Phase 1 (reads
-// only) gives each wave d_t and the path length and translation just before
-// its chunk; after the barrier, phase 2 rewrites the chunk.  The sum runs in k
-// order in both phases, so d_k does not depend on W.
+// only) sums each chunk's segments, in keyframe order, into LDS; after the
+// barrier every wave adds the sums of the chunks before its own (in chunk
+// order) and phase 2 rewrites its chunk.  Loads are issued B keyframes at a
+// time so that their latencies overlap.
 template <int W>
 __device__ __forceinline__ void kf_propagate(const StepDesc &d, int i, int lane, int wave,
-                                             const int *s_loop, const float (*s_upd)[64])
+                                             const int *s_loop, const float (*s_upd)[64],
+                                             float (*s_seg)[64])
 {
+    constexpr int B = 4;
     const int N = d.N, K = d.K;
     const int o = s_loop[lane];
     const bool act = o >= 0 && i < N;
     float *kp = d.kf_pose;
     const size_t col = act ? (size_t)i : 0;
-    const int len = K - 1 - o;
+    const int len = act ? K - 1 - o : 0;
     const int chunk = (len + W - 1) / W;
-    const int ka = o + 1 + wave * chunk;
-    const int kb = min(K, ka + chunk);
-    float dt = 0.0f, da = 0.0f, ax = 0.0f, ay = 0.0f, az = 0.0f;
+    const int ka = act ? o + 1 + wave * chunk : 0;
+    const int kb = act ? min(K, ka + chunk) : 0;
+    // Phase 1: segments (k-1, k) for k in [ka, kb), and the translations
+    // before the chunk and of the newest keyframe, all read before any write.
+    float seg = 0.0f, ax = 0.0f, ay = 0.0f, az = 0.0f, lx = 0.0f, ly = 0.0f, lz = 0.0f;
     if (act) {
-        float px = kp[((size_t)o * 7) * N + col], py = kp[((size_t)o * 7 + 1) * N + col],
-              pz = kp[((size_t)o * 7 + 2) * N + col];
-        float acc = 0.0f;
-        ax = px; ay = py; az = pz;
-        for (int k = o + 1; k < K; ++k) {
-            if (k == ka) { da = acc; ax = px; ay = py; az = pz; }
-            const size_t r = (size_t)k * 7 * N + col;
-            const float x = kp[r], y = kp[r + N], z = kp[r + 2 * N];
-            acc = __fadd_rn(acc, seg_len(x, y, z, px, py, pz));
-            px = x; py = y; pz = z;
-        }
-        dt = __fadd_rn(acc, seg_len(s_upd[6][lane], s_upd[7][lane], s_upd[8][lane], px, py, pz));
+        const size_t rl = (size_t)(K - 1) * 7 * N + col;
+        lx = kp[rl]; ly = kp[rl + N]; lz = kp[rl + 2 * N];
     }
+    if (ka < kb) {
+        const size_t r0 = (size_t)(ka - 1) * 7 * N + col;
+        float px = kp[r0], py = kp[r0 + N], pz = kp[r0 + 2 * N];
+        ax = px; ay = py; az = pz;
+        for (int k = ka; k < kb; k += B) {
+            float x[B], y[B], z[B];
+            for (int b = 0; b < B; ++b) {
+                const size_t r = (size_t)min(k + b, kb - 1) * 7 * N + col;
+                x[b] = kp[r]; y[b] = kp[r + N]; z[b] = kp[r + 2 * N];
+            }
+            for (int b = 0; b < B; ++b) {
+                if (k + b < kb) {
+                    seg = __fadd_rn(seg, seg_len(x[b], y[b], z[b], px, py, pz));
+                    px = x[b]; py = y[b]; pz = z[b];
+                }
+            }
+        }
+    }
+    s_seg[wave][lane] = seg;
     __syncthreads();
-    if (act && dt > 0.0f) {
-        for (int k = ka; k < kb; ++k) {
-            const size_t r = (size_t)k * 7 * N + col;
-            float t[3] = {kp[r], kp[r + N], kp[r + 2 * N]};
-            float q[4] = {kp[r + 3 * N], kp[r + 4 * N], kp[r + 5 * N], kp[r + 6 * N]};
+    float da = 0.0f, dsum = 0.0f;
+    for (int w = 0; w < W; ++w) {
+        if (w == wave) da = dsum;
+        dsum = __fadd_rn(dsum, s_seg[w][lane]);
+    }
+    const float dt = __fadd_rn(dsum, seg_len(s_upd[6][lane], s_upd[7][lane], s_upd[8][lane], lx, ly, lz));
+    if (!(ka < kb && dt > 0.0f)) return;
+    const float psi_rho[3] = {s_upd[0][lane], s_upd[1][lane], s_upd[2][lane]};
+    const float psi_phi[3] = {s_upd[3][lane], s_upd[4][lane], s_upd[5][lane]};
+    constexpr int B2 = 2;
+    for (int k = ka; k < kb; k += B2) {
+        float v[B2][7];
+        for (int b = 0; b < B2; ++b) {
+            const size_t r = (size_t)min(k + b, kb - 1) * 7 * N + col;
+            for (int c = 0; c < 7; ++c) v[b][c] = kp[r + (size_t)c * N];
+        }
+        for (int b = 0; b < B2; ++b) {
+            if (k + b >= kb) break;
+            float t[3] = {v[b][0], v[b][1], v[b][2]};
+            float q[4] = {v[b][3], v[b][4], v[b][5], v[b][6]};
             da = __fadd_rn(da, seg_len(t[0], t[1], t[2], ax, ay, az));
             ax = t[0]; ay = t[1]; az = t[2];
             const float ratio = __fdiv_rn(da, dt);
-            const float rho[3] = {ratio * s_upd[0][lane], ratio * s_upd[1][lane], ratio * s_upd[2][lane]};
-            const float phi[3] = {ratio * s_upd[3][lane], ratio * s_upd[4][lane], ratio * s_upd[5][lane]};
+            const float rho[3] = {ratio * psi_rho[0], ratio * psi_rho[1], ratio * psi_rho[2]};
+            const float phi[3] = {ratio * psi_phi[0], ratio * psi_phi[1], ratio * psi_phi[2]};
             right_exp(t, q, rho, phi);
+            const size_t r = (size_t)(k + b) * 7 * N + col;
             kp[r] = t[0]; kp[r + N] = t[1]; kp[r + 2 * N] = t[2];
             kp[r + 3 * N] = q[0]; kp[r + 4 * N] = q[1]; kp[r + 5 * N] = q[2]; kp[r + 6 * N] = q[3];
         }
@@ -820,6 +850,7 @@ __device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
     __shared__ int s_nb[kKfMaxNb][64];
     __shared__ int s_loop[64];                  // oldest neighbour when a loop is detected, else -1
     __shared__ float s_upd[9][64];              // psi and the translation before the step
+    __shared__ float s_seg[W][64];              // path length of each wave's keyframe chunk
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -959,7 +990,7 @@ __device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
         }
         __syncthreads();
         if (d.kf_loop && pass < d.iters) {
-            kf_propagate<W>(d, i, lane, wave, s_loop, s_upd);
+            kf_propagate<W>(d, i, lane, wave, s_loop, s_upd, s_seg);
             __syncthreads();
         }
     }
@@ -983,6 +1014,38 @@ __device__ __forceinline__ void pack_blk(const StepDesc &d, int b)
     const float4 v = ok ? make_float4(x, y, z, 0.0f) : make_float4(1e30f, 1e30f, 1e30f, 0.0f);
     d.scan4[j] = v;
     d.scan8[j] = make_double4(v.x, v.y, v.z, 0.0);
+}
+
+// Counter-based prediction noise: SplitMix64 (Steele, Lea and Flood, 2014)
+// outputs by index, turned into normals by Box-Muller.  The stream of frame f
+// is keyed by the f-th output of the seed's stream; particle i takes the
+// uniforms 6i .. 6i+5 of it.
+constexpr uint64_t kSm64Gamma = 0x9e3779b97f4a7c15ull;
+
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double sm64_uniform(uint64_t key, uint64_t j)
+{
+    return (double)(sm64_mix(key + (j + 1) * kSm64Gamma) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ void noise_normals(uint64_t seed, uint64_t frame, uint64_t i, double z[6])
+{
+    const uint64_t key = sm64_mix(seed + (frame + 1) * kSm64Gamma);
+    for (int m = 0; m < 3; ++m) {
+        const double ua = sm64_uniform(key, 6 * i + 2 * m);
+        const double ub = sm64_uniform(key, 6 * i + 2 * m + 1);
+        const double r = sqrt(-2.0 * log(1.0 - ua));
+        double sn, cs;
+        sincos(2.0 * M_PI * ub, &sn, &cs);
+        z[2 * m] = r * cs;
+        z[2 * m + 1] = r * sn;
+    }
 }
 
 // T_i <- T_i * dT * Exp(delta_i)  (Eq. 1), in FP64, rounded to FP32 once.
@@ -1011,7 +1074,13 @@ __device__ __forceinline__ void predict_blk(const StepDesc &d, int b)
     const double m = (nq[0] < 0.0 ? -1.0 : 1.0) /
                      sqrt(nq[0] * nq[0] + nq[1] * nq[1] + nq[2] * nq[2] + nq[3] * nq[3]);
     for (int a = 0; a < 4; ++a) nq[a] *= m;
-    if (d.noise) {
+    if (d.noise_rng) {
+        double z[6];
+        noise_normals(d.rng_seed, d.rng_frame, (uint64_t)i, z);
+        const double rho[3] = {d.noise_sigma[0] * z[0], d.noise_sigma[1] * z[1], d.noise_sigma[2] * z[2]};
+        const double phi[3] = {d.noise_sigma[3] * z[3], d.noise_sigma[4] * z[4], d.noise_sigma[5] * z[5]};
+        right_exp_d(t, nq, rho, phi);
+    } else if (d.noise) {
         const float *nz = d.noise + 6 * (size_t)i;
         const double rho[3] = {nz[0], nz[1], nz[2]};
         const double phi[3] = {nz[3], nz[4], nz[5]};
@@ -1120,8 +1189,11 @@ __device__ __forceinline__ void block_argmax(double &v, int &idx, double *shv, i
     __syncthreads();
 }
 
+constexpr int kPolicyAlways = 1, kPolicyEss = 2, kPolicyPrune = 3;
+
 // Per-block partials of the weight update: logw += beta l, then the block's
-// max (lowest index on ties), sum of exp(logw - max) and of its square.
+// max (lowest index on ties), sum of exp(logw - max) and of its square, and
+// its largest log-likelihood.
 __device__ __forceinline__ void weights_blk(const StepDesc &d, int b)
 {
     constexpr int B = kWeightBlock;
@@ -1130,9 +1202,10 @@ __device__ __forceinline__ void weights_blk(const StepDesc &d, int b)
     const int tid = threadIdx.x;
     const int i = b * B + tid;
     const int N = d.N;
-    double lw = -INFINITY;
+    double lw = -INFINITY, ll = -INFINITY;
     if (i < N) {
-        lw = d.logw[i] + d.beta * (double)d.loglik[i];
+        ll = (double)d.loglik[i];
+        lw = d.logw[i] + d.beta * ll;
         d.logw[i] = lw;
     }
     double m = lw;
@@ -1141,14 +1214,17 @@ __device__ __forceinline__ void weights_blk(const StepDesc &d, int b)
     const double e = (i < N && m > -INFINITY) ? exp(lw - m) : 0.0;
     const double S = block_sum<B>(e, sh);
     const double Q = block_sum<B>(e * e, sh);
+    int li = i;
+    block_argmax<B>(ll, li, sh, shi);
     if (tid == 0) {
-        double *p = d.part + 4 * (size_t)b;
-        p[0] = m; p[1] = S; p[2] = Q; p[3] = (double)am;
+        double *p = d.part + kPartPerBlock * (size_t)b;
+        p[0] = m; p[1] = S; p[2] = Q; p[3] = (double)am; p[4] = ll;
     }
 }
 
 // One block per session: combine the per-block partials (fixed order) into
-// L = logsumexp(logw), ESS, the representative and the resampling decision.
+// L = logsumexp(logw), ESS, the representative, max l and the resampling
+// decision.
 __device__ __forceinline__ void wcombine_blk(const StepDesc &d)
 {
     constexpr int B = kWeightBlock;
@@ -1157,22 +1233,25 @@ __device__ __forceinline__ void wcombine_blk(const StepDesc &d)
     const int tid = threadIdx.x;
     const int N = d.N;
     const int nb = weight_blocks(N);
-    double gm = -INFINITY;
-    int gam = INT_MAX;
+    double gm = -INFINITY, lm = -INFINITY;
+    int gam = INT_MAX, lmi = 0;
     for (int bk = tid; bk < nb; bk += B) {
-        const double bm = d.part[4 * (size_t)bk];
-        const int bi = (int)d.part[4 * (size_t)bk + 3];
+        const double *p = d.part + kPartPerBlock * (size_t)bk;
+        const double bm = p[0];
+        const int bi = (int)p[3];
         if (bm > gm || (bm == gm && bi < gam)) { gm = bm; gam = bi; }
+        if (p[4] > lm) lm = p[4];
     }
     block_argmax<B>(gm, gam, sh, shi);
+    block_argmax<B>(lm, lmi, sh, shi);
     double s = 0.0, q = 0.0;
     if (gm > -INFINITY) {
         for (int bk = tid; bk < nb; bk += B) {
-            const double bm = d.part[4 * (size_t)bk];
-            if (bm > -INFINITY) {
-                const double f = exp(bm - gm);
-                s += d.part[4 * (size_t)bk + 1] * f;
-                q += d.part[4 * (size_t)bk + 2] * f * f;
+            const double *p = d.part + kPartPerBlock * (size_t)bk;
+            if (p[0] > -INFINITY) {
+                const double f = exp(p[0] - gm);
+                s += p[1] * f;
+                q += p[2] * f * f;
             }
         }
     }
@@ -1192,17 +1271,21 @@ __device__ __forceinline__ void wcombine_blk(const StepDesc &d)
             const double ess = St * St / Qt;
             st->lse = L;
             st->ess = ess;
-            st->resampled = (d.policy == 1) || (d.policy == 2 && ess < d.ess_frac * (double)N);
+            st->resampled = (d.policy == kPolicyAlways) ||
+                            (d.policy == kPolicyEss && ess < d.ess_frac * (double)N);
             st->best = gam;
             st->degenerate = 0;
         }
+        st->lmax = lm;
+        st->prune = 0;
+        st->pruned = 0;
         const int bb = degenerate ? 0 : gam;
         for (int c = 0; c < 7; ++c) st->best_pose[c] = d.pose[(size_t)c * N + bb];
     }
 }
 
 // ---------------------------------------------------------------------------
-// Normalisation and systematic resampling
+// Normalisation, systematic resampling and dead-particle pruning
 // ---------------------------------------------------------------------------
 
 // Inclusive scan of one value per thread over the block (Hillis-Steele,
@@ -1225,15 +1308,27 @@ __device__ __forceinline__ double block_scan(double v, double (*sh)[B])
     return v;
 }
 
+// Dead-particle test of the pruning policy (Sec. III-F) on the normalised
+// log-weight: weight below the posterior threshold, or likelihood relative to
+// the frame's best below the likelihood threshold.
+__device__ __forceinline__ bool is_dead(const StepDesc &d, double lw, float l, double lmax)
+{
+    return lw < d.ln_prune_post || ((double)l - lmax) < d.ln_prune_lik;
+}
+
 // logw -= L (uniform reset when degenerate); when resampling, the block-local
-// inclusive scan of w = exp(logw) and the block total.
+// inclusive scan of w = exp(logw) and the block total.  When pruning, the
+// scan runs over the live weights only, and the block's dead count and
+// largest live index are kept too.
 __device__ __forceinline__ void normscan_blk(const StepDesc &d, int b)
 {
     constexpr int B = kWeightBlock;
     __shared__ double sh[2][B];
+    __shared__ int shi[B];
     const int tid = threadIdx.x;
     const int i = b * B + tid;
     const int N = d.N;
+    const int nb = weight_blocks(N);
     const StepStatsDev *st = d.stats;
     const int degenerate = st->degenerate;
     const int resampled = st->resampled;
@@ -1243,45 +1338,133 @@ __device__ __forceinline__ void normscan_blk(const StepDesc &d, int b)
         lw = degenerate ? -log((double)N) : d.logw[i] - L;
         d.logw[i] = lw;
     }
+    if (d.policy == kPolicyPrune) {
+        if (degenerate) return;
+        const bool dead = i < N && is_dead(d, lw, d.loglik[i], st->lmax);
+        const bool live = i < N && !dead;
+        const double v = block_scan<B>(live ? exp(lw) : 0.0, sh);
+        if (i < N) {
+            d.cdf_local[i] = v;
+            d.copies[i] = 0;
+        }
+        if (tid == B - 1) d.part[b] = v;
+        const double nd = block_sum<B>(dead ? 1.0 : 0.0, sh[0]);
+        double lv = live ? (double)i : -1.0;
+        int dummy = 0;
+        block_argmax<B>(lv, dummy, sh[1], shi);
+        if (tid == 0) {
+            d.part[nb + b] = nd;
+            d.part[2 * (size_t)nb + b] = lv;
+        }
+        return;
+    }
     if (!resampled) return;
     const double v = block_scan<B>((i < N) ? exp(lw) : 0.0, sh);
     if (i < N) d.cdf_local[i] = v;
     if (tid == B - 1) d.part[b] = v;
 }
 
-// One block per session: exclusive prefix of the block totals, in place.
+// Exclusive prefix of a[0..n) in place by one block; returns the total.
 // Thread t owns a contiguous chunk; chunk sums are scanned, then each chunk
 // is rewritten sequentially from the previous chunk's inclusive prefix.
+template <int B>
+__device__ __forceinline__ double block_exclusive_prefix(double *a, int n, double (*sh)[B], double *incl)
+{
+    const int tid = threadIdx.x;
+    const int per = (n + B - 1) / B;
+    const int c0 = min(n, tid * per), c1 = min(n, c0 + per);
+    double csum = 0.0;
+    for (int k = c0; k < c1; ++k) csum += a[k];
+    incl[tid] = block_scan<B>(csum, sh);
+    __syncthreads();
+    double off = tid > 0 ? incl[tid - 1] : 0.0;
+    for (int k = c0; k < c1; ++k) {
+        const double tot = a[k];
+        a[k] = off;
+        off += tot;
+    }
+    const double total = incl[B - 1];
+    __syncthreads();
+    return total;
+}
+
+// One block per session: exclusive prefix of the block totals, in place.
+// When pruning, also of the block dead counts, and the decision to prune.
 __device__ __forceinline__ void prefix_blk(const StepDesc &d)
 {
     constexpr int B = kWeightBlock;
     __shared__ double sh[2][B];
     __shared__ double incl[B];
-    if (!d.stats->resampled) return;
-    const int tid = threadIdx.x;
+    __shared__ int shi[B];
+    StepStatsDev *st = d.stats;
     const int nb = weight_blocks(d.N);
-    const int per = (nb + B - 1) / B;
-    const int c0 = min(nb, tid * per), c1 = min(nb, c0 + per);
-    double csum = 0.0;
-    for (int bk = c0; bk < c1; ++bk) csum += d.part[bk];
-    incl[tid] = block_scan<B>(csum, sh);
-    __syncthreads();
-    double off = tid > 0 ? incl[tid - 1] : 0.0;
-    for (int bk = c0; bk < c1; ++bk) {
-        const double tot = d.part[bk];
-        d.part[bk] = off;
-        off += tot;
+    if (d.policy == kPolicyPrune) {
+        if (st->degenerate) return;
+        const double W = block_exclusive_prefix<B>(d.part, nb, sh, incl);
+        const double D = block_exclusive_prefix<B>(d.part + nb, nb, sh, incl);
+        double lv = -1.0;
+        for (int bk = threadIdx.x; bk < nb; bk += B) lv = fmax(lv, d.part[2 * (size_t)nb + bk]);
+        int dummy = 0;
+        block_argmax<B>(lv, dummy, sh[0], shi);
+        if (threadIdx.x == 0) {
+            const bool go = D > 0.0 && lv >= 0.0 && W > 0.0;
+            st->live_mass = W;
+            st->last_live = (int)lv;
+            st->prune = go ? 1 : 0;
+            st->pruned = go ? (int)D : 0;
+        }
+        return;
     }
+    if (!st->resampled) return;
+    block_exclusive_prefix<B>(d.part, nb, sh, incl);
 }
 
-// a_k = min{i : CDF_i > (u + k)/N} (N - 1 if none) by binary search on
-// CDF_i = offset[i / B] + local_i, then gather of the pose rows.
+// Resampling: a_k = min{i : CDF_i > (u + k)/N} (N - 1 if none) by binary
+// search on CDF_i = offset[i / B] + local_i, then gather of the state rows.
+// Pruning: dead slot number r (in index order) takes
+// a_r = min{i : C_i > (u + r)/D W} over the live CDF, copies the parent's
+// pose and keyframe poses, and counts the copy.
 __device__ __forceinline__ void search_blk(const StepDesc &d, int b)
 {
-    const int k = b * kWeightBlock + threadIdx.x;
+    constexpr int B = kWeightBlock;
+    const int k = b * B + threadIdx.x;
     const int N = d.N;
+    const StepStatsDev *st = d.stats;
+    if (d.policy == kPolicyPrune) {
+        __shared__ double sh[2][B];
+        if (!st->prune) {
+            if (k < N) d.parents[k] = k;
+            return;
+        }
+        const double lmax = st->lmax;
+        const bool dead = k < N && is_dead(d, d.logw[k], d.loglik[k], lmax);
+        const double incl = block_scan<B>(dead ? 1.0 : 0.0, sh);
+        if (k >= N) return;
+        if (!dead) {
+            d.parents[k] = k;
+            return;
+        }
+        const int nb = weight_blocks(N);
+        const double rank = d.part[nb + b] + incl - 1.0;
+        const double target = (d.u + rank) / (double)st->pruned * st->live_mass;
+        int lo = 0, hi = N;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const double c = d.part[mid / B] + d.cdf_local[mid];
+            if (c > target) hi = mid; else lo = mid + 1;
+        }
+        // The live CDF is flat over dead entries; a rounding step at a block
+        // boundary must not make a dead entry the parent.
+        while (lo < N && is_dead(d, d.logw[lo], d.loglik[lo], lmax)) ++lo;
+        const int a = lo < N ? lo : st->last_live;
+        d.parents[k] = a;
+        for (int c = 0; c < 7; ++c) d.pose[(size_t)c * N + k] = d.pose[(size_t)c * N + a];
+        for (int r = 0; r < 7 * d.K; ++r) d.kf_pose[(size_t)r * N + k] = d.kf_pose[(size_t)r * N + a];
+        __hip_atomic_fetch_add(d.copies + a, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
     if (k >= N) return;
-    if (!d.stats->resampled) {
+    if (!st->resampled) {
         d.parents[k] = k;
         return;
     }
@@ -1289,7 +1472,7 @@ __device__ __forceinline__ void search_blk(const StepDesc &d, int b)
     int lo = 0, hi = N;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        const double c = d.part[mid / kWeightBlock] + d.cdf_local[mid];
+        const double c = d.part[mid / B] + d.cdf_local[mid];
         if (c > uk) hi = mid; else lo = mid + 1;
     }
     const int anc = lo < N ? lo : N - 1;
@@ -1298,14 +1481,32 @@ __device__ __forceinline__ void search_blk(const StepDesc &d, int b)
     for (int r = 0; r < 7 * d.K; ++r) d.kf_pose_tmp[(size_t)r * N + k] = d.kf_pose[(size_t)r * N + anc];
 }
 
+// Resampling: copy the gathered rows back, logw = -ln N.  Pruning: a live
+// particle shares its weight with its copies and the live mass is
+// renormalised, logw_p -= ln(1 + c_p) + ln W.
 __device__ __forceinline__ void commit_blk(const StepDesc &d, int b)
 {
     const int k = b * kWeightBlock + threadIdx.x;
     const int N = d.N;
-    if (k >= N || !d.stats->resampled) return;
+    if (k >= N) return;
+    if (d.policy == kPolicyPrune) {
+        if (d.stats->prune && d.parents[k] == k)
+            d.logw[k] = d.logw[k] - log1p((double)d.copies[k]) - log(d.stats->live_mass);
+        return;
+    }
+    if (!d.stats->resampled) return;
     for (int r = 0; r < 7; ++r) d.pose[(size_t)r * N + k] = d.pose_tmp[(size_t)r * N + k];
     for (int r = 0; r < 7 * d.K; ++r) d.kf_pose[(size_t)r * N + k] = d.kf_pose_tmp[(size_t)r * N + k];
     d.logw[k] = -log((double)N);
+}
+
+// Pruning: a respawned slot takes its parent's updated log-weight.
+__device__ __forceinline__ void fill_blk(const StepDesc &d, int b)
+{
+    const int k = b * kWeightBlock + threadIdx.x;
+    if (k >= d.N || d.policy != kPolicyPrune || !d.stats->prune) return;
+    const int a = d.parents[k];
+    if (a != k) d.logw[k] = d.logw[a];
 }
 
 // ---------------------------------------------------------------------------
@@ -1340,40 +1541,26 @@ __global__ __launch_bounds__(kWeightBlock) void k_normscan(StepDesc d) { normsca
 __global__ __launch_bounds__(kWeightBlock) void k_prefix(StepDesc d) { prefix_blk(d); }
 __global__ __launch_bounds__(kWeightBlock) void k_search(StepDesc d) { search_blk(d, blockIdx.x); }
 __global__ __launch_bounds__(kWeightBlock) void k_commit(StepDesc d) { commit_blk(d, blockIdx.x); }
+__global__ __launch_bounds__(kWeightBlock) void k_fill(StepDesc d) { fill_blk(d, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
 // Kernels: persistent, batched over many sessions
 // ---------------------------------------------------------------------------
 
-// Pull the next work item of `kind`; false when the list is exhausted.  The
-// item is uniform across the workgroup.
-__device__ __forceinline__ bool next_item(const BatchTables &t, int kind, int2 &w)
-{
-    __shared__ int s_item;
-    if (threadIdx.x == 0)
-        s_item = (int)__hip_atomic_fetch_add(t.heads + kind, 1u, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();
-    if (it >= t.counts[kind]) return false;
-    const int2 v = t.items[t.offs[kind] + it];
-    w.x = __builtin_amdgcn_readfirstlane(v.x);
-    w.y = __builtin_amdgcn_readfirstlane(v.y);
-    return true;
-}
-
-__global__ void kb_reset(unsigned int *heads)
-{
-    if (threadIdx.x < kNumKinds) heads[threadIdx.x] = 0u;
-}
-
-#define MCS_BATCH_LOOP(KIND, BODY)                 \
-    int2 w;                                        \
-    while (next_item(t, KIND, w)) {                \
-        const StepDesc &d = t.descs[w.x];          \
-        BODY;                                      \
-        __syncthreads();                           \
+// Workgroup g of a persistent grid of G takes the items g, g + G, g + 2G, ...
+// of a stage's list: a static assignment, with no shared counter to contend
+// on.  The item is uniform across the workgroup.
+#define MCS_BATCH_LOOP(KIND, BODY)                                          \
+    const int n_items = t.counts[KIND];                                     \
+    const int2 *items = t.items + t.offs[KIND];                             \
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {              \
+        const int2 v = items[it];                                           \
+        int2 w;                                                             \
+        w.x = __builtin_amdgcn_readfirstlane(v.x);                          \
+        w.y = __builtin_amdgcn_readfirstlane(v.y);                          \
+        const StepDesc &d = t.descs[w.x];                                   \
+        BODY;                                                               \
+        __syncthreads();                                                    \
     }
 
 __global__ __launch_bounds__(kWeightBlock) void kb_pack(BatchTables t) { MCS_BATCH_LOOP(kPack, pack_blk(d, w.y)) }
@@ -1384,6 +1571,7 @@ __global__ __launch_bounds__(kWeightBlock) void kb_normscan(BatchTables t) { MCS
 __global__ __launch_bounds__(kWeightBlock) void kb_prefix(BatchTables t) { MCS_BATCH_LOOP(kPrefix, prefix_blk(d)) }
 __global__ __launch_bounds__(kWeightBlock) void kb_search(BatchTables t) { MCS_BATCH_LOOP(kSearch, search_blk(d, w.y)) }
 __global__ __launch_bounds__(kWeightBlock) void kb_commit(BatchTables t) { MCS_BATCH_LOOP(kCommit, commit_blk(d, w.y)) }
+__global__ __launch_bounds__(kWeightBlock) void kb_fill(BatchTables t) { MCS_BATCH_LOOP(kFill, fill_blk(d, w.y)) }
 
 template <int DT, bool SKIP, int W, int U>
 __global__ __launch_bounds__(64 * W) void kb_eval(BatchTables t)
@@ -1490,6 +1678,8 @@ hipError_t launch_resample(const StepDesc &d, hipStream_t st)
     hipLaunchKernelGGL(k_search, dim3(nb), dim3(kWeightBlock), 0, st, d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_commit, dim3(nb), dim3(kWeightBlock), 0, st, d);
+    if ((e = hipGetLastError()) != hipSuccess || d.policy != kPolicyPrune) return e;
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kWeightBlock), 0, st, d);
     return hipGetLastError();
 }
 
@@ -1501,7 +1691,6 @@ constexpr unsigned kBatchGridOne = 256;     // one-block-per-session stages
 template <int DT, bool SKIP>
 static hipError_t launch_batch_dt(const BatchTables &t, hipStream_t st)
 {
-    hipLaunchKernelGGL(kb_reset, dim3(1), dim3(64), 0, st, t.heads);
     hipLaunchKernelGGL(kb_pack, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_predict, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL((kb_eval<DT, SKIP, kEvalW, kEvalU>), dim3(kBatchGridEval), dim3(64 * kEvalW), 0, st, t);
@@ -1511,6 +1700,7 @@ static hipError_t launch_batch_dt(const BatchTables &t, hipStream_t st)
     hipLaunchKernelGGL(kb_prefix, dim3(kBatchGridOne), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_search, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_commit, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
+    hipLaunchKernelGGL(kb_fill, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     return hipGetLastError();
 }
 

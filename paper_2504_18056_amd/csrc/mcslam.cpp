@@ -59,11 +59,12 @@ Layout session_layout(int N, int M_max, int K)
         (size_t)M_max * 16,         // 8 scan4
         n * 8,                      // 9 logw
         n * 8,                      // 10 cdf_local
-        nb * 4 * 8,                 // 11 part
+        nb * kPartPerBlock * 8,     // 11 part
         n * 4,                      // 12 parents
         (K > 0 ? (size_t)kMaxNeighbors * n * 4 : 0),  // 13 neighbors
         sizeof(StepStatsDev),       // 14 stats
         (size_t)M_max * 32,         // 15 scan8
+        n * 4,                      // 16 copies
     };
     Layout L{};
     size_t o = 0;
@@ -218,8 +219,18 @@ mcs_status validate_params(const Session *s, const mcs_step_params *p, int M)
     if (!(p->eps > 0.0f)) return fail(MCS_EINVAL, "eps must be > 0");
     if (p->rho_max < 0.0f || p->phi_max < 0.0f) return fail(MCS_EINVAL, "clamps must be >= 0");
     if (p->oob != MCS_OOB_FLOOR && p->oob != MCS_OOB_SKIP) return fail(MCS_EINVAL, "bad oob mode");
-    if (p->resample < MCS_RESAMPLE_NEVER || p->resample > MCS_RESAMPLE_ESS)
+    if (p->resample < MCS_RESAMPLE_NEVER || p->resample > MCS_RESAMPLE_PRUNE)
         return fail(MCS_EINVAL, "bad resample policy");
+    if (p->resample == MCS_RESAMPLE_PRUNE &&
+        !(p->prune_post > 0.0f && p->prune_lik > 0.0f && std::isfinite(p->prune_post) &&
+          std::isfinite(p->prune_lik)))
+        return fail(MCS_EINVAL, "pruning thresholds must be finite and > 0");
+    if (p->noise_mode != MCS_NOISE_INPUT && p->noise_mode != MCS_NOISE_DEVICE)
+        return fail(MCS_EINVAL, "bad noise mode");
+    if (p->predict && p->noise_mode == MCS_NOISE_DEVICE)
+        for (int c = 0; c < 6; ++c)
+            if (!(p->noise_sigma[c] >= 0.0f && std::isfinite(p->noise_sigma[c])))
+                return fail(MCS_EINVAL, "noise_sigma must be finite and >= 0");
     if (!(p->u >= 0.0 && p->u < 1.0)) return fail(MCS_EINVAL, "u must be in [0, 1)");
     if (p->resample == MCS_RESAMPLE_ESS && !std::isfinite(p->ess_frac))
         return fail(MCS_EINVAL, "ess_frac not finite");
@@ -261,11 +272,17 @@ StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float 
     d.n_nb = s->K > 0 ? p->n_neighbors : 0;
     d.kf_loop = s->K > 0 && p->kf_update == MCS_KF_LOOP;
     d.n_recent = p->n_recent;
+    d.noise_rng = p->predict && p->noise_mode == MCS_NOISE_DEVICE;
+    d.rng_seed = p->rng_seed;
+    d.rng_frame = p->rng_frame;
+    for (int c = 0; c < 6; ++c) d.noise_sigma[c] = p->noise_sigma[c];
+    d.ln_prune_post = std::log((double)p->prune_post);
+    d.ln_prune_lik = std::log((double)p->prune_lik);
     d.pose = s->pose; d.pose_tmp = s->pose_tmp;
     d.kf_pose = s->kf_pose; d.kf_pose_tmp = s->kf_pose_tmp;
     d.loglik = s->loglik; d.grad = s->grad;
     d.logw = s->logw; d.cdf_local = s->cdf_local; d.part = s->part;
-    d.parents = s->parents; d.neighbors = s->neighbors;
+    d.parents = s->parents; d.copies = s->copies; d.neighbors = s->neighbors;
     d.stats = s->stats;
     d.N = s->N; d.M = M;
     d.scan3 = scan3_dev; d.scan4 = s->scan4; d.scan8 = s->scan8;
@@ -540,6 +557,7 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
     ss->neighbors = (int32_t *)(b + L.off[13]);
     ss->stats = (StepStatsDev *)(b + L.off[14]);
     ss->scan8 = (double4 *)(b + L.off[15]);
+    ss->copies = (int32_t *)(b + L.off[16]);
     e = hipMemsetAsync(ss->block, 0, L.total, ss->stream);
     if (e != hipSuccess) return undo(hip_fail(e, "hipMemset(session)"));
     // Initial state: poses, uniform log-weights, identity parents.
@@ -632,7 +650,7 @@ mcs_status mcs_filter_step(mcs_ctx *ctx, int32_t sid, const float *scan, int32_t
     if (st != MCS_OK) return st;
     for (int64_t k = 0; k < (int64_t)M * 3; ++k)
         if (!std::isfinite(scan[k])) return fail(MCS_EINVAL, "scan value %lld not finite", (long long)k);
-    const bool use_noise = p->predict && noise;
+    const bool use_noise = p->predict && noise && p->noise_mode == MCS_NOISE_INPUT;
     if (use_noise)
         for (int64_t k = 0; k < (int64_t)s->N * 6; ++k)
             if (!std::isfinite(noise[k])) return fail(MCS_EINVAL, "noise value not finite");
@@ -769,7 +787,7 @@ mcs_status mcs_get_particles(mcs_ctx *ctx, int32_t sid, float *poses, double *lo
         if (stats->best_pose[3] < 0.0f)
             for (int c = 3; c < 7; ++c) stats->best_pose[c] = -stats->best_pose[c];
         stats->degenerate = d.degenerate;
-        stats->pad = 0;
+        stats->pruned = d.pruned;
     }
     return MCS_OK;
 }

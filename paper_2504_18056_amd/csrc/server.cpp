@@ -48,13 +48,11 @@ struct Request {
 // One table buffer of BATCHED mode.  Device and pinned host images share one
 // layout: a header (per-stage item counts and offsets), max_batch step
 // descriptors, then the work items of all stages packed back to back.  A tick
-// copies the header, the descriptors and the used items in one transfer.  The
-// per-stage pull counters live after the item area and are reset on the
-// device by the graph's first kernel.
+// copies the header, the descriptors and the used items in one transfer.
 struct TableBuf {
     void *dev = nullptr;
     void *host = nullptr;
-    size_t items_off = 0, heads_off = 0, bytes = 0;
+    size_t items_off = 0, bytes = 0;
     int32_t *counts_h = nullptr, *offs_h = nullptr;
     StepDesc *descs_h = nullptr;
     int2 *items_h = nullptr;
@@ -108,14 +106,12 @@ mcs_status alloc_tables(mcs_server *s, TableBuf &b)
     const size_t n_hdr = align_up(2 * kNumKinds * sizeof(int32_t));
     const size_t n_desc = align_up((size_t)s->max_batch * sizeof(StepDesc));
     const size_t n_items = align_up((size_t)kNumKinds * s->max_items * sizeof(int2));
-    const size_t n_heads = align_up(kNumKinds * sizeof(unsigned int));
     b.items_off = n_hdr + n_desc;
-    b.heads_off = b.items_off + n_items;
-    b.bytes = b.heads_off + n_heads;
+    b.bytes = b.items_off + n_items;
     HIP_TRY(hipMalloc(&b.dev, b.bytes), "hipMalloc(server tables)");
-    HIP_TRY(hipHostMalloc(&b.host, b.heads_off, hipHostMallocDefault), "hipHostMalloc(server tables)");
+    HIP_TRY(hipHostMalloc(&b.host, b.bytes, hipHostMallocDefault), "hipHostMalloc(server tables)");
     HIP_TRY(hipMemset(b.dev, 0, b.bytes), "hipMemset(server tables)");
-    std::memset(b.host, 0, b.heads_off);
+    std::memset(b.host, 0, b.bytes);
     char *h = (char *)b.host;
     b.counts_h = (int32_t *)h;
     b.offs_h = b.counts_h + kNumKinds;
@@ -129,7 +125,6 @@ mcs_status alloc_tables(mcs_server *s, TableBuf &b)
     t.offs = t.counts + kNumKinds;
     t.descs = (const StepDesc *)(d + n_hdr);
     t.items = (const int2 *)(d + b.items_off);
-    t.heads = (unsigned int *)(d + b.heads_off);
     HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal), "capture begin");
     hipError_t e = launch_batch(t, s->dtype, s->oob == MCS_OOB_SKIP, b.stream);
     hipError_t e2 = hipStreamEndCapture(b.stream, &b.graph);
@@ -206,7 +201,8 @@ bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b, T
         }
         const StepDesc d = make_desc(ss, r.scan, r.M, r.noise, &r.p);
         const int nb = weight_blocks(d.N), nt = particle_tiles(d.N), ns = scan_blocks(d.M);
-        const std::array<int, kNumKinds> need = {ns, d.predict ? nb : 0, nt, nb, 1, nb, 1, nb, nb};
+        const std::array<int, kNumKinds> need = {ns, d.predict ? nb : 0, nt, nb, 1, nb, 1, nb, nb,
+                                                 d.policy == MCS_RESAMPLE_PRUNE ? nb : 0};
         bool fits = true;
         for (int k = 0; k < kNumKinds; ++k) fits = fits && counts[k] + need[k] <= s->max_items;
         if (!fits) {

@@ -51,7 +51,7 @@ struct Session {
     float4 *scan4 = nullptr;
     double4 *scan8 = nullptr;
     double *logw = nullptr, *cdf_local = nullptr, *part = nullptr;
-    int32_t *parents = nullptr, *neighbors = nullptr;
+    int32_t *parents = nullptr, *neighbors = nullptr, *copies = nullptr;
     StepStatsDev *stats = nullptr;
     float *pinned = nullptr;         // host staging for host-pointer steps
     size_t pinned_floats = 0;

@@ -127,3 +127,31 @@ def check_loop_update(poses_in, kf_in, out, params, n_recent):
         ang = quat_angle(got[:, 3:], want[:, 3:])
         assert np.all(ang <= 2e-6), "rotation off by %g rad" % ang.max()
     return ref
+
+
+def check_prune(logw_in, loglik_gpu, beta, u, out, tau_post, tau_lik):
+    """Dead-particle pruning (Sec. III-F), the oracle fed the GPU's likelihoods:
+    dead count and parents exact except near-ties of the systematic draw,
+    log-weights to rounding, respawned poses bit-exact copies of the parent's.
+    Returns the oracle's result."""
+    beta = float(np.float32(beta))
+    tau_post, tau_lik = float(np.float32(tau_post)), float(np.float32(tau_lik))
+    l64 = loglik_gpu.astype(np.float64)
+    lw_ref, L, ess = oracle.weights(logw_in, l64, beta)
+    r = oracle.prune(lw_ref, l64, tau_post, tau_lik, u)
+    # A dead decision taken within rounding of the threshold is not checked.
+    assert not np.any(np.abs(lw_ref - np.log(tau_post)) < 1e-9), "near-tie in the weight test"
+    st = out["stats"]
+    assert st["pruned"] == r["n_dead"], (st["pruned"], r["n_dead"])
+    par = out["parents"]
+    ties = r["margin"] < 1e-12
+    mism = par != r["parents"]
+    assert np.all(ties[mism]), "parents differ away from ties: %s" % np.flatnonzero(mism & ~ties)[:10]
+    ok = ~mism
+    dl = np.abs(out["logw"][ok] - r["logw"][ok])
+    fin = np.isfinite(r["logw"][ok])
+    assert np.all(dl[fin] <= 1e-12 + 1e-12 * np.abs(r["logw"][ok][fin])), dl[fin].max()
+    dead = par != np.arange(len(par))
+    assert np.array_equal(out["poses"][dead], out["poses"][par[dead]])
+    assert abs(np.sum(np.exp(out["logw"])) - 1.0) < 1e-10
+    return r

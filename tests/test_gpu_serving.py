@@ -45,6 +45,11 @@ def make_sessions(ctx, specs, dtype=abi.GRID_FP16, frames=3):
         params = [dict(c["params"], iters=2, u=float(0.1 + 0.2 * f), beta=0.01, resample=abi.RESAMPLE_ESS,
                        ess_frac=0.5, delta_T=np.array([0.05, 0.0, 0.0, *dq], np.float32))
                   for f in range(frames)]
+        if seed in PRUNING_SEEDS:
+            # Dead-particle pruning with noise drawn on the device.
+            for f, q in enumerate(params):
+                q.update(resample=abi.RESAMPLE_PRUNE, beta=0.2, noise_mode=abi.NOISE_DEVICE,
+                         rng_seed=seed, rng_frame=f, noise_sigma=(0.02, 0.02, 0.02, 0.005, 0.005, 0.005))
         out.append(dict(cfg=c, N=N, M=M, mid=mid, sid=sid, params=params,
                         scans=torch.from_numpy(scans).to(DEV), noise=torch.from_numpy(noise).to(DEV)))
     torch.cuda.synchronize()
@@ -54,7 +59,7 @@ def make_sessions(ctx, specs, dtype=abi.GRID_FP16, frames=3):
 def snapshot(ctx, s):
     o = abi.mcs_get_particles(ctx, s["sid"], s["N"])
     return {k: o[k].copy() for k in ("poses", "logw", "parents", "loglik", "grad")} | {
-        "lse": o["stats"]["lse"], "ess": o["stats"]["ess"]}
+        "lse": o["stats"]["lse"], "ess": o["stats"]["ess"], "pruned": o["stats"]["pruned"]}
 
 
 def reset(ctx, s):
@@ -77,9 +82,10 @@ def run_alone(ctx, sessions, frames):
 def assert_same(a, b, what):
     for k in ("poses", "logw", "parents", "loglik", "grad"):
         assert np.array_equal(a[k], b[k]), "%s: %s differs" % (what, k)
-    assert a["lse"] == b["lse"] and a["ess"] == b["ess"], what
+    assert a["lse"] == b["lse"] and a["ess"] == b["ess"] and a["pruned"] == b["pruned"], what
 
 
+PRUNING_SEEDS = (204, 206)
 SPECS = [(1000, 8, 64, 201), (3000, 16, 96, 202), (64, 8, 64, 203), (12345, 32, 128, 204),
          (257, 12, 64, 205), (40000, 20, 128, 206)]
 
@@ -119,6 +125,7 @@ def test_each_session_same_alone_and_in_the_mix(ctx, mode):
             abi.mcs_server_drain(srv)
             for k, s in enumerate(sessions):
                 assert_same(ref[k][frames - 1], snapshot(ctx, s), "session %d (mixed)" % k)
+            assert any(ref[k][f]["pruned"] > 0 for k in range(len(sessions)) for f in range(frames))
             st = abi.mcs_server_stats_get(srv)
             assert st["requests"] == 2 * frames * len(sessions)
             if mode != abi.SERVE_SERIAL:
