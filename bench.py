@@ -211,47 +211,22 @@ def run_serving(args, abi, torch, prepared):
                                          "refused": refused, "in_use_gb": round(in_use / 1e9, 2)}}
 
 
-def run_precision(abi):
-    """Errors of one box-room step (N = 1,024, M = 512) against the FP64 oracle, per grid dtype."""
-    import oracle
-    from synth import configs
+def run_floors(abi):
+    """Kidnapped start over four identical storeys (N = 20,000, 80 frames): storey
+    shares before the distinguishing feature is seen, and convergence after."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from parity import quat_angle
-    c = configs.box_room()
-    N = c["poses"].shape[0]
-    beta = 0.002      # tempered so that resampling keeps many ancestors
-    out = {}
-    ctx = abi.mcs_create(0)
-    for dtype, name in ((abi.GRID_FP32, "fp32"), (abi.GRID_FP16, "fp16"), (abi.GRID_BF16, "bf16")):
-        g = {0: c["grid"], 1: oracle.quantize_fp16(c["grid"]), 2: oracle.quantize_bf16(c["grid"])}[dtype]
-        p = dict(c["params"], u=c["u"], beta=beta, resample=abi.RESAMPLE_ALWAYS)
-        mid = abi.mcs_init_map(ctx, abi.grid_desc(c["dims"], c["origin"], c["h"], dtype), c["grid"])
-        sid = abi.mcs_session_create(ctx, mid, c["poses"], M_max=512)
-        abi.mcs_filter_step(ctx, sid, c["scan"], p)
-        o = abi.mcs_get_particles(ctx, sid, N)
-        abi.mcs_session_destroy(ctx, sid)
-        abi.mcs_release_map(ctx, mid)
-        ref = oracle.evaluate(g, c["dims"], c["origin"], c["h"], p["eps"], c["scan"], c["poses"], delta=5e-4)
-        ref32 = oracle.evaluate(c["grid"], c["dims"], c["origin"], c["h"], p["eps"], c["scan"], c["poses"])
-        rel_l = np.abs(o["loglik"] - ref["loglik"]) / np.abs(ref["loglik"])
-        rel_g = np.max((np.abs(o["grad"] - ref["grad"]) - ref["amb_g"]) / ref["gabs"], axis=1)
-        stepped = oracle.step(c["poses"], ref["grad"], p["alpha_t"], p["alpha_r"], p["rho_max"], p["phi_max"])
-        anc = o["parents"]
-        dt = np.linalg.norm(o["poses"][:, :3] - stepped[anc, :3], axis=1)
-        da = quat_angle(o["poses"][:, 3:], stepped[anc, 3:])
-        lw, L, ess = oracle.weights(c["logw"], o["loglik"].astype(np.float64), float(np.float32(beta)))
-        a_ref, margin = oracle.resample(lw, p["u"])
-        mism = int(np.sum(a_ref != o["parents"]))
-        out[name] = {"loglik_rel_max": float("%.3g" % rel_l.max()),
-                     "grad_rel_max": float("%.3g" % max(0.0, rel_g.max())),
-                     "pose_err_m_max": float("%.3g" % dt.max()), "pose_err_rad_max": float("%.3g" % da.max()),
-                     "resample_mismatch": mism, "resample_near_ties": int(np.sum(margin < 1e-12)),
-                     "loglik_rel_vs_fp32_grid": float("%.3g" % (np.abs(o["loglik"] - ref32["loglik"]) /
-                                                               np.abs(ref32["loglik"])).max())}
-    abi.mcs_destroy(ctx)
-    return {"workload": "box_room N=1024 M=512, one step, beta=0.002", "by_grid_dtype": out,
-            "note": "grad_rel: max over particles and components of (|dg| - cell-face allowance) / "
-                    "sum_j |dl_j/dxi|; pose error: GPU step vs the oracle step from the oracle's gradient"}
+    import floors_demo
+    from synth import configs
+    c = configs.repeated_floors(N=20000)
+    out = {"workload": "repeated floors: 4 identical storeys of a 51.2 m maze level, one box only on "
+                       "the true storey, N=20000, M=512, 10 m range, 80 frames, beta=0.05, "
+                       "device random-walk noise"}
+    for policy, name in ((abi.RESAMPLE_PRUNE, "pruning"), (abi.RESAMPLE_ESS, "ess_resampling")):
+        t0 = time.perf_counter()
+        mass, share, best = floors_demo.run(c, policy)
+        out[name] = dict(floors_demo.summary(c, mass, share, best),
+                         ms_per_frame=round(1e3 * (time.perf_counter() - t0) / len(mass), 3))
+    return out
 
 
 def run_keyframes(abi, steps=5):
@@ -306,7 +281,7 @@ def main():
     ap.add_argument("--serving-load", type=float, default=1.0,
                     help="multiplier on the 10 Hz per-session arrival rate")
     ap.add_argument("--extras", type=int, default=1,
-                    help="1: also report the precision table and the keyframe-map timing")
+                    help="1: also report the keyframe-map timing and the repeated-floors demo")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -426,13 +401,14 @@ def main():
                "sample": "one corridors frame (prediction, 3 passes, weights, ESS resampling) "
                          "for %d particles x %d points; %.2f s wall" % (ns, M, dt)}
 
-    precision = keyframes = None
+    floors = keyframes = None
     if args.extras:
-        log("precision table (box_room, fp32/fp16/bf16 grids)")
-        precision = run_precision(abi)
         log("keyframe-map timing")
         keyframes = run_keyframes(abi)
         log("keyframes: %s" % keyframes)
+        log("repeated-floors demo")
+        floors = run_floors(abi)
+        log("floors: %s" % floors)
     serving = None
     if args.serving_seconds > 0:
         serving = run_serving(args, abi, torch, prepared)
@@ -465,7 +441,7 @@ def main():
                            if serving else None),
         "serving": serving,
         "keyframes": keyframes,
-        "precision": precision,
+        "repeated_floors": floors,
     }
     print(json.dumps(res), flush=True)
 

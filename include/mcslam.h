@@ -230,6 +230,54 @@ mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t session_id, const float *sc
                                int32_t M, const float *noise_dev, const mcs_step_params *p,
                                void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* GICP likelihood and Gauss-Newton correction (Sec. III-C, Eq. 2-7)          */
+/* ------------------------------------------------------------------------ */
+
+/* A keyframe's voxel map for the distribution-to-distribution (GICP)
+ * likelihood with voxel correspondences: voxel (i, j, k) covers
+ * [origin + (i, j, k) edge, origin + (i+1, j+1, k+1) edge) in the keyframe's
+ * frame. */
+typedef struct {
+    int32_t nx, ny, nz;     /* voxels per axis, 1 .. 65536 */
+    float origin[3];
+    float edge;             /* voxel edge (m), > 0 */
+} mcs_voxel_desc;
+
+/* Load K keyframe voxel maps (all of one shape and edge).  voxels[k]: host
+ * nx*ny*nz*12 FP32, x fastest: the mean of the keyframe's points in the
+ * voxel (3), their count (0: empty voxel), their covariance
+ * (xx xy xz yy yz zz), 2 unused.  Sessions on the map carry per-particle
+ * keyframe poses as for mcs_load_keyframes and are stepped with
+ * mcs_filter_step_gicp*.  Errors: MCS_EINVAL, MCS_EBUDGET, MCS_ENOMEM. */
+mcs_status mcs_load_gicp_keyframes(mcs_ctx *ctx, int32_t K, const mcs_voxel_desc *descs,
+                                   const float *const *voxels, int32_t *map_id);
+
+/* One filter step with the GICP likelihood (Eq. 2-4) and Gauss-Newton passes
+ * (Eq. 5-7) on a voxel keyframe map.  mu: M*3 scan point means, cov: M*6
+ * their covariances (xx xy xz yy yz zz), sensor frame.  For each particle and
+ * each of its n_neighbors keyframes (chosen as for grid keyframes), a point
+ * x = kT mu (kT = T_k^-1 T) takes the Gaussian (mu', S') of the voxel holding
+ * it, if any; l = -sum e^T Omega e with e = mu' - x and
+ * Omega = (S' + R Sigma R^T)^-1 (R the rotation of kT); H and b of Eq. 6 in
+ * the body frame; psi = -H^-1 b (Cholesky; no step when H is not positive
+ * definite), each block clamped to rho_max / phi_max, T <- T Exp(psi).  The
+ * step's alpha_t, alpha_r and eps are not used.  kf_update, weights,
+ * resampling and pruning work as in mcs_filter_step.  Returns MCS_EINVAL on a
+ * grid map (and mcs_filter_step returns MCS_EINVAL on a voxel map). */
+mcs_status mcs_filter_step_gicp(mcs_ctx *ctx, int32_t session_id, const float *mu, const float *cov,
+                                int32_t M, const float *noise, const mcs_step_params *p);
+
+/* As mcs_filter_step_gicp with device pointers and an optional stream. */
+mcs_status mcs_filter_step_gicp_dev(mcs_ctx *ctx, int32_t session_id, const float *mu_dev,
+                                    const float *cov_dev, int32_t M, const float *noise_dev,
+                                    const mcs_step_params *p, void *stream);
+
+/* The Gauss-Newton system of the last stepping pass of a GICP session (after
+ * waiting for its work): H N*21 (upper triangle of the 6x6, row-major, [rho;
+ * phi] order) and b N*6, indexed before resampling.  Either may be NULL. */
+mcs_status mcs_get_gicp_system(mcs_ctx *ctx, int32_t session_id, float *H, float *b);
+
 /* Wait for the session's queued work, then copy out the state.  Any output
  * may be NULL.  poses N*7; logw N (FP64, normalised); parents N (ancestor of
  * each particle in the last step, identity when it did not resample); loglik N

@@ -36,6 +36,11 @@ class GridDesc(C.Structure):
                 ("origin", C.c_float * 3), ("res", C.c_float), ("dtype", C.c_int32)]
 
 
+class VoxelDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("origin", C.c_float * 3), ("edge", C.c_float)]
+
+
 class StepParams(C.Structure):
     _fields_ = [("iters", C.c_int32), ("alpha_t", C.c_float), ("alpha_r", C.c_float),
                 ("rho_max", C.c_float), ("phi_max", C.c_float), ("eps", C.c_float),
@@ -113,6 +118,10 @@ def lib():
             "mcs_server_stats_get": (i32, [vp, P(ServerStats)]),
             "mcs_session_profile": (i32, [vp, i32, i32]),
             "mcs_session_profile_read": (i32, [vp, i32, P(Profile)]),
+            "mcs_load_gicp_keyframes": (i32, [vp, i32, P(VoxelDesc), P(vp), P(i32)]),
+            "mcs_filter_step_gicp": (i32, [vp, i32, vp, vp, i32, vp, P(StepParams)]),
+            "mcs_filter_step_gicp_dev": (i32, [vp, i32, vp, vp, i32, vp, P(StepParams), vp]),
+            "mcs_get_gicp_system": (i32, [vp, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -190,6 +199,51 @@ def mcs_load_keyframes(ctx, descs, values):
     mid = C.c_int32()
     _check(lib().mcs_load_keyframes(ctx, K, arr, ptrs, C.byref(mid)))
     return mid.value
+
+
+def voxel_desc(dims, origin, edge):
+    d = VoxelDesc()
+    d.nx, d.ny, d.nz = (int(v) for v in dims)
+    for a in range(3):
+        d.origin[a] = float(origin[a])
+    d.edge = float(edge)
+    return d
+
+
+def mcs_load_gicp_keyframes(ctx, descs, voxels):
+    """descs: VoxelDesc per keyframe; voxels: per keyframe (nz, ny, nx, 12) FP32."""
+    K = len(descs)
+    arr = (VoxelDesc * K)(*descs)
+    keep = [_f32(v, (-1,)) for v in voxels]
+    ptrs = (C.c_void_p * K)(*[k.ctypes.data for k in keep])
+    mid = C.c_int32()
+    _check(lib().mcs_load_gicp_keyframes(ctx, K, arr, ptrs, C.byref(mid)))
+    return mid.value
+
+
+def mcs_filter_step_gicp(ctx, sid, mu, cov, params, noise=None):
+    m = _f32(mu, (-1, 3))
+    c = _f32(cov, (-1, 6))
+    n = None if noise is None else _f32(noise, (-1, 6))
+    p = params if isinstance(params, StepParams) else step_params(params)
+    _check(lib().mcs_filter_step_gicp(ctx, int(sid), _ptr(m), _ptr(c), m.shape[0], _ptr(n), C.byref(p)))
+
+
+def mcs_filter_step_gicp_dev(ctx, sid, mu_dev_ptr, cov_dev_ptr, M, params, noise_dev_ptr=None,
+                             stream=None):
+    p = params if isinstance(params, StepParams) else step_params(params)
+    _check(lib().mcs_filter_step_gicp_dev(
+        ctx, int(sid), C.c_void_p(int(mu_dev_ptr)), C.c_void_p(int(cov_dev_ptr)), int(M),
+        None if noise_dev_ptr is None else C.c_void_p(int(noise_dev_ptr)), C.byref(p),
+        None if stream is None else C.c_void_p(int(stream))))
+
+
+def mcs_get_gicp_system(ctx, sid, N):
+    """(H (N, 21) upper triangle row-major, b (N, 6)) of the last stepping pass."""
+    H = np.empty((N, 21), np.float32)
+    b = np.empty((N, 6), np.float32)
+    _check(lib().mcs_get_gicp_system(ctx, int(sid), _ptr(H), _ptr(b)))
+    return H, b
 
 
 def mcs_release_map(ctx, map_id):

@@ -69,6 +69,12 @@ struct StepDesc {
     uint64_t rng_seed, rng_frame;
     float noise_sigma[6];
     double ln_prune_post, ln_prune_lik;   // pruning thresholds, natural log
+    // GICP likelihood with Gauss-Newton passes on voxel keyframe maps: cells
+    // then holds K maps of nx*ny*nz voxel records (48 B), h the voxel edge.
+    int32_t gicp;
+    const float *cov6;       // [M][6] scan point covariances (xx xy xz yy yz zz)
+    float4 *scan_g;          // [3M] packed points: (mu, 0), (xx xy xz yy), (yz zz 0 0)
+    float *hess;             // [21][N] H of the last pass (upper triangle, row-major)
 };
 
 constexpr int kWeightBlock = 256;

@@ -840,6 +840,295 @@ __device__ __forceinline__ void kf_propagate(const StepDesc &d, int i, int lane,
     }
 }
 
+// Wave 0 of a keyframe tile: the tile's poses into LDS, each particle's
+// neighbour keyframes (the n_nb smallest FP32 squared translation distances,
+// ties to the smaller k) and its loop flag (Sec. III-C.2: an old keyframe
+// among the neighbours; the oldest neighbour, else -1).
+__device__ __forceinline__ void kf_select(const StepDesc &d, int i, int lane, float (*s_pose)[64],
+                                          int (*s_nb)[64], int *s_loop)
+{
+    const int N = d.N, K = d.K, n_nb = d.n_nb;
+    const int ic = i < N ? i : N - 1;
+    load_tile_pose(d, i, lane, s_pose);
+    const float tx = s_pose[0][lane], ty = s_pose[1][lane], tz = s_pose[2][lane];
+    float bd[kKfMaxNb];
+    int bk[kKfMaxNb];
+    for (int s = 0; s < kKfMaxNb; ++s) { bd[s] = INFINITY; bk[s] = K; }
+    for (int k = 0; k < K; ++k) {
+        const size_t r = (size_t)k * 7 * N + ic;
+        const float dd = dist2_rn(tx, ty, tz, d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]);
+        // Insert (dd, k) into the sorted list; k ascending keeps ties on the smaller k.
+        float cd = dd;
+        int ck = k;
+        for (int s = 0; s < kKfMaxNb; ++s) {
+            if (s < n_nb && cd < bd[s]) {
+                const float td = bd[s];
+                const int tk = bk[s];
+                bd[s] = cd; bk[s] = ck;
+                cd = td; ck = tk;
+            }
+        }
+    }
+    // Every slot below n_nb <= K is filled (distances are finite); guard anyway.
+    for (int s = 0; s < kKfMaxNb; ++s) s_nb[s][lane] = bk[s] < K ? bk[s] : 0;
+    if (i < N)
+        for (int s = 0; s < n_nb; ++s) d.neighbors[(size_t)s * N + i] = s_nb[s][lane];
+    int o = K;
+    for (int s = 0; s < n_nb; ++s) o = min(o, s_nb[s][lane]);
+    s_loop[lane] = (d.kf_loop && o < K - d.n_recent) ? o : -1;
+}
+
+// ---------------------------------------------------------------------------
+// GICP likelihood with voxel correspondences and Gauss-Newton passes (Eq. 2-7)
+// ---------------------------------------------------------------------------
+
+// Upper-triangle index of H[r][c], r <= c, row-major over the 6x6 system.
+__host__ __device__ constexpr int htri(int r, int c) { return r * 6 - r * (r - 1) / 2 + (c - r); }
+
+// psi = -H^-1 b by Cholesky in FP64; false when H is not positive definite
+// (a pivot at most 1e-12 of the largest diagonal entry).
+__device__ __forceinline__ bool gn_solve(const float h[21], const float b[6], float psi[6])
+{
+    double L[21];
+    double dmax = 0.0;
+    for (int r = 0; r < 6; ++r) dmax = fmax(dmax, (double)h[htri(r, r)]);
+    if (!(dmax > 0.0)) return false;
+    // L stored as the transpose of the upper triangle: L[htri(c, r)] = L_rc for r >= c.
+    for (int c = 0; c < 6; ++c) {
+        double sd = h[htri(c, c)];
+        for (int k = 0; k < c; ++k) sd -= L[htri(k, c)] * L[htri(k, c)];
+        if (!(sd > 1e-12 * dmax)) return false;
+        const double lc = sqrt(sd);
+        L[htri(c, c)] = lc;
+        const double il = 1.0 / lc;
+        for (int r = c + 1; r < 6; ++r) {
+            double sv = h[htri(c, r)];
+            for (int k = 0; k < c; ++k) sv -= L[htri(k, r)] * L[htri(k, c)];
+            L[htri(c, r)] = sv * il;
+        }
+    }
+    double y[6], x[6];
+    for (int r = 0; r < 6; ++r) {
+        double sv = -(double)b[r];
+        for (int k = 0; k < r; ++k) sv -= L[htri(k, r)] * y[k];
+        y[r] = sv / L[htri(r, r)];
+    }
+    for (int r = 5; r >= 0; --r) {
+        double sv = y[r];
+        for (int k = r + 1; k < 6; ++k) sv -= L[htri(r, k)] * x[k];
+        x[r] = sv / L[htri(r, r)];
+    }
+    for (int r = 0; r < 6; ++r) psi[r] = (float)x[r];
+    return true;
+}
+
+typedef const __attribute__((address_space(4))) f4v *gscan_ptr;
+
+// One (particle, point, keyframe) term of Eq. 3-6 in the scan's frame:
+// x = R' mu + t' (FP64) selects the voxel; e = mu_v - x; with R'^T the
+// rotation back, e_s = R'^T e, Omega_s = (R'^T S_v R' + Sigma)^-1 (FP64
+// inverse), w = Omega_s e_s; l -= e_s^T w; b += J_s^T w and
+// H += J_s^T Omega_s J_s with J_s = [-I, [mu]x].
+__device__ __forceinline__ void gicp_point(const double R[9], const float Rf[9], const double t[3],
+                                           const double o[3], double inv_vs, int nx, int ny, int nz,
+                                           uint64_t vbase, const f4v p4, const f4v c4a, const f4v c4b,
+                                           double &l, float acc[27])
+{
+    const double x0 = fma(R[0], (double)p4.x, fma(R[1], (double)p4.y, fma(R[2], (double)p4.z, t[0])));
+    const double x1 = fma(R[3], (double)p4.x, fma(R[4], (double)p4.y, fma(R[5], (double)p4.z, t[1])));
+    const double x2 = fma(R[6], (double)p4.x, fma(R[7], (double)p4.y, fma(R[8], (double)p4.z, t[2])));
+    const double u0 = floor((x0 - o[0]) * inv_vs), u1 = floor((x1 - o[1]) * inv_vs),
+                 u2 = floor((x2 - o[2]) * inv_vs);
+    if (!(u0 >= 0.0 && u0 < (double)nx && u1 >= 0.0 && u1 < (double)ny && u2 >= 0.0 && u2 < (double)nz))
+        return;
+    const uint64_t rec = (uint64_t)u0 + (uint64_t)nx * ((uint64_t)u1 + (uint64_t)ny * (uint64_t)u2);
+    const f4v *vr = reinterpret_cast<const f4v *>(vbase + rec * 48u);
+    const f4v va = vr[0];
+    if (!(va.w > 0.0f)) return;
+    const f4v vb = vr[1], vc = vr[2];
+    // Residual in the keyframe frame (FP64 difference, then FP32) and in the scan frame.
+    const float e0 = (float)((double)va.x - x0), e1 = (float)((double)va.y - x1),
+                e2 = (float)((double)va.z - x2);
+    const float es0 = Rf[0] * e0 + Rf[3] * e1 + Rf[6] * e2;
+    const float es1 = Rf[1] * e0 + Rf[4] * e1 + Rf[7] * e2;
+    const float es2 = Rf[2] * e0 + Rf[5] * e1 + Rf[8] * e2;
+    // S_v (xx xy xz yy yz zz) = (vb.x vb.y vb.z vb.w vc.x vc.y); T = S_v R', Ss = R'^T T.
+    const float S00 = vb.x, S01 = vb.y, S02 = vb.z, S11 = vb.w, S12 = vc.x, S22 = vc.y;
+    float T[9];
+    for (int c = 0; c < 3; ++c) {
+        T[c] = S00 * Rf[c] + S01 * Rf[3 + c] + S02 * Rf[6 + c];
+        T[3 + c] = S01 * Rf[c] + S11 * Rf[3 + c] + S12 * Rf[6 + c];
+        T[6 + c] = S02 * Rf[c] + S12 * Rf[3 + c] + S22 * Rf[6 + c];
+    }
+    const double C00 = (double)(Rf[0] * T[0] + Rf[3] * T[3] + Rf[6] * T[6]) + (double)c4a.x;
+    const double C01 = (double)(Rf[0] * T[1] + Rf[3] * T[4] + Rf[6] * T[7]) + (double)c4a.y;
+    const double C02 = (double)(Rf[0] * T[2] + Rf[3] * T[5] + Rf[6] * T[8]) + (double)c4a.z;
+    const double C11 = (double)(Rf[1] * T[1] + Rf[4] * T[4] + Rf[7] * T[7]) + (double)c4a.w;
+    const double C12 = (double)(Rf[1] * T[2] + Rf[4] * T[5] + Rf[7] * T[8]) + (double)c4b.x;
+    const double C22 = (double)(Rf[2] * T[2] + Rf[5] * T[5] + Rf[8] * T[8]) + (double)c4b.y;
+    // Inverse of the symmetric C by its adjugate.
+    const double a00 = C11 * C22 - C12 * C12, a01 = C02 * C12 - C01 * C22, a02 = C01 * C12 - C02 * C11;
+    const double det = C00 * a00 + C01 * a01 + C02 * a02;
+    if (!(det > 0.0)) return;
+    const double id = 1.0 / det;
+    const double O00 = a00 * id, O01 = a01 * id, O02 = a02 * id;
+    const double O11 = (C00 * C22 - C02 * C02) * id, O12 = (C01 * C02 - C00 * C12) * id,
+                 O22 = (C00 * C11 - C01 * C01) * id;
+    const double w0 = O00 * es0 + O01 * es1 + O02 * es2;
+    const double w1 = O01 * es0 + O11 * es1 + O12 * es2;
+    const double w2 = O02 * es0 + O12 * es1 + O22 * es2;
+    l -= (double)es0 * w0 + (double)es1 * w1 + (double)es2 * w2;
+    const float px = p4.x, py = p4.y, pz = p4.z;
+    const float fw0 = (float)w0, fw1 = (float)w1, fw2 = (float)w2;
+    // b = J_s^T w = [-w; -(mu x w)]
+    acc[21] -= fw0; acc[22] -= fw1; acc[23] -= fw2;
+    acc[24] -= py * fw2 - pz * fw1;
+    acc[25] -= pz * fw0 - px * fw2;
+    acc[26] -= px * fw1 - py * fw0;
+    const float o00 = (float)O00, o01 = (float)O01, o02 = (float)O02, o11 = (float)O11,
+                o12 = (float)O12, o22 = (float)O22;
+    // H_rho,rho = Omega
+    acc[htri(0, 0)] += o00; acc[htri(0, 1)] += o01; acc[htri(0, 2)] += o02;
+    acc[htri(1, 1)] += o11; acc[htri(1, 2)] += o12; acc[htri(2, 2)] += o22;
+    // OK = Omega [mu]x, rows r: (Om[r][1] pz - Om[r][2] py, Om[r][2] px - Om[r][0] pz, Om[r][0] py - Om[r][1] px)
+    const float k00 = o01 * pz - o02 * py, k01 = o02 * px - o00 * pz, k02 = o00 * py - o01 * px;
+    const float k10 = o11 * pz - o12 * py, k11 = o12 * px - o01 * pz, k12 = o01 * py - o11 * px;
+    const float k20 = o12 * pz - o22 * py, k21 = o22 * px - o02 * pz, k22 = o02 * py - o12 * px;
+    // H_rho,phi = -OK
+    acc[htri(0, 3)] -= k00; acc[htri(0, 4)] -= k01; acc[htri(0, 5)] -= k02;
+    acc[htri(1, 3)] -= k10; acc[htri(1, 4)] -= k11; acc[htri(1, 5)] -= k12;
+    acc[htri(2, 3)] -= k20; acc[htri(2, 4)] -= k21; acc[htri(2, 5)] -= k22;
+    // H_phi,phi = [mu]x^T OK: row 0 = pz OK[1] - py OK[2], row 1 = px OK[2] - pz OK[0],
+    // row 2 = py OK[0] - px OK[1] (upper triangle).
+    acc[htri(3, 3)] += pz * k10 - py * k20;
+    acc[htri(3, 4)] += pz * k11 - py * k21;
+    acc[htri(3, 5)] += pz * k12 - py * k22;
+    acc[htri(4, 4)] += px * k21 - pz * k01;
+    acc[htri(4, 5)] += px * k22 - pz * k02;
+    acc[htri(5, 5)] += py * k02 - px * k12;
+}
+
+template <int W>
+__device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
+{
+    __shared__ double s_l[W][64];
+    __shared__ float s_h[27][W][64];            // H (21) and b (6) partial sums per wave
+    __shared__ float s_pose[7][64];
+    __shared__ int s_nb[kKfMaxNb][64];
+    __shared__ int s_loop[64];
+    __shared__ float s_upd[9][64];
+    __shared__ float s_seg[W][64];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int N = d.N, n_nb = d.n_nb;
+    const int i = tile * 64 + lane;
+    const int ic = i < N ? i : N - 1;
+    const gscan_ptr scan = (gscan_ptr)d.scan_g;
+    const double inv_vs = 1.0 / (double)d.h;
+
+    if (wave == 0) kf_select(d, i, lane, s_pose, s_nb, s_loop);
+    const int chunk = (d.M + W - 1) / W;
+    const int j0 = min(d.M, wave * chunk);
+    const int j1 = min(d.M, j0 + chunk);
+    const int passes = d.iters + d.post_eval;
+    __syncthreads();
+
+    for (int pass = 0; pass < passes; ++pass) {
+        const float tf[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
+        const float qf[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
+        double tp[3], qp[4], Rp[9];
+        load_pose_d(tf, qf, tp, qp);
+        rot_of_quat_d(qp[0], qp[1], qp[2], qp[3], Rp);
+        double l = 0.0;
+        float acc[27];
+        for (int c = 0; c < 27; ++c) acc[c] = 0.0f;
+        for (int s = 0; s < n_nb; ++s) {
+            // Relative pose T_k^-1 T (Eq. 4) in FP64: R' = R_k^T R, t' = R_k^T (t - t_k).
+            const int k = s_nb[s][lane];
+            const size_t r = (size_t)k * 7 * N + ic;
+            const float ktf[3] = {d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]};
+            const float kqf[4] = {d.kf_pose[r + 3 * N], d.kf_pose[r + 4 * N], d.kf_pose[r + 5 * N],
+                                  d.kf_pose[r + 6 * N]};
+            double kt[3], kq[4], Rk[9], R[9], t[3], o[3];
+            load_pose_d(ktf, kqf, kt, kq);
+            rot_of_quat_d(kq[0], kq[1], kq[2], kq[3], Rk);
+            const double dt[3] = {tp[0] - kt[0], tp[1] - kt[1], tp[2] - kt[2]};
+            float Rf[9];
+            for (int row = 0; row < 3; ++row) {
+                for (int col = 0; col < 3; ++col) {
+                    R[3 * row + col] = Rk[row] * Rp[col] + Rk[3 + row] * Rp[3 + col] + Rk[6 + row] * Rp[6 + col];
+                    Rf[3 * row + col] = (float)R[3 * row + col];
+                }
+                t[row] = Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2];
+                o[row] = (double)d.origins[3 * k + row];
+            }
+            const uint64_t vbase = (uint64_t)d.cells + (uint64_t)k * (uint64_t)d.grid_stride;
+            for (int j = j0; j < j1; ++j)
+                gicp_point(R, Rf, t, o, inv_vs, d.nx, d.ny, d.nz, vbase, scan[3 * j], scan[3 * j + 1],
+                           scan[3 * j + 2], l, acc);
+        }
+        s_l[wave][lane] = l;
+        for (int c = 0; c < 27; ++c) s_h[c][wave][lane] = acc[c];
+        __syncthreads();
+        if (wave == 0) {
+            double lt = 0.0;
+            float h[27];
+            for (int c = 0; c < 27; ++c) h[c] = 0.0f;
+            for (int w = 0; w < W; ++w) {
+                lt += s_l[w][lane];
+                for (int c = 0; c < 27; ++c) h[c] += s_h[c][w][lane];
+            }
+            const bool stepping = pass < d.iters;
+            if (i < N) {
+                d.loglik[i] = (float)lt;
+                if (stepping) {
+                    for (int c = 0; c < 6; ++c) d.grad[(size_t)c * N + i] = h[21 + c];
+                    for (int c = 0; c < 21; ++c) d.hess[(size_t)c * N + i] = h[c];
+                }
+            }
+            const bool gate = !d.kf_loop || s_loop[lane] >= 0;
+            float psi[6];
+            if (stepping && gate && gn_solve(h, h + 21, psi)) {
+                float rho[3] = {psi[0], psi[1], psi[2]}, phi[3] = {psi[3], psi[4], psi[5]};
+                const float nr = sqrtf(rho[0] * rho[0] + rho[1] * rho[1] + rho[2] * rho[2]);
+                const float np = sqrtf(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
+                if (nr > d.rho_max) {
+                    const float f = d.rho_max / nr;
+                    rho[0] *= f; rho[1] *= f; rho[2] *= f;
+                }
+                if (np > d.phi_max) {
+                    const float f = d.phi_max / np;
+                    phi[0] *= f; phi[1] *= f; phi[2] *= f;
+                }
+                float t3[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
+                float q4[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
+                for (int c = 0; c < 3; ++c) {
+                    s_upd[c][lane] = rho[c];
+                    s_upd[3 + c][lane] = phi[c];
+                    s_upd[6 + c][lane] = t3[c];
+                }
+                right_exp(t3, q4, rho, phi);
+                s_pose[0][lane] = t3[0]; s_pose[1][lane] = t3[1]; s_pose[2][lane] = t3[2];
+                s_pose[3][lane] = q4[0]; s_pose[4][lane] = q4[1]; s_pose[5][lane] = q4[2];
+                s_pose[6][lane] = q4[3];
+            } else if (d.kf_loop) {
+                // No step: nothing to propagate for this particle.
+                for (int c = 0; c < 6; ++c) s_upd[c][lane] = 0.0f;
+                s_upd[6][lane] = s_pose[0][lane]; s_upd[7][lane] = s_pose[1][lane];
+                s_upd[8][lane] = s_pose[2][lane];
+            }
+        }
+        __syncthreads();
+        if (d.kf_loop && pass < d.iters) {
+            kf_propagate<W>(d, i, lane, wave, s_loop, s_upd, s_seg);
+            __syncthreads();
+        }
+    }
+    if (wave == 0) store_tile_pose(d, i, lane, s_pose);
+    __syncthreads();
+}
+
 template <int DT, bool SKIP, int W>
 __device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
 {
@@ -854,7 +1143,7 @@ __device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int N = d.N, K = d.K, n_nb = d.n_nb;
+    const int N = d.N, n_nb = d.n_nb;
     const int i = tile * 64 + lane;
     const int ic = i < N ? i : N - 1;
     const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
@@ -863,37 +1152,7 @@ __device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
     const uint64_t base = (uint64_t)d.cells;
     const scan_ptr scan = (scan_ptr)d.scan4;
 
-    if (wave == 0) {
-        load_tile_pose(d, i, lane, s_pose);
-        // Neighbour keyframes: the n_nb smallest squared distances, ties to the smaller k.
-        const float tx = s_pose[0][lane], ty = s_pose[1][lane], tz = s_pose[2][lane];
-        float bd[kKfMaxNb];
-        int bk[kKfMaxNb];
-        for (int s = 0; s < kKfMaxNb; ++s) { bd[s] = INFINITY; bk[s] = K; }
-        for (int k = 0; k < K; ++k) {
-            const size_t r = (size_t)k * 7 * N + ic;
-            const float dd = dist2_rn(tx, ty, tz, d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]);
-            // Insert (dd, k) into the sorted list; k ascending keeps ties on the smaller k.
-            float cd = dd;
-            int ck = k;
-            for (int s = 0; s < kKfMaxNb; ++s) {
-                if (s < n_nb && cd < bd[s]) {
-                    const float td = bd[s];
-                    const int tk = bk[s];
-                    bd[s] = cd; bk[s] = ck;
-                    cd = td; ck = tk;
-                }
-            }
-        }
-        // Every slot below n_nb <= K is filled (distances are finite); guard anyway.
-        for (int s = 0; s < kKfMaxNb; ++s) s_nb[s][lane] = bk[s] < K ? bk[s] : 0;
-        if (i < N)
-            for (int s = 0; s < n_nb; ++s) d.neighbors[(size_t)s * N + i] = s_nb[s][lane];
-        // Loop detection (Sec. III-C.2): an old keyframe among the neighbours.
-        int o = K;
-        for (int s = 0; s < n_nb; ++s) o = min(o, s_nb[s][lane]);
-        s_loop[lane] = (d.kf_loop && o < K - d.n_recent) ? o : -1;
-    }
+    if (wave == 0) kf_select(d, i, lane, s_pose, s_nb, s_loop);
     const int chunk = (d.M + W - 1) / W;
     const int j0 = min(d.M, wave * chunk);
     const int j1 = min(d.M, j0 + chunk);
@@ -1009,6 +1268,19 @@ __device__ __forceinline__ void pack_blk(const StepDesc &d, int b)
 {
     const int j = b * kWeightBlock + threadIdx.x;
     if (j >= d.M) return;
+    if (d.gicp) {
+        // A point with a non-finite mean or covariance is moved far outside
+        // every voxel map, so it finds no correspondence.
+        const float *c = d.cov6 + 6 * (size_t)j;
+        const float x = d.scan3[3 * j], y = d.scan3[3 * j + 1], z = d.scan3[3 * j + 2];
+        bool ok = fabsf(x) <= 1e30f && fabsf(y) <= 1e30f && fabsf(z) <= 1e30f;
+        for (int e = 0; e < 6; ++e) ok = ok && fabsf(c[e]) <= 1e30f;
+        float4 *o = d.scan_g + 3 * (size_t)j;
+        o[0] = ok ? make_float4(x, y, z, 0.0f) : make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+        o[1] = ok ? make_float4(c[0], c[1], c[2], c[3]) : make_float4(1.0f, 0.0f, 0.0f, 1.0f);
+        o[2] = ok ? make_float4(c[4], c[5], 0.0f, 0.0f) : make_float4(0.0f, 1.0f, 0.0f, 0.0f);
+        return;
+    }
     const float x = d.scan3[3 * j], y = d.scan3[3 * j + 1], z = d.scan3[3 * j + 2];
     const bool ok = fabsf(x) <= 1e30f && fabsf(y) <= 1e30f && fabsf(z) <= 1e30f;
     const float4 v = ok ? make_float4(x, y, z, 0.0f) : make_float4(1e30f, 1e30f, 1e30f, 0.0f);
@@ -1535,6 +1807,12 @@ __global__ __launch_bounds__(64 * W) void k_kf_eval(StepDesc d)
     kf_tile<DT, SKIP, W>(d, blockIdx.x);
 }
 
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_gicp_eval(StepDesc d)
+{
+    gicp_tile<W>(d, blockIdx.x);
+}
+
 __global__ __launch_bounds__(kWeightBlock) void k_weights(StepDesc d) { weights_blk(d, blockIdx.x); }
 __global__ __launch_bounds__(kWeightBlock) void k_wcombine(StepDesc d) { wcombine_blk(d); }
 __global__ __launch_bounds__(kWeightBlock) void k_normscan(StepDesc d) { normscan_blk(d, blockIdx.x); }
@@ -1587,6 +1865,7 @@ __global__ __launch_bounds__(64 * W) void kb_eval(BatchTables t)
 
 constexpr int kEvalW = 4, kEvalU = 2;   // waves per workgroup, points per batch
 constexpr int kKfW = 4;
+constexpr int kGicpW = 4;
 
 hipError_t launch_build_cells(const float *grid, void *cells, int nx, int ny, int nz, int dtype,
                               hipStream_t st)
@@ -1649,6 +1928,11 @@ static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st)
 hipError_t launch_eval(const StepDesc &d, hipStream_t st)
 {
     if (!eval_supported(d)) return hipErrorInvalidValue;
+    if (d.gicp) {
+        hipLaunchKernelGGL((k_gicp_eval<kGicpW>), dim3((unsigned)particle_tiles(d.N)), dim3(64 * kGicpW),
+                           0, st, d);
+        return hipGetLastError();
+    }
     const bool skip = d.oob_skip != 0;
     switch (d.dtype) {
     case 0: return skip ? launch_eval_dt<0, true>(d, st) : launch_eval_dt<0, false>(d, st);

@@ -44,7 +44,7 @@ struct Layout {
     size_t total;
 };
 
-Layout session_layout(int N, int M_max, int K)
+Layout session_layout(int N, int M_max, int K, bool gicp)
 {
     const size_t n = (size_t)N, nb = (size_t)weight_blocks(N);
     const size_t sizes[] = {
@@ -65,6 +65,9 @@ Layout session_layout(int N, int M_max, int K)
         sizeof(StepStatsDev),       // 14 stats
         (size_t)M_max * 32,         // 15 scan8
         n * 4,                      // 16 copies
+        (gicp ? (size_t)M_max * kVoxelRecordBytes : 0),   // 17 scan_g
+        (gicp ? (size_t)M_max * 6 * 4 : 0),                // 18 cov6
+        (gicp ? 21 * n * 4 : 0),                           // 19 hess
     };
     Layout L{};
     size_t o = 0;
@@ -256,12 +259,18 @@ mcs_status validate_params(const Session *s, const mcs_step_params *p, int M)
 
 // The device-side description of one step of session s.
 StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float *noise_dev,
-                   const mcs_step_params *p)
+                   const mcs_step_params *p, const float *cov_dev)
 {
     const Map *m = s->map;
     StepDesc d{};
     d.cells = m->cells;
-    d.grid_stride = (int64_t)align_up((size_t)m->records * record_bytes(m->desc.dtype));
+    d.grid_stride = (int64_t)align_up((size_t)m->records * (m->kind == kVoxelMap
+                                                                ? kVoxelRecordBytes
+                                                                : record_bytes(m->desc.dtype)));
+    d.gicp = m->kind == kVoxelMap;
+    d.cov6 = cov_dev;
+    d.scan_g = s->scan_g;
+    d.hess = s->hess;
     d.origins = m->origins_dev;
     d.nx = m->desc.nx; d.ny = m->desc.ny; d.nz = m->desc.nz;
     d.dtype = m->desc.dtype;
@@ -323,9 +332,13 @@ mcs_status prof_begin(Session *s, std::array<hipEvent_t, 5> *&ev)
 
 // The step sequence of one session on stream st.
 mcs_status enqueue_step(Session *s, const float *scan3_dev, int M, const float *noise_dev,
-                        const mcs_step_params *p, hipStream_t st)
+                        const mcs_step_params *p, hipStream_t st, const float *cov_dev)
 {
-    const StepDesc d = make_desc(s, scan3_dev, M, noise_dev, p);
+    if ((s->map->kind == kVoxelMap) != (cov_dev != nullptr))
+        return fail(MCS_EINVAL, s->map->kind == kVoxelMap
+                                    ? "a GICP map needs scan covariances (mcs_filter_step_gicp*)"
+                                    : "scan covariances are for GICP maps only");
+    const StepDesc d = make_desc(s, scan3_dev, M, noise_dev, p, cov_dev);
     if (!eval_supported(d)) return fail(MCS_EINVAL, "map or neighbour count not supported");
     std::array<hipEvent_t, 5> *ev = nullptr;
     mcs_status ps = prof_begin(s, ev);
@@ -449,6 +462,74 @@ mcs_status mcs_load_keyframes(mcs_ctx *ctx, int32_t K, const mcs_grid_desc *desc
     return build_map(ctx, K, descs, values, map_id);
 }
 
+mcs_status mcs_load_gicp_keyframes(mcs_ctx *ctx, int32_t K, const mcs_voxel_desc *descs,
+                                   const float *const *voxels, int32_t *map_id)
+{
+    if (!ctx || !descs || !voxels || !map_id) return fail(MCS_EINVAL, "NULL argument");
+    if (K < 1) return fail(MCS_EINVAL, "K must be >= 1");
+    const mcs_voxel_desc &d0 = descs[0];
+    for (int k = 0; k < K; ++k) {
+        const mcs_voxel_desc &d = descs[k];
+        if (d.nx < 1 || d.ny < 1 || d.nz < 1 || d.nx > (1 << 16) || d.ny > (1 << 16) || d.nz > (1 << 16))
+            return fail(MCS_EINVAL, "voxel map %d: dims outside [1, 65536]", k);
+        if (!(d.edge > 0.0f) || !std::isfinite(d.edge)) return fail(MCS_EINVAL, "voxel map %d: bad edge", k);
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(d.origin[a])) return fail(MCS_EINVAL, "voxel map %d: bad origin", k);
+        if (d.nx != d0.nx || d.ny != d0.ny || d.nz != d0.nz || d.edge != d0.edge)
+            return fail(MCS_EINVAL, "voxel map %d differs in shape or edge", k);
+        if (!voxels[k]) return fail(MCS_EINVAL, "voxel map %d is NULL", k);
+    }
+    mcs_status s = set_device(ctx);
+    if (s != MCS_OK) return s;
+    const int64_t recs = (int64_t)d0.nx * d0.ny * d0.nz;
+    const size_t map_bytes = (size_t)recs * kVoxelRecordBytes;
+    const size_t total = align_up(map_bytes) * K + align_up((size_t)K * 3 * sizeof(float));
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!budget_allows(ctx, total))
+            return fail(MCS_EBUDGET, "map needs %zu bytes; budget %llu, in use %llu", total,
+                        (unsigned long long)ctx->budget, (unsigned long long)ctx->in_use);
+        ctx->in_use += total;
+    }
+    Map *m = new Map;
+    m->kind = kVoxelMap;
+    m->K = K;
+    m->desc.nx = d0.nx; m->desc.ny = d0.ny; m->desc.nz = d0.nz;
+    for (int a = 0; a < 3; ++a) m->desc.origin[a] = d0.origin[a];
+    m->desc.res = d0.edge;
+    m->desc.dtype = MCS_GRID_FP32;
+    m->records = recs;
+    m->bytes = total;
+    for (int k = 0; k < K; ++k)
+        for (int a = 0; a < 3; ++a) m->origins.push_back(descs[k].origin[a]);
+    hipError_t e = hipMalloc(&m->cells, total);
+    if (e == hipSuccess) {
+        m->origins_dev = reinterpret_cast<float *>((char *)m->cells + align_up(map_bytes) * K);
+        for (int k = 0; k < K && e == hipSuccess; ++k)
+            e = hipMemcpy((char *)m->cells + align_up(map_bytes) * k, voxels[k], map_bytes,
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(m->origins_dev, m->origins.data(), (size_t)K * 3 * sizeof(float),
+                          hipMemcpyHostToDevice);
+    } else {
+        m->cells = nullptr;
+    }
+    if (e != hipSuccess) {
+        if (m->cells) (void)hipFree(m->cells);
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->in_use -= total;
+        }
+        delete m;
+        return hip_fail(e, "voxel map upload");
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    m->id = ctx->next_id++;
+    ctx->maps[m->id] = m;
+    *map_id = m->id;
+    return MCS_OK;
+}
+
 mcs_status mcs_release_map(mcs_ctx *ctx, int32_t map_id)
 {
     if (!ctx) return fail(MCS_EINVAL, "NULL context");
@@ -475,13 +556,15 @@ mcs_status mcs_session_bytes(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M_
     if (!ctx || !bytes) return fail(MCS_EINVAL, "NULL argument");
     if (N < 1 || M_max < 1) return fail(MCS_EINVAL, "N and M_max must be >= 1");
     int K = 0;
+    bool gicp = false;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         auto it = ctx->maps.find(map_id);
         if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
         K = it->second->K;
+        gicp = it->second->kind == kVoxelMap;
     }
-    *bytes = session_layout(N, M_max, K).total;
+    *bytes = session_layout(N, M_max, K, gicp).total;
     return MCS_OK;
 }
 
@@ -503,7 +586,7 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
         if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
         m = it->second;
         if (m->K > 0 && !kf_poses) return fail(MCS_EINVAL, "keyframe map needs kf_poses");
-        L = session_layout(N, M_max, m->K);
+        L = session_layout(N, M_max, m->K, m->kind == kVoxelMap);
         Lp = &L;
         if (!budget_allows(ctx, L.total))
             return fail(MCS_EBUDGET, "session needs %zu bytes; budget %llu, in use %llu", L.total,
@@ -558,6 +641,11 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
     ss->stats = (StepStatsDev *)(b + L.off[14]);
     ss->scan8 = (double4 *)(b + L.off[15]);
     ss->copies = (int32_t *)(b + L.off[16]);
+    if (m->kind == kVoxelMap) {
+        ss->scan_g = (float4 *)(b + L.off[17]);
+        ss->cov6 = (float *)(b + L.off[18]);
+        ss->hess = (float *)(b + L.off[19]);
+    }
     e = hipMemsetAsync(ss->block, 0, L.total, ss->stream);
     if (e != hipSuccess) return undo(hip_fail(e, "hipMemset(session)"));
     // Initial state: poses, uniform log-weights, identity parents.
@@ -640,23 +728,37 @@ mcs_status mcs_set_particles(mcs_ctx *ctx, int32_t sid, const float *poses, cons
     return MCS_OK;
 }
 
-mcs_status mcs_filter_step(mcs_ctx *ctx, int32_t sid, const float *scan, int32_t M,
-                           const float *noise, const mcs_step_params *p)
+}  // extern "C"
+
+namespace {
+
+// A step on host inputs: stage scan (and covariances, noise) through pinned
+// memory on the session's stream, then enqueue the step.
+mcs_status filter_step_host(mcs_ctx *ctx, int32_t sid, const float *scan, const float *cov, int32_t M,
+                            const float *noise, const mcs_step_params *p)
 {
     if (!ctx || !scan) return fail(MCS_EINVAL, "NULL argument");
     Session *s = find_session(ctx, sid);
     if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
     mcs_status st = validate_params(s, p, M);
     if (st != MCS_OK) return st;
+    if ((s->map->kind == kVoxelMap) != (cov != nullptr))
+        return fail(MCS_EINVAL, s->map->kind == kVoxelMap
+                                    ? "a GICP map needs scan covariances (mcs_filter_step_gicp)"
+                                    : "scan covariances are for GICP maps only");
     for (int64_t k = 0; k < (int64_t)M * 3; ++k)
         if (!std::isfinite(scan[k])) return fail(MCS_EINVAL, "scan value %lld not finite", (long long)k);
+    if (cov)
+        for (int64_t k = 0; k < (int64_t)M * 6; ++k)
+            if (!std::isfinite(cov[k])) return fail(MCS_EINVAL, "covariance value %lld not finite", (long long)k);
     const bool use_noise = p->predict && noise && p->noise_mode == MCS_NOISE_INPUT;
     if (use_noise)
         for (int64_t k = 0; k < (int64_t)s->N * 6; ++k)
             if (!std::isfinite(noise[k])) return fail(MCS_EINVAL, "noise value not finite");
     if ((st = set_device(ctx)) != MCS_OK) return st;
     // Stage through pinned host memory; wait for the previous upload from it.
-    const size_t need = (size_t)M * 3 + (use_noise ? (size_t)s->N * 6 : 0);
+    const size_t n_scan = (size_t)M * 3, n_cov = cov ? (size_t)M * 6 : 0;
+    const size_t need = n_scan + n_cov + (use_noise ? (size_t)s->N * 6 : 0);
     if (s->staged_pending) HIP_TRY(hipEventSynchronize(s->staged), "wait staging");
     s->staged_pending = false;
     if (s->pinned_floats < need) {
@@ -667,21 +769,27 @@ mcs_status mcs_filter_step(mcs_ctx *ctx, int32_t sid, const float *scan, int32_t
                 "hipHostMalloc");
         s->pinned_floats = need;
     }
-    std::memcpy(s->pinned, scan, (size_t)M * 3 * sizeof(float));
-    HIP_TRY(hipMemcpyAsync(s->scan3, s->pinned, (size_t)M * 3 * sizeof(float),
-                           hipMemcpyHostToDevice, s->stream), "upload scan");
+    std::memcpy(s->pinned, scan, n_scan * sizeof(float));
+    HIP_TRY(hipMemcpyAsync(s->scan3, s->pinned, n_scan * sizeof(float), hipMemcpyHostToDevice,
+                           s->stream), "upload scan");
+    if (cov) {
+        std::memcpy(s->pinned + n_scan, cov, n_cov * sizeof(float));
+        HIP_TRY(hipMemcpyAsync(s->cov6, s->pinned + n_scan, n_cov * sizeof(float),
+                               hipMemcpyHostToDevice, s->stream), "upload covariances");
+    }
     if (use_noise) {
-        std::memcpy(s->pinned + (size_t)M * 3, noise, (size_t)s->N * 6 * sizeof(float));
-        HIP_TRY(hipMemcpyAsync(s->noise, s->pinned + (size_t)M * 3, (size_t)s->N * 6 * sizeof(float),
+        std::memcpy(s->pinned + n_scan + n_cov, noise, (size_t)s->N * 6 * sizeof(float));
+        HIP_TRY(hipMemcpyAsync(s->noise, s->pinned + n_scan + n_cov, (size_t)s->N * 6 * sizeof(float),
                                hipMemcpyHostToDevice, s->stream), "upload noise");
     }
     HIP_TRY(hipEventRecord(s->staged, s->stream), "event");
     s->staged_pending = true;
-    return enqueue_step(s, s->scan3, M, use_noise ? s->noise : nullptr, p, s->stream);
+    return enqueue_step(s, s->scan3, M, use_noise ? s->noise : nullptr, p, s->stream,
+                        cov ? s->cov6 : nullptr);
 }
 
-mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev, int32_t M,
-                               const float *noise_dev, const mcs_step_params *p, void *stream)
+mcs_status filter_step_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev, const float *cov_dev,
+                           int32_t M, const float *noise_dev, const mcs_step_params *p, void *stream)
 {
     if (!ctx || !scan_dev) return fail(MCS_EINVAL, "NULL argument");
     Session *s = find_session(ctx, sid);
@@ -690,7 +798,63 @@ mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev,
     if (st != MCS_OK) return st;
     if ((st = set_device(ctx)) != MCS_OK) return st;
     hipStream_t hs = stream ? (hipStream_t)stream : s->stream;
-    return enqueue_step(s, scan_dev, M, p->predict ? noise_dev : nullptr, p, hs);
+    return enqueue_step(s, scan_dev, M, p->predict ? noise_dev : nullptr, p, hs, cov_dev);
+}
+
+}  // namespace
+
+extern "C" {
+
+mcs_status mcs_filter_step(mcs_ctx *ctx, int32_t sid, const float *scan, int32_t M,
+                           const float *noise, const mcs_step_params *p)
+{
+    return filter_step_host(ctx, sid, scan, nullptr, M, noise, p);
+}
+
+mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev, int32_t M,
+                               const float *noise_dev, const mcs_step_params *p, void *stream)
+{
+    return filter_step_dev(ctx, sid, scan_dev, nullptr, M, noise_dev, p, stream);
+}
+
+mcs_status mcs_filter_step_gicp(mcs_ctx *ctx, int32_t sid, const float *mu, const float *cov,
+                                int32_t M, const float *noise, const mcs_step_params *p)
+{
+    if (!cov) return fail(MCS_EINVAL, "NULL covariances");
+    return filter_step_host(ctx, sid, mu, cov, M, noise, p);
+}
+
+mcs_status mcs_filter_step_gicp_dev(mcs_ctx *ctx, int32_t sid, const float *mu_dev,
+                                    const float *cov_dev, int32_t M, const float *noise_dev,
+                                    const mcs_step_params *p, void *stream)
+{
+    if (!cov_dev) return fail(MCS_EINVAL, "NULL covariances");
+    return filter_step_dev(ctx, sid, mu_dev, cov_dev, M, noise_dev, p, stream);
+}
+
+mcs_status mcs_get_gicp_system(mcs_ctx *ctx, int32_t sid, float *H, float *b)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    if (s->map->kind != kVoxelMap) return fail(MCS_EINVAL, "session %d has no GICP map", sid);
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    const size_t N = s->N;
+    if (H) {
+        std::vector<float> soa(21 * N);
+        HIP_TRY(hipMemcpy(soa.data(), s->hess, soa.size() * 4, hipMemcpyDeviceToHost), "hess");
+        for (size_t i = 0; i < N; ++i)
+            for (int c = 0; c < 21; ++c) H[21 * i + c] = soa[c * N + i];
+    }
+    if (b) {
+        std::vector<float> soa(6 * N);
+        HIP_TRY(hipMemcpy(soa.data(), s->grad, soa.size() * 4, hipMemcpyDeviceToHost), "b");
+        for (size_t i = 0; i < N; ++i)
+            for (int c = 0; c < 6; ++c) b[6 * i + c] = soa[c * N + i];
+    }
+    return MCS_OK;
 }
 
 mcs_status mcs_get_neighbors(mcs_ctx *ctx, int32_t sid, int32_t *out, int32_t *n_neighbors)

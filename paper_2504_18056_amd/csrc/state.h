@@ -27,14 +27,18 @@ constexpr int kMaxNeighbors = 8;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 inline size_t record_bytes(int dtype) { return dtype == MCS_GRID_FP32 ? 32 : 16; }
 
+enum MapKind { kGridMap = 0, kVoxelMap = 1 };
+constexpr size_t kVoxelRecordBytes = 48;   // mean (3), count, covariance (6), 2 unused
+
 struct Map {
     int id = 0;
+    int kind = kGridMap;             // likelihood grids, or GICP voxel Gaussians
     int K = 0;                       // 0: single grid; >0: keyframe grids
     mcs_grid_desc desc{};            // dims, res, dtype (origin of grid 0)
     std::vector<float> origins;      // K x 3 (or 1 x 3)
     void *cells = nullptr;
     size_t bytes = 0;
-    int64_t records = 0;             // per grid
+    int64_t records = 0;             // per grid (cells or voxels)
     float *origins_dev = nullptr;
     int users = 0;
 };
@@ -53,6 +57,9 @@ struct Session {
     double *logw = nullptr, *cdf_local = nullptr, *part = nullptr;
     int32_t *parents = nullptr, *neighbors = nullptr, *copies = nullptr;
     StepStatsDev *stats = nullptr;
+    float4 *scan_g = nullptr;        // GICP: packed points and covariances
+    float *cov6 = nullptr;           // GICP: uploaded covariances (host-pointer steps)
+    float *hess = nullptr;           // GICP: [21][N] Gauss-Newton H
     float *pinned = nullptr;         // host staging for host-pointer steps
     size_t pinned_floats = 0;
     int last_nb = 0;                 // neighbours per particle in the last keyframe step
@@ -86,8 +93,8 @@ mcs_status set_device(mcs_ctx *ctx);
 Session *find_session(mcs_ctx *ctx, int32_t sid);
 mcs_status validate_params(const Session *s, const mcs_step_params *p, int M);
 StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float *noise_dev,
-                   const mcs_step_params *p);
+                   const mcs_step_params *p, const float *cov_dev = nullptr);
 mcs_status enqueue_step(Session *s, const float *scan3_dev, int M, const float *noise_dev,
-                        const mcs_step_params *p, hipStream_t st);
+                        const mcs_step_params *p, hipStream_t st, const float *cov_dev = nullptr);
 
 }  // namespace mcs

@@ -366,7 +366,8 @@ def keyframe_grid(points, grid_n, h, sigma, cutoff_sigmas=6.0):
 
 def keyframes(N=50000, K=64, kf_points=16384, M_rings=32, n_az=64, grid_n=128, h=0.2,
               sigma=0.1, n_nb=4, seed=1003, kf_drift=(0.05, 0.5), ambiguous=False,
-              out_and_back=False, grid_dtype=GRID_FP32, workers=8):
+              out_and_back=False, grid_dtype=GRID_FP32, workers=8, gicp=False, vox_n=64,
+              vox_edge=0.4):
     """Keyframe-map workload: K keyframes along a corridor trajectory.
 
     Each keyframe scan (kf_points rays, 64 rings over [-15, 15] deg) is
@@ -378,6 +379,9 @@ def keyframes(N=50000, K=64, kf_points=16384, M_rings=32, n_az=64, grid_n=128, h
     With out_and_back=True the path turns round half way and retraces itself, so
     the current frame is back at the start: its neighbour keyframes include the
     oldest ones (a loop) as well as the newest.
+    With gicp=True each keyframe is also voxelised into vox_n^3 voxel
+    Gaussians of edge vox_edge centred on the keyframe (synth.gicp), and the
+    current scan gets per-point covariances (10 nearest neighbours).
     """
     rng = np.random.default_rng(seed)
     if ambiguous:
@@ -401,14 +405,20 @@ def keyframes(N=50000, K=64, kf_points=16384, M_rings=32, n_az=64, grid_n=128, h
     els_kf = np.linspace(-15.0, 15.0, n_kf_rings)
     from concurrent.futures import ThreadPoolExecutor
 
+    from . import gicp as gicp_inputs
+    vox_origin = -0.5 * vox_n * vox_edge
+
     def kf_one(k):
         f = kf_frames[k]
         pts = lidar_scan(scene, t_traj[f], q_traj[f], els_kf, kf_az, 60.0, 0.02,
                          np.random.default_rng([seed, 11, k]))
-        return keyframe_grid(pts, grid_n, h, sigma)
+        vox = (gicp_inputs.voxel_gaussians(pts, (vox_n,) * 3, (vox_origin,) * 3, vox_edge)
+               if gicp else None)
+        return keyframe_grid(pts, grid_n, h, sigma), vox
 
     with ThreadPoolExecutor(max_workers=workers) as ex:
-        grids = np.stack(list(ex.map(kf_one, range(K))))
+        made = list(ex.map(kf_one, range(K)))
+    grids = np.stack([m[0] for m in made])
     scan = lidar_scan(scene, t_traj[cur], q_traj[cur], np.linspace(-15.0, 15.0, M_rings), n_az,
                       60.0, 0.02, np.random.default_rng([seed, 12]))
     prng = np.random.default_rng(seed + 1)
@@ -420,7 +430,13 @@ def keyframes(N=50000, K=64, kf_points=16384, M_rings=32, n_az=64, grid_n=128, h
     origin = -0.5 * grid_n * h
     params = step_params(scan, h, sigma, iters=3)
     params["n_neighbors"] = n_nb
+    extra = {}
+    if gicp:
+        extra = dict(vox=np.stack([m[1] for m in made]), vox_dims=(vox_n,) * 3,
+                     vox_origins=np.full((K, 3), vox_origin), vox_edge=vox_edge,
+                     scan_cov=gicp_inputs.point_covariances(scan))
     return dict(
+        **extra,
         name="keyframes", grids=grids, dims=(grid_n,) * 3, origins=np.full((K, 3), origin),
         h=h, sigma=sigma, grid_dtype=grid_dtype, scan=scan, poses=poses, kf_poses=kf,
         logw=np.full(N, -math.log(N)), params=params, u=float(splitmix64_uniforms(seed + 2, 1)[0]),
@@ -537,3 +553,73 @@ def poisson_arrivals(rate_hz, duration_s, rng):
         if t >= duration_s:
             return np.array(out)
         out.append(t)
+
+
+# ---------------------------------------------------------------------------
+# repeated floors: a kidnapped start over identical storeys
+# ---------------------------------------------------------------------------
+
+def repeated_floors(N=20000, floors=4, true_floor=2, n_frames=80, M_rings=8, n_az=64, seed=1006,
+                    grid=(256, 256, 128), h=0.2, sigma=0.1, storey=4.0, feature_frame=0.6,
+                    rmax=10.0, min_blind=10, grid_dtype=GRID_FP32):
+    """A building of `floors` identical storeys (the same maze level copied every
+    `storey` metres), except one box that stands only on the true floor, next
+    to the path at the fraction `feature_frame` of the trajectory.  The sensor
+    moves on the true floor; the particles start kidnapped: their storey is
+    drawn uniformly, the rest is the true start pose with 0.3 m / 3 deg of
+    spread.  Until the box comes into view every storey explains the scans
+    equally well.  The range sensor reaches rmax metres."""
+    rng = np.random.default_rng(seed)
+    size_xy, size_z = grid[0] * h, grid[2] * h
+    cells = int(size_xy // 5.0) - 1
+    level = corridor_scene(rng, cells=cells, cell=5.0, size_xy=size_xy, size_z=size_z, floor_z=1.0,
+                           ceil_z=1.0 + storey - 1.0, n_boxes=4 * cells)
+    lo, hi, planes = [], [], []
+    for f in range(floors):
+        dz = f * storey
+        lo.append(level.lo + [0.0, 0.0, dz])
+        hi.append(level.hi + [0.0, 0.0, dz])
+        planes += [1.0 + dz, 1.0 + dz + storey - 1.0]
+    z_true = 2.5 + true_floor * storey
+    t_traj, q_traj = maze_trajectory(level, rng, n_frames=n_frames, z=z_true)
+    # The distinguishing box: beside the path on the true floor only, at the
+    # first frame from `feature_frame` on whose box no scan of the first
+    # `min_blind` frames sees; `first_seen` is the first frame that does.
+    els = np.linspace(-15.0, 15.0, M_rings)
+    vol = ([0.0, 0.0, 0.0], [size_xy, size_xy, size_z])
+    plain = Scene(np.vstack(lo), np.vstack(hi), planes, *vol)
+    scans_plain = frame_scans(plain, t_traj, q_traj, els, n_az, rmax, 0.02, seed)
+    base = 1.0 + true_floor * storey
+    scene = None
+    for cand in range(int(feature_frame * (n_frames - 1)), n_frames - 2):
+        side = geo.quat_to_matrix(q_traj[cand])[:, 1]
+        c = t_traj[cand, :2] + 1.2 * side[:2] / max(1e-9, np.linalg.norm(side[:2]))
+        trial = Scene(np.vstack(lo + [[[c[0] - 0.35, c[1] - 0.35, base]]]),
+                      np.vstack(hi + [[[c[0] + 0.35, c[1] + 0.35, base + 1.8]]]), planes, *vol)
+        scans = frame_scans(trial, t_traj, q_traj, els, n_az, rmax, 0.02, seed)
+        differs = [f for f in range(n_frames) if not np.array_equal(scans[f], scans_plain[f])]
+        if differs and differs[0] >= min_blind:
+            scene, fk, first_seen = trial, cand, differs[0]
+            break
+    if scene is None:
+        raise ValueError("no place for the distinguishing box that stays unseen; try another seed")
+    G = scene.likelihood_grid(grid, (0.0, 0.0, 0.0), h, sigma)
+    odo = np.zeros((n_frames, 7), np.float32)
+    odo[0] = [0, 0, 0, 1, 0, 0, 0]
+    for f in range(1, n_frames):
+        dt, dq = relative_motion(t_traj[f - 1], q_traj[f - 1], t_traj[f], q_traj[f])
+        dt = dt + rng.normal(0.0, 0.01, 3)
+        dq = geo.quat_mul(dq, geo.quat_from_axis_angle(rng.normal(0.0, math.radians(0.2), 3)))
+        odo[f] = np.concatenate([dt, dq / np.linalg.norm(dq)])
+    prng = np.random.default_rng(seed + 1)
+    poses = gaussian_particles(t_traj[0], q_traj[0], N, 0.3, 3.0, prng)
+    floor_of = prng.integers(0, floors, N)
+    poses[:, 2] += ((floor_of - true_floor) * storey).astype(np.float32)
+    params = step_params(scans[0], h, sigma, iters=2)
+    return dict(name="repeated_floors", grid=G, dims=tuple(grid), origin=(0.0, 0.0, 0.0), h=h,
+                sigma=sigma, grid_dtype=grid_dtype, scans=scans, poses=poses,
+                logw=np.full(N, -math.log(N)), params=params, odometry=odo,
+                u=splitmix64_uniforms(seed + 2, n_frames), t_traj=t_traj, q_traj=q_traj,
+                floors=floors, true_floor=true_floor, storey=storey, feature_frame=fk,
+                first_seen=first_seen,
+                floor_of_start=floor_of, scene=scene)

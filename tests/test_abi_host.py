@@ -50,26 +50,22 @@ def test_version_and_error_strings(lib):
 
 
 def test_struct_layouts_match_header():
-    """Compile a C probe of sizeof/offsetof against the header and compare with ctypes."""
+    """Compile a C probe of sizeof/offsetof of every field against the header and
+    compare with the ctypes structures of the binding."""
     import ctypes as C
 
     from paper_2504_18056_amd import abi
-    probe = r'''
-#include <stdio.h>
-#include <stddef.h>
-#include "mcslam.h"
-#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
-int main(void) {
-  printf("mcs_grid_desc %zu\n", sizeof(mcs_grid_desc));
-  printf("mcs_step_params %zu\n", sizeof(mcs_step_params));
-  printf("mcs_step_stats %zu\n", sizeof(mcs_step_stats));
-  F(mcs_grid_desc, origin) F(mcs_grid_desc, res) F(mcs_grid_desc, dtype)
-  F(mcs_step_params, oob) F(mcs_step_params, ess_frac) F(mcs_step_params, u)
-  F(mcs_step_params, predict) F(mcs_step_params, delta_T) F(mcs_step_params, n_neighbors)
-  F(mcs_step_stats, resampled) F(mcs_step_stats, best_pose) F(mcs_step_stats, degenerate)
-  return 0;
-}
-'''
+    structs = {"mcs_grid_desc": abi.GridDesc, "mcs_voxel_desc": abi.VoxelDesc,
+               "mcs_step_params": abi.StepParams, "mcs_step_stats": abi.StepStats,
+               "mcs_profile": abi.Profile, "mcs_request_times": abi.RequestTimes,
+               "mcs_server_stats": abi.ServerStats}
+    body = []
+    for name, cls in structs.items():
+        body.append('  printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for field, _ in cls._fields_:
+            body.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, field, name, field))
+    probe = "#include <stdio.h>\n#include <stddef.h>\n#include \"mcslam.h\"\nint main(void) {\n%s\n  return 0;\n}\n" % (
+        "\n".join(body))
     with tempfile.TemporaryDirectory() as d:
         src = os.path.join(d, "p.c")
         exe = os.path.join(d, "p")
@@ -77,15 +73,10 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
         lines = subprocess.run([exe], stdout=subprocess.PIPE, text=True, check=True).stdout.split("\n")
     got = dict(line.rsplit(" ", 1) for line in lines if line)
-    assert int(got["mcs_grid_desc"]) == C.sizeof(abi.GridDesc)
-    assert int(got["mcs_step_params"]) == C.sizeof(abi.StepParams)
-    assert int(got["mcs_step_stats"]) == C.sizeof(abi.StepStats)
-    for key, val in got.items():
-        if "." in key:
-            sname, field = key.split(".")
-            cls = {"mcs_grid_desc": abi.GridDesc, "mcs_step_params": abi.StepParams,
-                   "mcs_step_stats": abi.StepStats}[sname]
-            assert getattr(cls, field).offset == int(val), key
+    for name, cls in structs.items():
+        assert int(got[name]) == C.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert getattr(cls, field).offset == int(got["%s.%s" % (name, field)]), (name, field)
 
 
 def test_create_without_gpu_reports_an_error(lib):
