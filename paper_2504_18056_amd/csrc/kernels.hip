@@ -490,6 +490,7 @@ typedef const __attribute__((address_space(4))) d4v *scan64_ptr;
 struct GridMap64 {
     double A[9];
     double b[3];
+    uint32_t base;         // byte offset of the grid in the record buffer (keyframe maps)
 };
 
 __device__ __forceinline__ void grid_map64(const float *t, const float *q, double ox, double oy,
@@ -505,6 +506,7 @@ __device__ __forceinline__ void grid_map64(const float *t, const float *q, doubl
     m.b[0] = ((double)t[0] - ox) * ih - 0.5;
     m.b[1] = ((double)t[1] - oy) * ih - 0.5;
     m.b[2] = ((double)t[2] - oz) * ih - 0.5;
+    m.base = 0;
 }
 
 // floor(x) as int32 in one instruction (saturating for out-of-range x).
@@ -516,7 +518,7 @@ __device__ __forceinline__ int cvt_floor_d(double x)
     return r;
 }
 
-template <int DT, bool BIG>
+template <int DT, bool BIG, bool KF = false>
 __device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, double px,
                                            double py, double pz)
 {
@@ -535,11 +537,12 @@ __device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, 
     const uint32_t rec = BIG ? (uint32_t)ix + g.cx * (uint32_t)iy + g.cxy * (uint32_t)iz
                              : (uint32_t)ix + __umul24(g.cx, (uint32_t)iy) +
                                    __umul24(g.cxy, (uint32_t)iz);
-    p.off = p.inside ? (rec << record_shift<DT>()) : kOutside;
+    p.off = p.inside ? (KF ? gm.base + (rec << record_shift<DT>()) : (rec << record_shift<DT>()))
+                     : kOutside;
     return p;
 }
 
-template <int DT, bool BIG, bool SKIP, int U>
+template <int DT, bool BIG, bool SKIP, int U, bool KF = false>
 __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, int j0, int j1,
                                              const GridMap64 &gm, Acc &acc)
 {
@@ -551,7 +554,7 @@ __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, in
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const d4v s = scan[j + k];
-            p[k] = prep_point64<DT, BIG>(g, gm, s.x, s.y, s.z);
+            p[k] = prep_point64<DT, BIG, KF>(g, gm, s.x, s.y, s.z);
             load_cell<DT>(g.rs, p[k].off, c[k]);
         }
 #pragma unroll
@@ -559,7 +562,7 @@ __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, in
     }
     for (; j < j1; ++j) {
         const d4v s = scan[j];
-        const Pt p = prep_point64<DT, BIG>(g, gm, s.x, s.y, s.z);
+        const Pt p = prep_point64<DT, BIG, KF>(g, gm, s.x, s.y, s.z);
         Cell<DT> c;
         load_cell<DT>(g.rs, p.off, c);
         accumulate1<DT, SKIP>(g, p, c, acc);
@@ -1118,6 +1121,108 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
                 s_upd[6][lane] = s_pose[0][lane]; s_upd[7][lane] = s_pose[1][lane];
                 s_upd[8][lane] = s_pose[2][lane];
             }
+        }
+        __syncthreads();
+        if (d.kf_loop && pass < d.iters) {
+            kf_propagate<W>(d, i, lane, wave, s_loop, s_upd, s_seg);
+            __syncthreads();
+        }
+    }
+    if (wave == 0) store_tile_pose(d, i, lane, s_pose);
+    __syncthreads();
+}
+
+// Keyframe tile with the single-grid point loop: all K keyframe grids sit in
+// one buffer (the maps must fit its 32-bit range), each lane adds the byte
+// offset of its neighbour's grid to the record offsets, and an outside point
+// still reads zeros past the buffer's end.  Every wave builds the relative
+// grid maps itself (FP64, per neighbour), so no map is held in LDS.
+template <int DT, bool SKIP, int W, int U>
+__device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
+{
+    __shared__ double s_l[W][64];
+    __shared__ float s_g[6][W][64];
+    __shared__ float s_pose[7][64];
+    __shared__ int s_nb[kKfMaxNb][64];
+    __shared__ int s_loop[64];
+    __shared__ float s_upd[9][64];
+    __shared__ float s_seg[W][64];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int N = d.N, n_nb = d.n_nb;
+    const int i = tile * 64 + lane;
+    const int ic = i < N ? i : N - 1;
+    GridK g;
+    const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
+    g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
+                                             (int)((uint32_t)d.grid_stride * (uint32_t)d.K), kRsrcWord3);
+    g.nxm = cxn; g.nym = cyn; g.nzm = czn;
+    g.cx = cxn;
+    g.cxy = cxn * cyn;
+    g.eps = d.eps;
+    const double ih = 1.0 / (double)d.h;
+
+    if (wave == 0) kf_select(d, i, lane, s_pose, s_nb, s_loop);
+    const int chunk = (d.M + W - 1) / W;
+    const int j0 = min(d.M, wave * chunk);
+    const int j1 = min(d.M, j0 + chunk);
+    const int passes = d.iters + d.post_eval;
+    __syncthreads();
+
+    for (int pass = 0; pass < passes; ++pass) {
+        double l = 0.0;
+        float gsum[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (int s = 0; s < n_nb; ++s) {
+            // The particle's pose is re-read from LDS per neighbour so that it
+            // holds no registers during the point loop.
+            const float tf[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
+            const float qf[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
+            double tp[3], qp[4], Rp[9];
+            load_pose_d(tf, qf, tp, qp);
+            rot_of_quat_d(qp[0], qp[1], qp[2], qp[3], Rp);
+            // Relative pose T_k^-1 T (Eq. 4): R' = R_k^T R, t' = R_k^T (t - t_k), as the grid
+            // map A' = R'/h, b' = (t' - o_k)/h - 1/2 of keyframe k's grid.
+            const int k = s_nb[s][lane];
+            const size_t r = (size_t)k * 7 * N + ic;
+            const float ktf[3] = {d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]};
+            const float kqf[4] = {d.kf_pose[r + 3 * N], d.kf_pose[r + 4 * N], d.kf_pose[r + 5 * N],
+                                  d.kf_pose[r + 6 * N]};
+            double kt[3], kq[4], Rk[9];
+            load_pose_d(ktf, kqf, kt, kq);
+            rot_of_quat_d(kq[0], kq[1], kq[2], kq[3], Rk);
+            const double dt[3] = {tp[0] - kt[0], tp[1] - kt[1], tp[2] - kt[2]};
+            GridMap64 gm;
+            for (int row = 0; row < 3; ++row) {
+                for (int col = 0; col < 3; ++col)
+                    gm.A[3 * row + col] =
+                        (Rk[row] * Rp[col] + Rk[3 + row] * Rp[3 + col] + Rk[6 + row] * Rp[6 + col]) * ih;
+                const double tr = Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2];
+                gm.b[row] = (tr - (double)d.origins[3 * k + row]) * ih - 0.5;
+            }
+            gm.base = (uint32_t)k * (uint32_t)d.grid_stride;
+            Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            eval_range64<DT, false, SKIP, U, true>(g, (scan64_ptr)d.scan8, j0, j1, gm, acc);
+            l += acc.l;
+            // Body-frame gradient of this neighbour: R'^T A_n / h = A'^T A_n, R'^T B_n = h A'^T B_n.
+            float A[9];
+            for (int e = 0; e < 9; ++e) A[e] = (float)gm.A[e];
+            const float h = d.h;
+            gsum[0] += A[0] * acc.ax + A[3] * acc.ay + A[6] * acc.az;
+            gsum[1] += A[1] * acc.ax + A[4] * acc.ay + A[7] * acc.az;
+            gsum[2] += A[2] * acc.ax + A[5] * acc.ay + A[8] * acc.az;
+            gsum[3] += h * (A[0] * acc.bx + A[3] * acc.by + A[6] * acc.bz);
+            gsum[4] += h * (A[1] * acc.bx + A[4] * acc.by + A[7] * acc.bz);
+            gsum[5] += h * (A[2] * acc.bx + A[5] * acc.by + A[8] * acc.bz);
+        }
+        s_l[wave][lane] = l;
+        for (int c = 0; c < 6; ++c) s_g[c][wave][lane] = gsum[c];
+        __syncthreads();
+        if (wave == 0) {
+            if (d.kf_loop)
+                tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose, s_loop, s_upd);
+            else
+                tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose);
         }
         __syncthreads();
         if (d.kf_loop && pass < d.iters) {
@@ -1801,6 +1906,15 @@ __global__ __launch_bounds__(64 * W) void k_eval(StepDesc d)
     eval_tile<DT, BIG, SKIP, W, U, TX64>(d, blockIdx.x);
 }
 
+// Four waves per SIMD (at most 128 VGPRs; the few spills fall outside the
+// point loop) so that all 64-particle tiles of a 50,000-particle session fit
+// on the device at once.
+template <int DT, bool SKIP, int W, int U>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_kf_eval_buf(StepDesc d)
+{
+    kf_tile_buf<DT, SKIP, W, U>(d, blockIdx.x);
+}
+
 template <int DT, bool SKIP, int W>
 __global__ __launch_bounds__(64 * W) void k_kf_eval(StepDesc d)
 {
@@ -1863,7 +1977,7 @@ __global__ __launch_bounds__(64 * W) void kb_eval(BatchTables t)
 // Launchers
 // ---------------------------------------------------------------------------
 
-constexpr int kEvalW = 4, kEvalU = 2;   // waves per workgroup, points per batch
+constexpr int kEvalW = 8, kEvalU = 2;   // waves per workgroup, points per batch
 constexpr int kKfW = 4;
 constexpr int kGicpW = 4;
 
@@ -1896,31 +2010,45 @@ bool eval_supported(const StepDesc &d)
     return (n_rec << (d.dtype == 0 ? 5 : 4)) <= (uint64_t)kOutside;
 }
 
-// MCSLAM_EVAL_TX32=1 selects the FP32 transform (split offset) instead of the
-// FP64 one, for comparison.
-static bool use_tx32()
+// Waves per workgroup of the evaluation kernel: each wave takes a contiguous
+// share of the scan for the block's 64 particles.  MCSLAM_EVAL_WAVES (4, 8 or
+// 16) overrides the default for measurement.
+static int eval_waves()
 {
     static int v = -1;
     if (v < 0) {
-        const char *e = getenv("MCSLAM_EVAL_TX32");
-        v = (e && e[0] == '1') ? 1 : 0;
+        const char *e = getenv("MCSLAM_EVAL_WAVES");
+        const int w = e ? atoi(e) : 0;
+        v = (w == 4 || w == 8 || w == 16) ? w : kEvalW;
     }
-    return v == 1;
+    return v;
 }
 
 template <int DT, bool SKIP>
 static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st)
 {
     const unsigned blocks = (unsigned)particle_tiles(d.N);
-    const dim3 wg(64 * kEvalW);
     if (d.K > 0) {
-        hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW>), dim3(blocks), dim3(64 * kKfW), 0, st, d);
+        // One buffer can address all keyframe grids when they fit its 32-bit range.
+        if ((uint64_t)d.grid_stride * (uint64_t)d.K <= (uint64_t)kOutside)
+            hipLaunchKernelGGL((k_kf_eval_buf<DT, SKIP, kKfW, kEvalU>), dim3(blocks), dim3(64 * kKfW), 0,
+                               st, d);
+        else
+            hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW>), dim3(blocks), dim3(64 * kKfW), 0, st, d);
     } else if (big_slab(d)) {
-        hipLaunchKernelGGL((k_eval<DT, true, SKIP, kEvalW, kEvalU, true>), dim3(blocks), wg, 0, st, d);
-    } else if (use_tx32()) {
-        hipLaunchKernelGGL((k_eval<DT, false, SKIP, kEvalW, kEvalU, false>), dim3(blocks), wg, 0, st, d);
+        hipLaunchKernelGGL((k_eval<DT, true, SKIP, kEvalW, kEvalU, true>), dim3(blocks),
+                           dim3(64 * kEvalW), 0, st, d);
     } else {
-        hipLaunchKernelGGL((k_eval<DT, false, SKIP, kEvalW, kEvalU, true>), dim3(blocks), wg, 0, st, d);
+        switch (eval_waves()) {
+        case 8:
+            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 8, kEvalU, true>), dim3(blocks), dim3(64 * 8), 0, st, d);
+            break;
+        case 16:
+            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 16, kEvalU, true>), dim3(blocks), dim3(64 * 16), 0, st, d);
+            break;
+        default:
+            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 4, kEvalU, true>), dim3(blocks), dim3(64 * 4), 0, st, d);
+        }
     }
     return hipGetLastError();
 }
