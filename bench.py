@@ -296,7 +296,8 @@ def run_keyframes(abi, steps=5):
         evals = N * M * 3 * p["n_neighbors"]
         res[name] = {"ms_per_step": round(1e3 * wall / steps, 3),
                      "eval_ms_per_step": round(prof["eval_ms"] / max(1, prof["steps"]), 3),
-                     "evals_per_s": round(evals * steps / wall, 1)}
+                     "evals_per_s": round(evals * steps / wall, 1),
+                     "grid_element_gathers_per_s": round(8 * evals * steps / wall, 1)}
     abi.mcs_destroy(ctx)
     return res
 
@@ -481,6 +482,8 @@ def main():
                    "grid": list(c["dims"]), "grid_dtype": dtype_name},
         "stage_ms": stage_ms,
         "eval_ms_first_frame_initial_spread": round(first_eval_ms, 4),
+        "trilinear_samples_per_s": round(value, 1),
+        "grid_element_gathers_per_s": round(8 * value, 1),
         "host_buffers_ms_per_step": round(host_ms, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,

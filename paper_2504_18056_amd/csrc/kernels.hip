@@ -1927,6 +1927,24 @@ __global__ __launch_bounds__(64 * W) void k_gicp_eval(StepDesc d)
     gicp_tile<W>(d, blockIdx.x);
 }
 
+// The same with the register budget of three waves per SIMD (spills allowed).
+template <int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_gicp_eval3(StepDesc d)
+{
+    gicp_tile<W>(d, blockIdx.x);
+}
+
+// MCSLAM_GICP_OCC=3 selects the three-waves-per-SIMD variant, for measurement.
+static bool gicp_occ3()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("MCSLAM_GICP_OCC");
+        v = (e && e[0] == '3') ? 1 : 0;
+    }
+    return v == 1;
+}
+
 __global__ __launch_bounds__(kWeightBlock) void k_weights(StepDesc d) { weights_blk(d, blockIdx.x); }
 __global__ __launch_bounds__(kWeightBlock) void k_wcombine(StepDesc d) { wcombine_blk(d); }
 __global__ __launch_bounds__(kWeightBlock) void k_normscan(StepDesc d) { normscan_blk(d, blockIdx.x); }
@@ -2057,8 +2075,12 @@ hipError_t launch_eval(const StepDesc &d, hipStream_t st)
 {
     if (!eval_supported(d)) return hipErrorInvalidValue;
     if (d.gicp) {
-        hipLaunchKernelGGL((k_gicp_eval<kGicpW>), dim3((unsigned)particle_tiles(d.N)), dim3(64 * kGicpW),
-                           0, st, d);
+        if (gicp_occ3())
+            hipLaunchKernelGGL((k_gicp_eval3<kGicpW>), dim3((unsigned)particle_tiles(d.N)),
+                               dim3(64 * kGicpW), 0, st, d);
+        else
+            hipLaunchKernelGGL((k_gicp_eval<kGicpW>), dim3((unsigned)particle_tiles(d.N)),
+                               dim3(64 * kGicpW), 0, st, d);
         return hipGetLastError();
     }
     const bool skip = d.oob_skip != 0;

@@ -97,5 +97,43 @@ def test_null_arguments_are_rejected(lib):
     assert lib.mcs_filter_step(None, 1, None, 1, None, None) == abi.MCS_EINVAL
     assert lib.mcs_get_particles(None, 1, None, None, None, None, None, None, None) == abi.MCS_EINVAL
     assert lib.mcs_destroy(None) == abi.MCS_OK
+    assert lib.mcs_load_gicp_keyframes(None, 1, None, None, None) == abi.MCS_EINVAL
+    assert lib.mcs_filter_step_gicp(None, 1, None, None, 1, None, None) == abi.MCS_EINVAL
+    assert lib.mcs_filter_step_gicp_dev(None, 1, None, None, 1, None, None, None) == abi.MCS_EINVAL
+    assert lib.mcs_get_gicp_system(None, 1, None, None) == abi.MCS_EINVAL
+    assert lib.mcs_server_create(None, 0, 0, 0, 1, 0, None) == abi.MCS_EINVAL
+    assert lib.mcs_server_drain(None) == abi.MCS_EINVAL
+    assert lib.mcs_server_destroy(None) == abi.MCS_OK
     assert "NULL" in abi.mcs_last_error()
     del C
+
+
+def test_plain_c_program_links_and_calls_the_library(lib):
+    """A C99 program includes the header, links libmcslam.so and calls the
+    entry points that need no device (version, errors, argument checks)."""
+    from paper_2504_18056_amd import abi
+    src = r'''
+#include <stdio.h>
+#include <string.h>
+#include "mcslam.h"
+int main(void) {
+    mcs_ctx *ctx = NULL;
+    int32_t map = 0;
+    if (strncmp(mcs_version(), "mcslam", 6) != 0) return 1;
+    if (mcs_init_map(NULL, NULL, NULL, &map) != MCS_EINVAL) return 2;
+    if (strlen(mcs_last_error()) == 0) return 3;
+    if (mcs_session_destroy(NULL, 1) != MCS_EINVAL) return 4;
+    if (mcs_destroy(ctx) != MCS_OK) return 5;
+    printf("ok\n");
+    return 0;
+}
+'''
+    libdir = os.path.dirname(abi.LIB_PATH)
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "m.c")
+        exe = os.path.join(d, "m")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), c,
+                        "-L", libdir, "-lmcslam", "-Wl,-rpath," + libdir, "-o", exe], check=True)
+        r = subprocess.run([exe], stdout=subprocess.PIPE, text=True)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.returncode
