@@ -191,6 +191,28 @@ mcs_status mcs_init_map(mcs_ctx *ctx, const mcs_grid_desc *desc, const float *va
 mcs_status mcs_load_keyframes(mcs_ctx *ctx, int32_t K, const mcs_grid_desc *descs,
                               const float *const *values, int32_t *map_id);
 
+/* Keyframes inserted one at a time (Sec. III-E: the keyframe list grows as the
+ * sensor moves; when to insert is the caller's decision).  A keyframe map
+ * with room for K_cap grids of the shape and dtype of desc starts empty.
+ * MCS_EBUDGET when the capacity does not fit the budget. */
+mcs_status mcs_create_keyframe_map(mcs_ctx *ctx, int32_t K_cap, const mcs_grid_desc *desc,
+                                   int32_t *map_id);
+
+/* Append keyframe *index = K (keyframes are numbered in insertion, i.e. time,
+ * order) to a keyframe grid map: desc gives its origin in its own frame and
+ * must match the map's shape, res and dtype; values as for
+ * mcs_load_keyframes.  MCS_EBUSY when the map is full.  Sessions on the map
+ * see the keyframe once they add it (mcs_session_add_keyframe). */
+mcs_status mcs_append_keyframe(mcs_ctx *ctx, int32_t map_id, const mcs_grid_desc *desc,
+                               const float *values, int32_t *index);
+
+/* Give the session's particles their pose of the next keyframe of its map
+ * (index *index): each particle's current pose, copied on the session's
+ * stream after its queued steps.  MCS_EINVAL when the map has no further
+ * keyframe.  A session on a keyframe map needs at least one keyframe before
+ * its first step. */
+mcs_status mcs_session_add_keyframe(mcs_ctx *ctx, int32_t session_id, int32_t *index);
+
 /* Release a map.  MCS_EBUSY while a session uses it. */
 mcs_status mcs_release_map(mcs_ctx *ctx, int32_t map_id);
 

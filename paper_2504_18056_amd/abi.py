@@ -119,6 +119,9 @@ def lib():
             "mcs_session_profile": (i32, [vp, i32, i32]),
             "mcs_session_profile_read": (i32, [vp, i32, P(Profile)]),
             "mcs_load_gicp_keyframes": (i32, [vp, i32, P(VoxelDesc), P(vp), P(i32)]),
+            "mcs_create_keyframe_map": (i32, [vp, i32, P(GridDesc), P(i32)]),
+            "mcs_append_keyframe": (i32, [vp, i32, P(GridDesc), vp, P(i32)]),
+            "mcs_session_add_keyframe": (i32, [vp, i32, P(i32)]),
             "mcs_filter_step_gicp": (i32, [vp, i32, vp, vp, i32, vp, P(StepParams)]),
             "mcs_filter_step_gicp_dev": (i32, [vp, i32, vp, vp, i32, vp, P(StepParams), vp]),
             "mcs_get_gicp_system": (i32, [vp, i32, vp, vp]),
@@ -244,6 +247,25 @@ def mcs_get_gicp_system(ctx, sid, N):
     b = np.empty((N, 6), np.float32)
     _check(lib().mcs_get_gicp_system(ctx, int(sid), _ptr(H), _ptr(b)))
     return H, b
+
+
+def mcs_create_keyframe_map(ctx, K_cap, desc):
+    mid = C.c_int32()
+    _check(lib().mcs_create_keyframe_map(ctx, int(K_cap), C.byref(desc), C.byref(mid)))
+    return mid.value
+
+
+def mcs_append_keyframe(ctx, map_id, desc, values):
+    v = _f32(values, (-1,))
+    k = C.c_int32()
+    _check(lib().mcs_append_keyframe(ctx, int(map_id), C.byref(desc), _ptr(v), C.byref(k)))
+    return k.value
+
+
+def mcs_session_add_keyframe(ctx, sid):
+    k = C.c_int32()
+    _check(lib().mcs_session_add_keyframe(ctx, int(sid), C.byref(k)))
+    return k.value
 
 
 def mcs_release_map(ctx, map_id):

@@ -131,6 +131,7 @@ mcs_status build_map(mcs_ctx *ctx, int K, const mcs_grid_desc *descs, const floa
     }
     Map *m = new Map;
     m->K = K;
+    m->K_cap = K;
     m->desc = d0;
     m->records = recs;
     m->bytes = total;
@@ -245,6 +246,8 @@ mcs_status validate_params(const Session *s, const mcs_step_params *p, int M)
         }
         if (!(qq > 1e-20)) return fail(MCS_EINVAL, "delta_T has a zero quaternion");
     }
+    if (s->K_cap > 0 && s->K == 0)
+        return fail(MCS_EINVAL, "the session has no keyframe yet (mcs_session_add_keyframe)");
     if (s->K > 0 && (p->n_neighbors < 1 || p->n_neighbors > std::min(s->K, kMaxNeighbors)))
         return fail(MCS_EINVAL, "n_neighbors=%d outside [1, %d]", p->n_neighbors,
                     std::min(s->K, kMaxNeighbors));
@@ -494,6 +497,7 @@ mcs_status mcs_load_gicp_keyframes(mcs_ctx *ctx, int32_t K, const mcs_voxel_desc
     Map *m = new Map;
     m->kind = kVoxelMap;
     m->K = K;
+    m->K_cap = K;
     m->desc.nx = d0.nx; m->desc.ny = d0.ny; m->desc.nz = d0.nz;
     for (int a = 0; a < 3; ++a) m->desc.origin[a] = d0.origin[a];
     m->desc.res = d0.edge;
@@ -530,6 +534,111 @@ mcs_status mcs_load_gicp_keyframes(mcs_ctx *ctx, int32_t K, const mcs_voxel_desc
     return MCS_OK;
 }
 
+mcs_status mcs_create_keyframe_map(mcs_ctx *ctx, int32_t K_cap, const mcs_grid_desc *desc,
+                                   int32_t *map_id)
+{
+    if (!ctx || !desc || !map_id) return fail(MCS_EINVAL, "NULL argument");
+    if (K_cap < 1 || K_cap > (1 << 16)) return fail(MCS_EINVAL, "K_cap=%d outside [1, 65536]", K_cap);
+    mcs_status s = validate_desc(desc);
+    if (s != MCS_OK) return s;
+    if ((s = set_device(ctx)) != MCS_OK) return s;
+    const int64_t recs = (int64_t)(desc->nx - 1) * (desc->ny - 1) * (desc->nz - 1);
+    const size_t grid_bytes = (size_t)recs * record_bytes(desc->dtype);
+    const size_t total = align_up(grid_bytes) * K_cap + align_up((size_t)K_cap * 3 * sizeof(float));
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!budget_allows(ctx, total))
+            return fail(MCS_EBUDGET, "map needs %zu bytes; budget %llu, in use %llu", total,
+                        (unsigned long long)ctx->budget, (unsigned long long)ctx->in_use);
+        ctx->in_use += total;
+    }
+    Map *m = new Map;
+    m->K = 0;
+    m->K_cap = K_cap;
+    m->desc = *desc;
+    m->records = recs;
+    m->bytes = total;
+    m->origins.assign((size_t)K_cap * 3, 0.0f);
+    hipError_t e = hipMalloc(&m->cells, total);
+    if (e != hipSuccess) {
+        m->cells = nullptr;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->in_use -= total;
+        delete m;
+        return hip_fail(e, "hipMalloc(map)");
+    }
+    m->origins_dev = reinterpret_cast<float *>((char *)m->cells + align_up(grid_bytes) * K_cap);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    m->id = ctx->next_id++;
+    ctx->maps[m->id] = m;
+    *map_id = m->id;
+    return MCS_OK;
+}
+
+mcs_status mcs_append_keyframe(mcs_ctx *ctx, int32_t map_id, const mcs_grid_desc *desc,
+                               const float *values, int32_t *index)
+{
+    if (!ctx || !desc || !values || !index) return fail(MCS_EINVAL, "NULL argument");
+    mcs_status s = validate_desc(desc);
+    if (s != MCS_OK) return s;
+    if ((s = set_device(ctx)) != MCS_OK) return s;
+    Map *m = nullptr;
+    int k = 0;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->maps.find(map_id);
+        if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
+        m = it->second;
+        if (m->kind != kGridMap || m->K_cap == 0) return fail(MCS_EINVAL, "map %d is not a keyframe grid map", map_id);
+        if (m->K >= m->K_cap) return fail(MCS_EBUSY, "map %d is full (%d keyframes)", map_id, m->K_cap);
+        if (desc->nx != m->desc.nx || desc->ny != m->desc.ny || desc->nz != m->desc.nz ||
+            desc->res != m->desc.res || desc->dtype != m->desc.dtype)
+            return fail(MCS_EINVAL, "keyframe grid differs in shape, res or dtype");
+        k = m->K;
+    }
+    const size_t samples = (size_t)desc->nx * desc->ny * desc->nz;
+    const size_t grid_bytes = (size_t)m->records * record_bytes(desc->dtype);
+    float *tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, samples * sizeof(float)), "hipMalloc(grid staging)");
+    hipError_t e = hipMemcpy(tmp, values, samples * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_build_cells(tmp, (char *)m->cells + align_up(grid_bytes) * k, desc->nx, desc->ny,
+                               desc->nz, desc->dtype, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(m->origins_dev + 3 * k, desc->origin, 3 * sizeof(float),
+                                       hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "keyframe upload");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (int a = 0; a < 3; ++a) m->origins[3 * (size_t)k + a] = desc->origin[a];
+    m->K = k + 1;
+    *index = k;
+    return MCS_OK;
+}
+
+mcs_status mcs_session_add_keyframe(mcs_ctx *ctx, int32_t sid, int32_t *index)
+{
+    if (!ctx || !index) return fail(MCS_EINVAL, "NULL argument");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    int map_k = 0;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        map_k = s->map->K;
+    }
+    if (s->K_cap == 0) return fail(MCS_EINVAL, "session %d has no keyframe map", sid);
+    if (s->K >= map_k) return fail(MCS_EINVAL, "the map has no keyframe %d yet", s->K);
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    // Every particle's pose of the new keyframe is its current pose.
+    const size_t N = s->N;
+    HIP_TRY(hipMemcpyAsync(s->kf_pose + (size_t)s->K * 7 * N, s->pose, 7 * N * sizeof(float),
+                           hipMemcpyDeviceToDevice, s->stream), "copy keyframe poses");
+    *index = s->K;
+    s->K++;
+    return MCS_OK;
+}
+
 mcs_status mcs_release_map(mcs_ctx *ctx, int32_t map_id)
 {
     if (!ctx) return fail(MCS_EINVAL, "NULL context");
@@ -561,7 +670,7 @@ mcs_status mcs_session_bytes(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M_
         std::lock_guard<std::mutex> lk(ctx->mu);
         auto it = ctx->maps.find(map_id);
         if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
-        K = it->second->K;
+        K = it->second->K_cap;
         gicp = it->second->kind == kVoxelMap;
     }
     *bytes = session_layout(N, M_max, K, gicp).total;
@@ -586,7 +695,7 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
         if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
         m = it->second;
         if (m->K > 0 && !kf_poses) return fail(MCS_EINVAL, "keyframe map needs kf_poses");
-        L = session_layout(N, M_max, m->K, m->kind == kVoxelMap);
+        L = session_layout(N, M_max, m->K_cap, m->kind == kVoxelMap);
         Lp = &L;
         if (!budget_allows(ctx, L.total))
             return fail(MCS_EBUDGET, "session needs %zu bytes; budget %llu, in use %llu", L.total,
@@ -605,6 +714,7 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
     ss->N = N;
     ss->M_max = M_max;
     ss->K = m->K;
+    ss->K_cap = m->K_cap;
     ss->bytes = Lp->total;
     auto undo = [&](mcs_status st) {
         if (ss->block) (void)hipFree(ss->block);

@@ -524,7 +524,7 @@ mcs_status mcs_server_submit(mcs_server *s, int32_t sid, const float *scan_dev, 
     if (!ss) return fail(MCS_ENOTFOUND, "no session %d", sid);
     mcs_status st = validate_params(ss, p, M);
     if (st != MCS_OK) return st;
-    if (ss->K > 0) return fail(MCS_EINVAL, "the server runs single-grid sessions only");
+    if (ss->K_cap > 0) return fail(MCS_EINVAL, "the server runs single-grid sessions only");
     if (ss->map->desc.dtype != s->dtype) return fail(MCS_EINVAL, "session grid dtype differs from the server's");
     if ((p->oob == MCS_OOB_SKIP) != (s->oob == MCS_OOB_SKIP))
         return fail(MCS_EINVAL, "out-of-grid rule differs from the server's");

@@ -33,7 +33,8 @@ constexpr size_t kVoxelRecordBytes = 48;   // mean (3), count, covariance (6), 2
 struct Map {
     int id = 0;
     int kind = kGridMap;             // likelihood grids, or GICP voxel Gaussians
-    int K = 0;                       // 0: single grid; >0: keyframe grids
+    int K = 0;                       // grids loaded (keyframe maps); 0 for a single grid
+    int K_cap = 0;                   // keyframe capacity; 0: single-grid map
     mcs_grid_desc desc{};            // dims, res, dtype (origin of grid 0)
     std::vector<float> origins;      // K x 3 (or 1 x 3)
     void *cells = nullptr;
@@ -46,7 +47,8 @@ struct Map {
 struct Session {
     int id = 0;
     Map *map = nullptr;
-    int N = 0, M_max = 0, K = 0;
+    int N = 0, M_max = 0, K = 0;     // K: keyframes this session has (<= the map's)
+    int K_cap = 0;                   // keyframe rows allocated (the map's capacity)
     hipStream_t stream = nullptr;
     void *block = nullptr;           // one device allocation holding every buffer
     size_t bytes = 0;

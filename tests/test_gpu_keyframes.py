@@ -163,3 +163,50 @@ def test_loop_mode_rejected_without_keyframes(ctx):
     finally:
         abi.mcs_session_destroy(ctx, sid)
         abi.mcs_release_map(ctx, mid)
+
+
+def test_incremental_keyframes_match_a_map_loaded_at_once(ctx):
+    """Keyframes appended one at a time, each particle's keyframe pose taken from
+    its pose at insertion, give the same step as the map loaded at once."""
+    c = configs.keyframes(N=500, K=10, kf_points=4096, seed=38)
+    K, N = 10, 500
+    p = dict(c["params"], iters=2, u=0.35, beta=0.01, resample=abi.RESAMPLE_ALWAYS,
+             kf_update=abi.KF_LOOP, n_recent=4)
+    ref = kf_step(ctx, c, p)
+    desc = [abi.grid_desc(c["dims"], c["origins"][k], c["h"]) for k in range(K)]
+    mid = abi.mcs_create_keyframe_map(ctx, 16, desc[0])
+    sid = abi.mcs_session_create(ctx, mid, c["poses"], M_max=c["scan"].shape[0])
+    try:
+        with pytest.raises(abi.McsError) as e:           # no keyframe yet
+            abi.mcs_filter_step(ctx, sid, c["scan"], p)
+        assert e.value.status == abi.MCS_EINVAL
+        with pytest.raises(abi.McsError) as e:           # the map has none either
+            abi.mcs_session_add_keyframe(ctx, sid)
+        assert e.value.status == abi.MCS_EINVAL
+        for k in range(K):
+            assert abi.mcs_append_keyframe(ctx, mid, desc[k], c["grids"][k]) == k
+            abi.mcs_set_particles(ctx, sid, poses=np.ascontiguousarray(c["kf_poses"][:, k]))
+            assert abi.mcs_session_add_keyframe(ctx, sid) == k
+        abi.mcs_set_particles(ctx, sid, poses=c["poses"])
+        abi.mcs_filter_step(ctx, sid, c["scan"], p)
+        out = abi.mcs_get_particles(ctx, sid, N, K=K, kf_poses=True)
+        out["neighbors"] = abi.mcs_get_neighbors(ctx, sid, N, p["n_neighbors"])
+    finally:
+        abi.mcs_session_destroy(ctx, sid)
+        abi.mcs_release_map(ctx, mid)
+    for key in ("poses", "kf_poses", "logw", "parents", "loglik", "grad", "neighbors"):
+        assert np.array_equal(out[key], ref[key]), key
+
+
+def test_keyframe_map_capacity(ctx):
+    c = configs.keyframes(N=64, K=3, kf_points=2048, seed=39)
+    desc = [abi.grid_desc(c["dims"], c["origins"][k], c["h"]) for k in range(3)]
+    mid = abi.mcs_create_keyframe_map(ctx, 2, desc[0])
+    try:
+        abi.mcs_append_keyframe(ctx, mid, desc[0], c["grids"][0])
+        abi.mcs_append_keyframe(ctx, mid, desc[1], c["grids"][1])
+        with pytest.raises(abi.McsError) as e:
+            abi.mcs_append_keyframe(ctx, mid, desc[2], c["grids"][2])
+        assert e.value.status == abi.MCS_EBUSY
+    finally:
+        abi.mcs_release_map(ctx, mid)
