@@ -29,12 +29,12 @@ sys.path.insert(0, ROOT)
 METRIC = "particle×point lik+grad evals/s; ms/step @100k particles; p99 session ms"
 # The evaluation kernel is bound by VALU issue.  Its algorithmic work is
 # counted in VALU lane-operations (FP32 or FP64, an FMA counting once): the
-# compiled inner loop (gfx950) issues 123 VALU instructions per 2 evaluations
-# with FP32 cell records, 161 with 16-bit records.  Peak: 256 CU x 4 SIMD x 16
+# compiled inner loop (gfx950) issues 245 VALU instructions per 4 evaluations
+# with FP32 cell records, 289 with FP16 and 321 with BF16 records.  Peak: 256 CU x 4 SIMD x 16
 # lanes x 2.4 GHz = 39.3e12 lane-ops/s without packed FP32 (disabled in this
 # build); the 157.3 TFLOP/s vector figure counts a packed FMA as 4 flops per
 # lane and cycle.
-VALU_OPS_PER_EVAL = {0: 61.5, 1: 80.5, 2: 80.5}
+VALU_OPS_PER_EVAL = {0: 61.25, 1: 72.25, 2: 80.25}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 BYTES_PER_EVAL = {0: 32, 1: 16, 2: 16}    # one cell record per evaluation
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_corridors_100k_counters.txt")
@@ -70,8 +70,8 @@ def cpu_cores():
         return os.cpu_count() or 1
 
 
-def run_cpu_baseline(c, frame, n_sample):
-    """The FP64 oracle on one frame for n_sample particles, all host threads."""
+def run_cpu_baseline(c, frame, n_sample, threads=None):
+    """The FP64 oracle on one frame for n_sample particles (all host threads by default)."""
     import oracle
     from synth import configs
     N = n_sample
@@ -82,7 +82,7 @@ def run_cpu_baseline(c, frame, n_sample):
     oracle.filter_step(c["grid"], c["dims"], c["origin"], c["h"], c["scans"][frame], poses,
                        np.full(N, -math.log(N)), p, float(c["u"][frame]), policy=2,
                        ess_frac=p["ess_frac"], dT=c["odometry"][frame].astype(np.float64),
-                       delta=noise, nthreads=cpu_cores())
+                       delta=noise, nthreads=threads or cpu_cores())
     dt = time.perf_counter() - t0
     evals = N * c["scans"].shape[1] * p["iters"]
     return evals / dt, dt
@@ -302,6 +302,41 @@ def run_keyframes(abi, steps=5):
     return res
 
 
+def run_ambiguous_rooms(abi):
+    """Keyframe map of a row of identical rooms (translated copies), K = 64, N = 50,000,
+    M = 2,048: the initial cloud copied at four room shifts (12,500 particles each), one step
+    of 3 passes with beta = 0.01 and no resampling.  Reports the ESS, the weight held by each
+    shift and the number of shifts holding at least 1 % of it (the translation modes)."""
+    import torch
+    from synth import configs
+    c = configs.keyframes(N=50000, K=64, ambiguous=True)
+    K = c["grids"].shape[0]
+    room = c["scene"].rooms["room"]
+    N, M = c["poses"].shape[0], c["scan"].shape[0]
+    shift = np.repeat(np.arange(-2, 2), N // 4)
+    poses = c["poses"].copy()
+    poses[:, 0] += (shift * room).astype(np.float32)
+    ctx = abi.mcs_create(0)
+    descs = [abi.grid_desc(c["dims"], c["origins"][k], c["h"]) for k in range(K)]
+    mid = abi.mcs_load_keyframes(ctx, descs, [c["grids"][k] for k in range(K)])
+    sid = abi.mcs_session_create(ctx, mid, poses, M_max=M, kf_poses=c["kf_poses"])
+    p = dict(c["params"], iters=3, u=0.5, beta=0.01, resample=abi.RESAMPLE_NEVER)
+    t0 = time.perf_counter()
+    abi.mcs_filter_step(ctx, sid, c["scan"], p)
+    out = abi.mcs_get_particles(ctx, sid, N)
+    wall = time.perf_counter() - t0
+    abi.mcs_destroy(ctx)
+    w = np.exp(out["logw"])
+    mass = [float(w[shift == s].sum()) for s in range(-2, 2)]
+    return {"workload": "keyframes over 6 identical rooms (8 m period): K=64, N=50000 as 4 copies "
+                        "of the initial cloud shifted by -2..+1 rooms along the row, M=2048, "
+                        "3 passes, beta=0.01",
+            "ess": round(float(out["stats"]["ess"]), 3),
+            "mass_per_room_shift": {str(s): round(m, 6) for s, m in zip(range(-2, 2), mass)},
+            "modes_over_1pct": int(sum(m >= 0.01 for m in mass)),
+            "step_ms_host_buffers": round(1e3 * wall, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -380,6 +415,17 @@ def main():
     abi.mcs_session_profile(ctx, sid, False)
     first_eval_ms = first["eval_ms"] / max(1, first["steps"])
     log("first frame (initial spread): eval %.3f ms" % first_eval_ms)
+    # The same frame from the same initial cloud again (the session ends in the
+    # same state), now with the grid's pages and cache lines touched once: the
+    # spread's own cost.
+    abi.mcs_set_particles(ctx, sid, poses=c["poses"], logw=np.full(N, -math.log(N)))
+    abi.mcs_session_profile(ctx, sid, True)
+    step(frames[0])
+    torch.cuda.synchronize()
+    again = abi.mcs_session_profile_read(ctx, sid)
+    abi.mcs_session_profile(ctx, sid, False)
+    spread_eval_ms = again["eval_ms"] / max(1, again["steps"])
+    log("initial spread, second time: eval %.3f ms" % spread_eval_ms)
     for k in range(1, args.warmup):
         step(frames[k])
     torch.cuda.synchronize()
@@ -436,7 +482,7 @@ def main():
     stage_ms = {k: round(prof[k] / max(1, prof["steps"]), 4)
                 for k in ("predict_ms", "eval_ms", "weights_ms", "resample_ms")}
 
-    cpu = None
+    cpu = cpu1 = None
     if args.cpu_sample > 0:
         ns = min(args.cpu_sample, N)
         log("cpu baseline: oracle on frame 1, %d particles, %d threads" % (ns, cpu_cores()))
@@ -445,12 +491,19 @@ def main():
                "kind": "oracle",
                "sample": "one corridors frame (prediction, 3 passes, weights, ESS resampling) "
                          "for %d particles x %d points; %.2f s wall" % (ns, M, dt)}
+        n1 = max(1, ns // 50)
+        rate1, dt1 = run_cpu_baseline(c, 1, n1, threads=1)
+        cpu1 = {"value": round(rate1, 1), "unit": "particle×point evals/s", "cores": 1,
+                "kind": "oracle",
+                "sample": "the same frame for %d particles, one thread; %.2f s wall" % (n1, dt1)}
 
     floors = keyframes = gicp = None
     if args.extras:
         log("keyframe-map timing")
         keyframes = run_keyframes(abi)
         log("keyframes: %s" % keyframes)
+        keyframes["ambiguous_rooms"] = run_ambiguous_rooms(abi)
+        log("ambiguous rooms: %s" % keyframes["ambiguous_rooms"])
         log("GICP timing")
         gicp = run_gicp(abi)
         log("gicp: %s" % gicp)
@@ -482,11 +535,13 @@ def main():
                    "grid": list(c["dims"]), "grid_dtype": dtype_name},
         "stage_ms": stage_ms,
         "eval_ms_first_frame_initial_spread": round(first_eval_ms, 4),
+        "eval_ms_initial_spread_second_time": round(spread_eval_ms, 4),
         "trilinear_samples_per_s": round(value, 1),
         "grid_element_gathers_per_s": round(8 * value, 1),
         "host_buffers_ms_per_step": round(host_ms, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_one_thread": cpu1,
         "ms_per_step_100k": round(1e3 * wall / args.steps, 4) if N == 100000 else None,
         "p99_session_ms": (min(serving["batched"]["p99_ms"], serving["concurrent"]["p99_ms"])
                            if serving else None),

@@ -126,7 +126,8 @@ typedef struct {
     float alpha_r;          /* rotation gain a_r (rad per unit gradient) */
     float rho_max;          /* clamp of |psi_rho| per pass (m) */
     float phi_max;          /* clamp of |psi_phi| per pass (rad) */
-    float eps;              /* likelihood floor in ln(G + eps), > 0 */
+    float eps;              /* likelihood floor in ln(G + eps), in [1e-9, 1] on
+                               grid maps (MCS_EINVAL otherwise) */
     float beta;             /* weight exponent: logw += beta * l */
     int32_t oob;            /* MCS_OOB_* */
     int32_t post_eval;      /* 0: weight with l of the last pass (taken before
@@ -178,7 +179,8 @@ mcs_status mcs_destroy(mcs_ctx *ctx);
 mcs_status mcs_memory_in_use(mcs_ctx *ctx, uint64_t *bytes);
 
 /* Load a likelihood grid map (the map M of Sec. III-A, as one grid).
- * values: host FP32, nx*ny*nz samples, x fastest.  The device keeps the grid
+ * values: host FP32, nx*ny*nz samples, x fastest, each a likelihood in
+ * [0, 1] (MCS_EINVAL for a sample outside it or not finite).  The device keeps the grid
  * in a cell-major layout holding the 8 corner samples of each cell together,
  * converted to desc->dtype.  Returns the map id in *map_id. */
 mcs_status mcs_init_map(mcs_ctx *ctx, const mcs_grid_desc *desc, const float *values,
@@ -187,7 +189,7 @@ mcs_status mcs_init_map(mcs_ctx *ctx, const mcs_grid_desc *desc, const float *va
 /* Load a keyframe map: K local grids, one per keyframe, each in its own
  * keyframe frame (Sec. III-A, "Particle state"; Fig. 2).  All descs must have
  * the same nx, ny, nz, res and dtype; origins may differ.  values[k] is host
- * FP32 for keyframe k.  Sessions on such a map hold N*K keyframe poses. */
+ * FP32 for keyframe k, samples in [0, 1] as for mcs_init_map.  Sessions on such a map hold N*K keyframe poses. */
 mcs_status mcs_load_keyframes(mcs_ctx *ctx, int32_t K, const mcs_grid_desc *descs,
                               const float *const *values, int32_t *map_id);
 

@@ -75,6 +75,8 @@ struct StepDesc {
     const float *cov6;       // [M][6] scan point covariances (xx xy xz yy yz zz)
     float4 *scan_g;          // [3M] packed points: (mu, 0), (xx xy xz yy), (yz zz 0 0)
     float *hess;             // [21][N] H of the last pass (upper triangle, row-major)
+    const void *zero_rec;    // keyframe grid maps: one zero record (read by outside points
+                             // when the grids exceed one buffer's range)
 };
 
 constexpr int kWeightBlock = 256;
@@ -96,6 +98,7 @@ hipError_t launch_weights(const StepDesc &d, hipStream_t st);
 hipError_t launch_resample(const StepDesc &d, hipStream_t st);
 // Whether the eval kernels accept this map (record buffer under 4 GiB).
 bool eval_supported(const StepDesc &d);
+bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe);
 
 // Batched steps of many sessions (the serving path).  Work lists in device
 // memory name (descriptor, block) pairs per stage; every stage kernel is

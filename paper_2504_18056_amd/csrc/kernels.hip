@@ -106,37 +106,6 @@ __device__ __forceinline__ void right_exp(float t[3], float q[4], const float rh
     q[0] = nw; q[1] = nx; q[2] = ny; q[3] = nz;
 }
 
-// FP64 per-particle setup and pose step (O(N) work; the per-point loop stays
-// FP32).  A pose held in FP32 is taken as exact; the grid map is computed
-// from it in FP64 and rounded once, and the translation part is split as
-// b = b_int + b_frac (b_int an exact integer), so that no rounding of a
-// 3-digit offset is shared by every point of the particle.
-struct GridMap {
-    float A[9];            // R / h
-    float bf[3];           // b_frac in [0, 1)
-    float bi[3];           // b_int (integer valued)
-};
-
-__device__ __forceinline__ void grid_map(const float *t, const float *q, double ox, double oy,
-                                         double oz, double h, GridMap &m)
-{
-    double w = q[0], x = q[1], y = q[2], z = q[3];
-    const double n = 1.0 / sqrt(w * w + x * x + y * y + z * z);
-    w *= n; x *= n; y *= n; z *= n;
-    const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
-                         2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
-                         2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
-    const double ih = 1.0 / h;
-    for (int e = 0; e < 9; ++e) m.A[e] = (float)(R[e] * ih);
-    const double o[3] = {ox, oy, oz};
-    for (int a = 0; a < 3; ++a) {
-        const double b = ((double)t[a] - o[a]) * ih - 0.5;
-        const double fl = floor(b);
-        m.bi[a] = (float)fl;
-        m.bf[a] = (float)(b - fl);
-    }
-}
-
 // Rotation matrix of a unit quaternion, FP64.
 __device__ __forceinline__ void rot_of_quat_d(double w, double x, double y, double z, double R[9])
 {
@@ -278,6 +247,27 @@ __device__ __forceinline__ void load_cell<2>(__amdgpu_buffer_rsrc_t rs, uint32_t
     c.a = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
 }
 
+// The same record through a 64-bit address (maps beyond one buffer's range).
+template <int DT>
+__device__ __forceinline__ void load_cell_g(uint64_t addr, Cell<DT> &c);
+template <>
+__device__ __forceinline__ void load_cell_g<0>(uint64_t addr, Cell<0> &c)
+{
+    const f4v *p = reinterpret_cast<const f4v *>(addr);
+    c.a = p[0];
+    c.b = p[1];
+}
+template <>
+__device__ __forceinline__ void load_cell_g<1>(uint64_t addr, Cell<1> &c)
+{
+    c.a = *reinterpret_cast<const u4v *>(addr);
+}
+template <>
+__device__ __forceinline__ void load_cell_g<2>(uint64_t addr, Cell<2> &c)
+{
+    c.a = *reinterpret_cast<const u4v *>(addr);
+}
+
 __device__ __forceinline__ float half_lo(uint32_t v)
 {
     return (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu));
@@ -313,6 +303,8 @@ struct Acc {
 // Grid constants of one evaluation loop.
 struct GridK {
     __amdgpu_buffer_rsrc_t rs;
+    const char *gbase;       // 64-bit addressing: the grid's records
+    const char *zero;        // 64-bit addressing: a zero record, read by outside points
     uint32_t nxm, nym, nzm;  // cells per axis (n - 1): valid cell indices are [0, n - 1)
     uint32_t cx, cxy;        // record strides: cells per row and per slab
     float eps;
@@ -338,32 +330,6 @@ struct Pt {
     bool inside;
 };
 
-template <int DT, bool BIG>
-__device__ __forceinline__ Pt prep_point(const GridK &g, const GridMap &gm, float px, float py,
-                                         float pz)
-{
-    Pt p;
-    const float *A = gm.A;
-    p.vx = fmaf(A[0], px, fmaf(A[1], py, A[2] * pz));
-    p.vy = fmaf(A[3], px, fmaf(A[4], py, A[5] * pz));
-    p.vz = fmaf(A[6], px, fmaf(A[7], py, A[8] * pz));
-    // u = (v' + b_frac) + b_int: the integer part is added last and exactly.
-    const float ux = (p.vx + gm.bf[0]) + gm.bi[0];
-    const float uy = (p.vy + gm.bf[1]) + gm.bi[1];
-    const float uz = (p.vz + gm.bf[2]) + gm.bi[2];
-    const int ix = cvt_floor(ux), iy = cvt_floor(uy), iz = cvt_floor(uz);
-    p.fx = __builtin_amdgcn_fractf(ux);
-    p.fy = __builtin_amdgcn_fractf(uy);
-    p.fz = __builtin_amdgcn_fractf(uz);
-    // 0 <= floor(u) < n - 1  <=>  0 <= u < n - 1; negative indices wrap high.
-    p.inside = ((uint32_t)ix < g.nxm) & ((uint32_t)iy < g.nym) & ((uint32_t)iz < g.nzm);
-    const uint32_t rec = BIG ? (uint32_t)ix + g.cx * (uint32_t)iy + g.cxy * (uint32_t)iz
-                             : (uint32_t)ix + __umul24(g.cx, (uint32_t)iy) +
-                                   __umul24(g.cxy, (uint32_t)iz);
-    p.off = p.inside ? (rec << record_shift<DT>()) : kOutside;
-    return p;
-}
-
 // Trilinear value and gradient (index units) of one cell record.
 template <int DT>
 __device__ __forceinline__ void trilinear(const Cell<DT> &cell, float fx, float fy, float fz,
@@ -375,6 +341,36 @@ __device__ __forceinline__ void trilinear(const Cell<DT> &cell, float fx, float 
     const float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
     const float e00 = fmaf(fx, d00, c[0]), e10 = fmaf(fx, d10, c[2]);
     const float e01 = fmaf(fx, d01, c[4]), e11 = fmaf(fx, d11, c[6]);
+    const float gy0 = e10 - e00, gy1 = e11 - e01;
+    const float f0 = fmaf(fy, gy0, e00), f1 = fmaf(fy, gy1, e01);
+    gz = f1 - f0;
+    G = fmaf(fz, gz, f0);
+    gy = fmaf(fz, gy1 - gy0, gy0);
+    const float dx0 = fmaf(fy, d10 - d00, d00), dx1 = fmaf(fy, d11 - d01, d01);
+    gx = fmaf(fz, dx1 - dx0, dx0);
+}
+
+// hi(c) - lo(c) of two packed FP16 samples in one mixed-precision FMA
+// (hi * 1 - lo, rounded once: the FP32 difference of the decoded samples).
+__device__ __forceinline__ float half_hi_minus_lo(uint32_t c)
+{
+    float r;
+    asm("v_fma_mix_f32 %0, %1, %2, -%1 op_sel:[1,0,0] op_sel_hi:[1,0,1]"
+        : "=v"(r) : "v"(c), "s"(1.0f));
+    return r;
+}
+
+// FP16 corners: the first x lerps read the packed samples directly through
+// mixed-precision FMAs, so no sample is decoded separately.  Same arithmetic,
+// and results, as the generic form.
+template <>
+__device__ __forceinline__ void trilinear<1>(const Cell<1> &cell, float fx, float fy, float fz,
+                                             float &G, float &gx, float &gy, float &gz)
+{
+    const float d00 = half_hi_minus_lo(cell.a.x), d10 = half_hi_minus_lo(cell.a.y);
+    const float d01 = half_hi_minus_lo(cell.a.z), d11 = half_hi_minus_lo(cell.a.w);
+    const float e00 = fmaf(fx, d00, half_lo(cell.a.x)), e10 = fmaf(fx, d10, half_lo(cell.a.y));
+    const float e01 = fmaf(fx, d01, half_lo(cell.a.z)), e11 = fmaf(fx, d11, half_lo(cell.a.w));
     const float gy0 = e10 - e00, gy1 = e11 - e01;
     const float f0 = fmaf(fy, gy0, e00), f1 = fmaf(fy, gy1, e01);
     gz = f1 - f0;
@@ -414,30 +410,6 @@ __device__ __forceinline__ void add_grad(const Pt &p, float gx, float gy, float 
     acc.bz = fmaf(p.vx, dy, fmaf(-p.vy, dx, acc.bz));
 }
 
-// Two points share one log2 and one reciprocal:
-//   log2(d0) + log2(d1) = log2(d0 d1),  1/d0 = d1 / (d0 d1),  1/d1 = d0 / (d0 d1),
-// with d in [eps, 1 + eps], so d0 d1 stays a normal FP32 number.  An outside
-// point has G = 0 (zero record), d = eps and a zero gradient; with SKIP its
-// factor is 1 so it adds nothing to the log sum.
-template <int DT, bool SKIP>
-__device__ __forceinline__ void accumulate2(const GridK &g, const Pt &p0, const Cell<DT> &c0,
-                                            const Pt &p1, const Cell<DT> &c1, Acc &acc)
-{
-    float G0, x0, y0, z0, G1, x1, y1, z1;
-    trilinear<DT>(c0, p0.fx, p0.fy, p0.fz, G0, x0, y0, z0);
-    trilinear<DT>(c1, p1.fx, p1.fy, p1.fz, G1, x1, y1, z1);
-    float d0 = G0 + g.eps, d1 = G1 + g.eps;
-    if (SKIP) {
-        d0 = p0.inside ? d0 : 1.0f;
-        d1 = p1.inside ? d1 : 1.0f;
-    }
-    const float prod = d0 * d1;
-    acc.l += (double)fast_log2(prod);
-    const float r = fast_rcp(prod);
-    add_grad(p0, x0, y0, z0, d1 * r, acc);
-    add_grad(p1, x1, y1, z1, d0 * r, acc);
-}
-
 template <int DT, bool SKIP>
 __device__ __forceinline__ void accumulate1(const GridK &g, const Pt &p, const Cell<DT> &c,
                                             Acc &acc)
@@ -450,40 +422,12 @@ __device__ __forceinline__ void accumulate1(const GridK &g, const Pt &p, const C
     add_grad(p, x, y, z, fast_rcp(d), acc);
 }
 
-// Points [j0, j1) of the scan against one pose.  U (even) points per batch:
-// all U record loads are issued before any of their arithmetic.
-template <int DT, bool BIG, bool SKIP, int U>
-__device__ __forceinline__ void eval_range(const GridK &g, scan_ptr scan, int j0, int j1,
-                                           const GridMap &gm, Acc &acc)
-{
-    static_assert(U % 2 == 0, "U must be even");
-    int j = j0;
-    for (; j + U <= j1; j += U) {
-        Pt p[U];
-        Cell<DT> c[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const f4v s = scan[j + k];
-            p[k] = prep_point<DT, BIG>(g, gm, s.x, s.y, s.z);
-            load_cell<DT>(g.rs, p[k].off, c[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < U; k += 2) accumulate2<DT, SKIP>(g, p[k], c[k], p[k + 1], c[k + 1], acc);
-    }
-    for (; j < j1; ++j) {
-        const f4v s = scan[j];
-        const Pt p = prep_point<DT, BIG>(g, gm, s.x, s.y, s.z);
-        Cell<DT> c;
-        load_cell<DT>(g.rs, p.off, c);
-        accumulate1<DT, SKIP>(g, p, c, acc);
-    }
-}
-
-// FP64 transform variant: the grid map stays in FP64 (A = R/h, b), points
-// arrive as FP64 (scalar loads of the FP64 copy of the scan), and u = A p + b,
-// floor(u) and the fraction are computed in FP64; only the fraction and v'
-// are rounded to FP32.  This removes the one systematic FP32 error left, the
-// rounding of A itself, at ~6 extra full-rate FP64 ops per evaluation.
+// The per-point transform runs in FP64: the grid map A = R/h, b stays in
+// FP64, points arrive as FP64 (scalar loads of the FP64 copy of the scan), and
+// u = A p + b, floor(u) and the fraction are computed in FP64; only the
+// fraction and v' are rounded to FP32.  An FP32 A would carry one rounding
+// shared by every point of the particle, a systematic error that the peaked
+// likelihood turns into gradient errors of order 1e-4 of the summation scale.
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) d4v *scan64_ptr;
 
@@ -542,12 +486,52 @@ __device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, 
     return p;
 }
 
-template <int DT, bool BIG, bool SKIP, int U, bool KF = false>
+// Four points share one log2 and one reciprocal:
+//   log2(d0 d1 d2 d3),  r = 1 / (d0 d1 d2 d3),  1/(d0 d1) = d2 d3 r,  1/(d2 d3) = d0 d1 r,
+// then 1/d0 = d1 / (d0 d1) and so on.  With grid values in [0, 1] and
+// eps >= 1e-9 every d lies in [1e-9, 1 + eps], so the product of four stays a
+// normal FP32 number.
+template <int DT, bool SKIP>
+__device__ __forceinline__ void accumulate4(const GridK &g, const Pt *p, const Cell<DT> *c, Acc &acc)
+{
+    float G[4], x[4], y[4], z[4], d[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        trilinear<DT>(c[k], p[k].fx, p[k].fy, p[k].fz, G[k], x[k], y[k], z[k]);
+        d[k] = G[k] + g.eps;
+        if (SKIP) d[k] = p[k].inside ? d[k] : 1.0f;
+    }
+    const float p01 = d[0] * d[1], p23 = d[2] * d[3];
+    const float prod = p01 * p23;
+    acc.l += (double)fast_log2(prod);
+    const float r = fast_rcp(prod);
+    const float r01 = p23 * r, r23 = p01 * r;
+    add_grad(p[0], x[0], y[0], z[0], d[1] * r01, acc);
+    add_grad(p[1], x[1], y[1], z[1], d[0] * r01, acc);
+    add_grad(p[2], x[2], y[2], z[2], d[3] * r23, acc);
+    add_grad(p[3], x[3], y[3], z[3], d[2] * r23, acc);
+}
+
+// Record of a prepared point: from the buffer (an outside point's offset lies
+// beyond its range and reads zeros) or, with GLB, through a 64-bit address
+// (an outside point reads the zero record).
+template <int DT, bool GLB>
+__device__ __forceinline__ void fetch(const GridK &g, const Pt &p, Cell<DT> &c)
+{
+    if (GLB)
+        load_cell_g<DT>(p.inside ? (uint64_t)(g.gbase + p.off) : (uint64_t)g.zero, c);
+    else
+        load_cell<DT>(g.rs, p.off, c);
+}
+
+// Points [j0, j1) of the scan against one pose, four at a time: the four
+// record loads are issued before any of their arithmetic.
+template <int DT, bool BIG, bool SKIP, bool KF = false, bool GLB = false>
 __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, int j0, int j1,
                                              const GridMap64 &gm, Acc &acc)
 {
-    static_assert(U % 2 == 0, "U must be even");
     int j = j0;
+    constexpr int U = 4;
     for (; j + U <= j1; j += U) {
         Pt p[U];
         Cell<DT> c[U];
@@ -555,16 +539,15 @@ __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, in
         for (int k = 0; k < U; ++k) {
             const d4v s = scan[j + k];
             p[k] = prep_point64<DT, BIG, KF>(g, gm, s.x, s.y, s.z);
-            load_cell<DT>(g.rs, p[k].off, c[k]);
+            fetch<DT, GLB>(g, p[k], c[k]);
         }
-#pragma unroll
-        for (int k = 0; k < U; k += 2) accumulate2<DT, SKIP>(g, p[k], c[k], p[k + 1], c[k + 1], acc);
+        accumulate4<DT, SKIP>(g, p, c, acc);
     }
     for (; j < j1; ++j) {
         const d4v s = scan[j];
         const Pt p = prep_point64<DT, BIG, KF>(g, gm, s.x, s.y, s.z);
         Cell<DT> c;
-        load_cell<DT>(g.rs, p.off, c);
+        fetch<DT, GLB>(g, p, c);
         accumulate1<DT, SKIP>(g, p, c, acc);
     }
 }
@@ -664,7 +647,7 @@ __device__ __forceinline__ void store_tile_pose(const StepDesc &d, int i, int la
     }
 }
 
-template <int DT, bool BIG, bool SKIP, int W, int U, bool TX64>
+template <int DT, bool BIG, bool SKIP, int W>
 __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
 {
     __shared__ double s_l[W][64];
@@ -685,7 +668,6 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
     g.cx = cxn;
     g.cxy = cxn * cyn;
     g.eps = d.eps;
-    const scan_ptr scan = (scan_ptr)d.scan4;
     const int M = d.M;
     const int chunk = (M + W - 1) / W;
     const int j0 = min(M, wave * chunk);
@@ -698,15 +680,9 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
         {
             const float t[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
             const float q[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
-            if (TX64) {
-                GridMap64 gm;
-                grid_map64(t, q, d.ox, d.oy, d.oz, d.h, gm);
-                eval_range64<DT, BIG, SKIP, U>(g, (scan64_ptr)d.scan8, j0, j1, gm, acc);
-            } else {
-                GridMap gm;
-                grid_map(t, q, d.ox, d.oy, d.oz, d.h, gm);
-                eval_range<DT, BIG, SKIP, U>(g, scan, j0, j1, gm, acc);
-            }
+            GridMap64 gm;
+            grid_map64(t, q, d.ox, d.oy, d.oz, d.h, gm);
+            eval_range64<DT, BIG, SKIP>(g, (scan64_ptr)d.scan8, j0, j1, gm, acc);
         }
         s_l[wave][lane] = acc.l;
         s_g[0][wave][lane] = acc.ax; s_g[1][wave][lane] = acc.ay; s_g[2][wave][lane] = acc.az;
@@ -730,26 +706,6 @@ __device__ __forceinline__ float dist2_rn(float ax, float ay, float az, float bx
 {
     const float dx = __fsub_rn(ax, bx), dy = __fsub_rn(ay, by), dz = __fsub_rn(az, bz);
     return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
-}
-
-template <int DT>
-__device__ __forceinline__ void load_cell_g(uint64_t addr, Cell<DT> &c);
-template <>
-__device__ __forceinline__ void load_cell_g<0>(uint64_t addr, Cell<0> &c)
-{
-    const f4v *p = reinterpret_cast<const f4v *>(addr);
-    c.a = p[0];
-    c.b = p[1];
-}
-template <>
-__device__ __forceinline__ void load_cell_g<1>(uint64_t addr, Cell<1> &c)
-{
-    c.a = *reinterpret_cast<const u4v *>(addr);
-}
-template <>
-__device__ __forceinline__ void load_cell_g<2>(uint64_t addr, Cell<2> &c)
-{
-    c.a = *reinterpret_cast<const u4v *>(addr);
 }
 
 // |a - b| with every operation rounded on its own (no contraction), so that
@@ -873,11 +829,24 @@ __device__ __forceinline__ void kf_select(const StepDesc &d, int i, int lane, fl
         }
     }
     // Every slot below n_nb <= K is filled (distances are finite); guard anyway.
-    for (int s = 0; s < kKfMaxNb; ++s) s_nb[s][lane] = bk[s] < K ? bk[s] : 0;
+    for (int s = 0; s < kKfMaxNb; ++s) bk[s] = bk[s] < K ? bk[s] : 0;
     if (i < N)
-        for (int s = 0; s < n_nb; ++s) d.neighbors[(size_t)s * N + i] = s_nb[s][lane];
-    int o = K;
-    for (int s = 0; s < n_nb; ++s) o = min(o, s_nb[s][lane]);
+        for (int s = 0; s < n_nb; ++s) d.neighbors[(size_t)s * N + i] = bk[s];
+    // The point loops visit a particle's neighbours in keyframe order, so that
+    // the lanes of a wave (particles with mostly the same neighbours) read the
+    // same keyframe's grid at the same time.
+    for (int s = 1; s < kKfMaxNb; ++s) {
+        if (s >= n_nb) break;
+        const int v = bk[s];
+        int t = s;
+        while (t > 0 && bk[t - 1] > v) {
+            bk[t] = bk[t - 1];
+            --t;
+        }
+        bk[t] = v;
+    }
+    for (int s = 0; s < kKfMaxNb; ++s) s_nb[s][lane] = bk[s];
+    const int o = bk[0];
     s_loop[lane] = (d.kf_loop && o < K - d.n_recent) ? o : -1;
 }
 
@@ -932,6 +901,8 @@ typedef const __attribute__((address_space(4))) f4v *gscan_ptr;
 // rotation back, e_s = R'^T e, Omega_s = (R'^T S_v R' + Sigma)^-1 (FP64
 // inverse), w = Omega_s e_s; l -= e_s^T w; b += J_s^T w and
 // H += J_s^T Omega_s J_s with J_s = [-I, [mu]x].
+typedef const __attribute__((address_space(1))) f4v *gf4_ptr;
+
 __device__ __forceinline__ void gicp_point(const double R[9], const float Rf[9], const double t[3],
                                            const double o[3], double inv_vs, int nx, int ny, int nz,
                                            uint64_t vbase, const f4v p4, const f4v c4a, const f4v c4b,
@@ -944,11 +915,14 @@ __device__ __forceinline__ void gicp_point(const double R[9], const float Rf[9],
                  u2 = floor((x2 - o[2]) * inv_vs);
     if (!(u0 >= 0.0 && u0 < (double)nx && u1 >= 0.0 && u1 < (double)ny && u2 >= 0.0 && u2 < (double)nz))
         return;
-    const uint64_t rec = (uint64_t)u0 + (uint64_t)nx * ((uint64_t)u1 + (uint64_t)ny * (uint64_t)u2);
-    const f4v *vr = reinterpret_cast<const f4v *>(vbase + rec * 48u);
-    const f4v va = vr[0];
+    // Fewer than 2^31 voxels per map (checked at load).
+    const uint32_t rec = (uint32_t)u0 + (uint32_t)nx * ((uint32_t)u1 + (uint32_t)ny * (uint32_t)u2);
+    const gf4_ptr vr = reinterpret_cast<gf4_ptr>(vbase + (uint64_t)rec * 48u);
+    // All three parts of the record are requested at once (one memory round
+    // trip), before the occupancy test.
+    const f4v va = vr[0], vb = vr[1], vc = vr[2];
+    asm volatile("" ::"v"(vb), "v"(vc));
     if (!(va.w > 0.0f)) return;
-    const f4v vb = vr[1], vc = vr[2];
     // Residual in the keyframe frame (FP64 difference, then FP32) and in the scan frame.
     const float e0 = (float)((double)va.x - x0), e1 = (float)((double)va.y - x1),
                 e2 = (float)((double)va.z - x2);
@@ -1132,12 +1106,14 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
     __syncthreads();
 }
 
-// Keyframe tile with the single-grid point loop: all K keyframe grids sit in
-// one buffer (the maps must fit its 32-bit range), each lane adds the byte
-// offset of its neighbour's grid to the record offsets, and an outside point
-// still reads zeros past the buffer's end.  Every wave builds the relative
-// grid maps itself (FP64, per neighbour), so no map is held in LDS.
-template <int DT, bool SKIP, int W, int U>
+// Keyframe tile with the single-grid point loop.  When all K keyframe grids
+// fit one buffer's 32-bit range, each lane adds the byte offset of its
+// neighbour's grid to the record offsets, and an outside point still reads
+// zeros past the buffer's end; otherwise (GLB) each lane reads its
+// neighbour's grid through 64-bit addresses and an outside point reads the
+// map's zero record.  Every wave builds the relative grid maps itself (FP64,
+// per neighbour), so no map is held in LDS.
+template <int DT, bool SKIP, int W, bool GLB>
 __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
 {
     __shared__ double s_l[W][64];
@@ -1156,7 +1132,10 @@ __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
     GridK g;
     const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
     g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
-                                             (int)((uint32_t)d.grid_stride * (uint32_t)d.K), kRsrcWord3);
+                                             GLB ? 0 : (int)((uint32_t)d.grid_stride * (uint32_t)d.K),
+                                             kRsrcWord3);
+    g.gbase = static_cast<const char *>(d.cells);
+    g.zero = static_cast<const char *>(d.zero_rec);
     g.nxm = cxn; g.nym = cyn; g.nzm = czn;
     g.cx = cxn;
     g.cxy = cxn * cyn;
@@ -1200,9 +1179,10 @@ __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
                 const double tr = Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2];
                 gm.b[row] = (tr - (double)d.origins[3 * k + row]) * ih - 0.5;
             }
-            gm.base = (uint32_t)k * (uint32_t)d.grid_stride;
+            gm.base = GLB ? 0u : (uint32_t)k * (uint32_t)d.grid_stride;
+            if (GLB) g.gbase = static_cast<const char *>(d.cells) + (uint64_t)k * (uint64_t)d.grid_stride;
             Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            eval_range64<DT, false, SKIP, U, true>(g, (scan64_ptr)d.scan8, j0, j1, gm, acc);
+            eval_range64<DT, false, SKIP, !GLB, GLB>(g, (scan64_ptr)d.scan8, j0, j1, gm, acc);
             l += acc.l;
             // Body-frame gradient of this neighbour: R'^T A_n / h = A'^T A_n, R'^T B_n = h A'^T B_n.
             float A[9];
@@ -1217,134 +1197,6 @@ __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
         }
         s_l[wave][lane] = l;
         for (int c = 0; c < 6; ++c) s_g[c][wave][lane] = gsum[c];
-        __syncthreads();
-        if (wave == 0) {
-            if (d.kf_loop)
-                tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose, s_loop, s_upd);
-            else
-                tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose);
-        }
-        __syncthreads();
-        if (d.kf_loop && pass < d.iters) {
-            kf_propagate<W>(d, i, lane, wave, s_loop, s_upd, s_seg);
-            __syncthreads();
-        }
-    }
-    if (wave == 0) store_tile_pose(d, i, lane, s_pose);
-    __syncthreads();
-}
-
-template <int DT, bool SKIP, int W>
-__device__ __forceinline__ void kf_tile(const StepDesc &d, int tile)
-{
-    __shared__ double s_l[W][64];
-    __shared__ float s_g[6][W][64];
-    __shared__ float s_pose[7][64];
-    __shared__ float s_aff[kKfMaxNb][15][64];   // per neighbour: A' (9), b_frac (3), b_int (3)
-    __shared__ int s_nb[kKfMaxNb][64];
-    __shared__ int s_loop[64];                  // oldest neighbour when a loop is detected, else -1
-    __shared__ float s_upd[9][64];              // psi and the translation before the step
-    __shared__ float s_seg[W][64];              // path length of each wave's keyframe chunk
-
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int N = d.N, n_nb = d.n_nb;
-    const int i = tile * 64 + lane;
-    const int ic = i < N ? i : N - 1;
-    const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
-    const float nxm = (float)cxn, nym = (float)cyn, nzm = (float)czn;
-    const uint64_t grid_bytes = (uint64_t)d.grid_stride;
-    const uint64_t base = (uint64_t)d.cells;
-    const scan_ptr scan = (scan_ptr)d.scan4;
-
-    if (wave == 0) kf_select(d, i, lane, s_pose, s_nb, s_loop);
-    const int chunk = (d.M + W - 1) / W;
-    const int j0 = min(d.M, wave * chunk);
-    const int j1 = min(d.M, j0 + chunk);
-    const int passes = d.iters + d.post_eval;
-    __syncthreads();
-
-    for (int pass = 0; pass < passes; ++pass) {
-        if (wave == 0) {
-            // Relative poses kT = T_k^-1 T in FP64: R' = R_k^T R, t' = R_k^T (t - t_k),
-            // as grid maps A' = R'/h and b' = (t' - o_k)/h - 1/2 = b_int + b_frac.
-            const float tf[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
-            const float qf[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
-            double t[3], q[4], R[9];
-            load_pose_d(tf, qf, t, q);
-            rot_of_quat_d(q[0], q[1], q[2], q[3], R);
-            const double ih = 1.0 / (double)d.h;
-            for (int s = 0; s < n_nb; ++s) {
-                const int k = s_nb[s][lane];
-                const size_t r = (size_t)k * 7 * N + ic;
-                const float ktf[3] = {d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]};
-                const float kqf[4] = {d.kf_pose[r + 3 * N], d.kf_pose[r + 4 * N], d.kf_pose[r + 5 * N],
-                                      d.kf_pose[r + 6 * N]};
-                double kt[3], kq[4], Rk[9];
-                load_pose_d(ktf, kqf, kt, kq);
-                rot_of_quat_d(kq[0], kq[1], kq[2], kq[3], Rk);
-                const double dt[3] = {t[0] - kt[0], t[1] - kt[1], t[2] - kt[2]};
-                for (int row = 0; row < 3; ++row) {
-                    for (int col = 0; col < 3; ++col)
-                        s_aff[s][3 * row + col][lane] =
-                            (float)((Rk[row] * R[col] + Rk[3 + row] * R[3 + col] + Rk[6 + row] * R[6 + col]) * ih);
-                    const double tr = Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2];
-                    const double bb = (tr - (double)d.origins[3 * k + row]) * ih - 0.5;
-                    const double fl = floor(bb);
-                    s_aff[s][9 + row][lane] = (float)(bb - fl);
-                    s_aff[s][12 + row][lane] = (float)fl;
-                }
-            }
-        }
-        __syncthreads();
-        double l = 0.0;
-        float g[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        for (int s = 0; s < n_nb; ++s) {
-            float A[9], bf[3], bi[3];
-            for (int e = 0; e < 9; ++e) A[e] = s_aff[s][e][lane];
-            for (int e = 0; e < 3; ++e) bf[e] = s_aff[s][9 + e][lane];
-            for (int e = 0; e < 3; ++e) bi[e] = s_aff[s][12 + e][lane];
-            const uint64_t gbase = base + (uint64_t)s_nb[s][lane] * grid_bytes;
-            Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            for (int j = j0; j < j1; ++j) {
-                const f4v sp = scan[j];
-                Pt p;
-                p.vx = fmaf(A[0], sp.x, fmaf(A[1], sp.y, A[2] * sp.z));
-                p.vy = fmaf(A[3], sp.x, fmaf(A[4], sp.y, A[5] * sp.z));
-                p.vz = fmaf(A[6], sp.x, fmaf(A[7], sp.y, A[8] * sp.z));
-                const float ux = (p.vx + bf[0]) + bi[0];
-                const float uy = (p.vy + bf[1]) + bi[1];
-                const float uz = (p.vz + bf[2]) + bi[2];
-                const bool inside = (ux >= 0.0f) & (ux < nxm) & (uy >= 0.0f) & (uy < nym) &
-                                    (uz >= 0.0f) & (uz < nzm);
-                const float sx = inside ? ux : 0.0f, sy = inside ? uy : 0.0f, sz = inside ? uz : 0.0f;
-                const int ix = cvt_floor(sx), iy = cvt_floor(sy), iz = cvt_floor(sz);
-                const float fx = __builtin_amdgcn_fractf(sx);
-                const float fy = __builtin_amdgcn_fractf(sy);
-                const float fz = __builtin_amdgcn_fractf(sz);
-                const uint64_t rec = (uint64_t)ix + (uint64_t)cxn * ((uint64_t)iy + (uint64_t)cyn * iz);
-                Cell<DT> c;
-                load_cell_g<DT>(gbase + (rec << record_shift<DT>()), c);
-                float G, gx, gy, gz;
-                trilinear<DT>(c, fx, fy, fz, G, gx, gy, gz);
-                const float m = inside ? 1.0f : 0.0f;
-                float dd = fmaf(G, m, d.eps);
-                if (SKIP) dd = inside ? dd : 1.0f;
-                acc.l += (double)fast_log2(dd);
-                add_grad(p, gx * m, gy * m, gz * m, fast_rcp(dd), acc);
-            }
-            l += acc.l;
-            // Body-frame gradient of this neighbour: R'^T A_n / h = A'^T A_n, R'^T B_n = h A'^T B_n.
-            const float h = d.h;
-            g[0] += A[0] * acc.ax + A[3] * acc.ay + A[6] * acc.az;
-            g[1] += A[1] * acc.ax + A[4] * acc.ay + A[7] * acc.az;
-            g[2] += A[2] * acc.ax + A[5] * acc.ay + A[8] * acc.az;
-            g[3] += h * (A[0] * acc.bx + A[3] * acc.by + A[6] * acc.bz);
-            g[4] += h * (A[1] * acc.bx + A[4] * acc.by + A[7] * acc.bz);
-            g[5] += h * (A[2] * acc.bx + A[5] * acc.by + A[8] * acc.bz);
-        }
-        s_l[wave][lane] = l;
-        for (int c = 0; c < 6; ++c) s_g[c][wave][lane] = g[c];
         __syncthreads();
         if (wave == 0) {
             if (d.kf_loop)
@@ -1900,49 +1752,27 @@ __global__ __launch_bounds__(kWeightBlock) void k_pack_predict(StepDesc d)
         predict_blk(d, blockIdx.x - ns);
 }
 
-template <int DT, bool BIG, bool SKIP, int W, int U, bool TX64>
-__global__ __launch_bounds__(64 * W) void k_eval(StepDesc d)
+template <int DT, bool BIG, bool SKIP, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_eval(StepDesc d)
 {
-    eval_tile<DT, BIG, SKIP, W, U, TX64>(d, blockIdx.x);
+    eval_tile<DT, BIG, SKIP, W>(d, blockIdx.x);
 }
 
 // Four waves per SIMD (at most 128 VGPRs; the few spills fall outside the
 // point loop) so that all 64-particle tiles of a 50,000-particle session fit
 // on the device at once.
-template <int DT, bool SKIP, int W, int U>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_kf_eval_buf(StepDesc d)
+template <int DT, bool SKIP, int W, bool GLB>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_kf_eval(StepDesc d)
 {
-    kf_tile_buf<DT, SKIP, W, U>(d, blockIdx.x);
+    kf_tile_buf<DT, SKIP, W, GLB>(d, blockIdx.x);
 }
 
-template <int DT, bool SKIP, int W>
-__global__ __launch_bounds__(64 * W) void k_kf_eval(StepDesc d)
-{
-    kf_tile<DT, SKIP, W>(d, blockIdx.x);
-}
-
+// Four waves per SIMD (128 VGPRs): the spills this costs are cheaper than the
+// latency hiding that fewer waves give up.
 template <int W>
-__global__ __launch_bounds__(64 * W) void k_gicp_eval(StepDesc d)
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_gicp_eval(StepDesc d)
 {
     gicp_tile<W>(d, blockIdx.x);
-}
-
-// The same with the register budget of three waves per SIMD (spills allowed).
-template <int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_gicp_eval3(StepDesc d)
-{
-    gicp_tile<W>(d, blockIdx.x);
-}
-
-// MCSLAM_GICP_OCC=3 selects the three-waves-per-SIMD variant, for measurement.
-static bool gicp_occ3()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("MCSLAM_GICP_OCC");
-        v = (e && e[0] == '3') ? 1 : 0;
-    }
-    return v == 1;
 }
 
 __global__ __launch_bounds__(kWeightBlock) void k_weights(StepDesc d) { weights_blk(d, blockIdx.x); }
@@ -1983,10 +1813,10 @@ __global__ __launch_bounds__(kWeightBlock) void kb_search(BatchTables t) { MCS_B
 __global__ __launch_bounds__(kWeightBlock) void kb_commit(BatchTables t) { MCS_BATCH_LOOP(kCommit, commit_blk(d, w.y)) }
 __global__ __launch_bounds__(kWeightBlock) void kb_fill(BatchTables t) { MCS_BATCH_LOOP(kFill, fill_blk(d, w.y)) }
 
-template <int DT, bool SKIP, int W, int U>
-__global__ __launch_bounds__(64 * W) void kb_eval(BatchTables t)
+template <int DT, bool SKIP, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void kb_eval(BatchTables t)
 {
-    MCS_BATCH_LOOP(kEval, (eval_tile<DT, false, SKIP, W, U, true>(d, w.y)))
+    MCS_BATCH_LOOP(kEval, (eval_tile<DT, false, SKIP, W>(d, w.y)))
 }
 
 }  // namespace
@@ -1995,7 +1825,7 @@ __global__ __launch_bounds__(64 * W) void kb_eval(BatchTables t)
 // Launchers
 // ---------------------------------------------------------------------------
 
-constexpr int kEvalW = 8, kEvalU = 2;   // waves per workgroup, points per batch
+constexpr int kEvalW = 8;   // waves per workgroup
 constexpr int kKfW = 4;
 constexpr int kGicpW = 4;
 
@@ -2021,11 +1851,21 @@ static bool big_slab(const StepDesc &d)
     return (uint64_t)(d.nx - 1) >= (1u << 24) || (uint64_t)(d.nx - 1) * (d.ny - 1) >= (1u << 24);
 }
 
+// One grid's records must fit a 32-bit byte offset (below the outside
+// sentinel); keyframe grids also take the 24-bit index products.
+bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe)
+{
+    const uint64_t n_rec = (uint64_t)(nx - 1) * (ny - 1) * (nz - 1);
+    const bool slab = (uint64_t)(nx - 1) >= (1u << 24) || (uint64_t)(nx - 1) * (ny - 1) >= (1u << 24);
+    return (n_rec << (dtype == 0 ? 5 : 4)) <= (uint64_t)kOutside && !(keyframe && slab);
+}
+
 bool eval_supported(const StepDesc &d)
 {
-    if (d.K > 0) return d.n_nb >= 1 && d.n_nb <= kKfMaxNb && d.n_nb <= d.K;
-    const uint64_t n_rec = (uint64_t)(d.nx - 1) * (d.ny - 1) * (d.nz - 1);
-    return (n_rec << (d.dtype == 0 ? 5 : 4)) <= (uint64_t)kOutside;
+    const bool nb_ok = d.n_nb >= 1 && d.n_nb <= kKfMaxNb && d.n_nb <= d.K;
+    if (d.gicp) return nb_ok;
+    if (d.K > 0) return nb_ok && grid_supported(d.nx, d.ny, d.nz, d.dtype, true);
+    return grid_supported(d.nx, d.ny, d.nz, d.dtype, false);
 }
 
 // Waves per workgroup of the evaluation kernel: each wave takes a contiguous
@@ -2047,25 +1887,26 @@ static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st)
 {
     const unsigned blocks = (unsigned)particle_tiles(d.N);
     if (d.K > 0) {
-        // One buffer can address all keyframe grids when they fit its 32-bit range.
-        if ((uint64_t)d.grid_stride * (uint64_t)d.K <= (uint64_t)kOutside)
-            hipLaunchKernelGGL((k_kf_eval_buf<DT, SKIP, kKfW, kEvalU>), dim3(blocks), dim3(64 * kKfW), 0,
-                               st, d);
+        // One buffer can address all keyframe grids when they fit its 32-bit
+        // range; larger maps are read through 64-bit addresses.
+        const bool one_buffer = (uint64_t)d.grid_stride * (uint64_t)d.K <= (uint64_t)kOutside;
+        if (one_buffer)
+            hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW, false>), dim3(blocks), dim3(64 * kKfW), 0, st, d);
         else
-            hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW>), dim3(blocks), dim3(64 * kKfW), 0, st, d);
+            hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW, true>), dim3(blocks), dim3(64 * kKfW), 0, st, d);
     } else if (big_slab(d)) {
-        hipLaunchKernelGGL((k_eval<DT, true, SKIP, kEvalW, kEvalU, true>), dim3(blocks),
+        hipLaunchKernelGGL((k_eval<DT, true, SKIP, kEvalW>), dim3(blocks),
                            dim3(64 * kEvalW), 0, st, d);
     } else {
         switch (eval_waves()) {
         case 8:
-            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 8, kEvalU, true>), dim3(blocks), dim3(64 * 8), 0, st, d);
+            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 8>), dim3(blocks), dim3(64 * 8), 0, st, d);
             break;
         case 16:
-            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 16, kEvalU, true>), dim3(blocks), dim3(64 * 16), 0, st, d);
+            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 16>), dim3(blocks), dim3(64 * 16), 0, st, d);
             break;
         default:
-            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 4, kEvalU, true>), dim3(blocks), dim3(64 * 4), 0, st, d);
+            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 4>), dim3(blocks), dim3(64 * 4), 0, st, d);
         }
     }
     return hipGetLastError();
@@ -2075,12 +1916,8 @@ hipError_t launch_eval(const StepDesc &d, hipStream_t st)
 {
     if (!eval_supported(d)) return hipErrorInvalidValue;
     if (d.gicp) {
-        if (gicp_occ3())
-            hipLaunchKernelGGL((k_gicp_eval3<kGicpW>), dim3((unsigned)particle_tiles(d.N)),
-                               dim3(64 * kGicpW), 0, st, d);
-        else
-            hipLaunchKernelGGL((k_gicp_eval<kGicpW>), dim3((unsigned)particle_tiles(d.N)),
-                               dim3(64 * kGicpW), 0, st, d);
+        hipLaunchKernelGGL((k_gicp_eval<kGicpW>), dim3((unsigned)particle_tiles(d.N)),
+                           dim3(64 * kGicpW), 0, st, d);
         return hipGetLastError();
     }
     const bool skip = d.oob_skip != 0;
@@ -2127,7 +1964,7 @@ static hipError_t launch_batch_dt(const BatchTables &t, hipStream_t st)
 {
     hipLaunchKernelGGL(kb_pack, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_predict, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
-    hipLaunchKernelGGL((kb_eval<DT, SKIP, kEvalW, kEvalU>), dim3(kBatchGridEval), dim3(64 * kEvalW), 0, st, t);
+    hipLaunchKernelGGL((kb_eval<DT, SKIP, kEvalW>), dim3(kBatchGridEval), dim3(64 * kEvalW), 0, st, t);
     hipLaunchKernelGGL(kb_weights, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_wcombine, dim3(kBatchGridOne), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_normscan, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);

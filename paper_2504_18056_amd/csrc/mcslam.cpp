@@ -112,16 +112,29 @@ mcs_status validate_desc(const mcs_grid_desc *d)
     return MCS_OK;
 }
 
+// Likelihood samples must be finite and in [0, 1].
+mcs_status check_samples(const float *v, size_t n, int k)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!(v[i] >= 0.0f && v[i] <= 1.0f))
+            return fail(MCS_EINVAL, "grid %d: sample %zu = %g is not in [0, 1]", k, i, (double)v[i]);
+    return MCS_OK;
+}
+
 // Upload K host FP32 grids of one shape and convert them into cell records.
 mcs_status build_map(mcs_ctx *ctx, int K, const mcs_grid_desc *descs, const float *const *values,
                      int32_t *map_id)
 {
     const mcs_grid_desc &d0 = descs[0];
     const size_t samples = (size_t)d0.nx * d0.ny * d0.nz;
+    for (int k = 0; k < (K > 0 ? K : 1); ++k) {
+        const mcs_status s = check_samples(values[k], samples, k);
+        if (s != MCS_OK) return s;
+    }
     const int64_t recs = (int64_t)(d0.nx - 1) * (d0.ny - 1) * (d0.nz - 1);
     const size_t grid_bytes = (size_t)recs * record_bytes(d0.dtype);
     const int G = K > 0 ? K : 1;
-    const size_t total = align_up(grid_bytes) * G + align_up((size_t)G * 3 * sizeof(float));
+    const size_t total = align_up(grid_bytes) * G + align_up((size_t)G * 3 * sizeof(float)) + kZeroBytes;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (!budget_allows(ctx, total))
@@ -147,6 +160,9 @@ mcs_status build_map(mcs_ctx *ctx, int K, const mcs_grid_desc *descs, const floa
     hipError_t e = hipMalloc(&m->cells, total);
     if (e != hipSuccess) { m->cells = nullptr; return undo(hip_fail(e, "hipMalloc(map)")); }
     m->origins_dev = reinterpret_cast<float *>((char *)m->cells + align_up(grid_bytes) * G);
+    m->zero_rec = (char *)m->origins_dev + align_up((size_t)G * 3 * sizeof(float));
+    e = hipMemset(m->zero_rec, 0, kZeroBytes);
+    if (e != hipSuccess) return undo(hip_fail(e, "hipMemset(zero record)"));
     float *tmp = nullptr;
     e = hipMalloc(&tmp, samples * sizeof(float));
     if (e != hipSuccess) return undo(hip_fail(e, "hipMalloc(grid staging)"));
@@ -221,6 +237,11 @@ mcs_status validate_params(const Session *s, const mcs_step_params *p, int M)
     for (float f : fs)
         if (!std::isfinite(f)) return fail(MCS_EINVAL, "non-finite step parameter");
     if (!(p->eps > 0.0f)) return fail(MCS_EINVAL, "eps must be > 0");
+    // The point loop multiplies up to four factors G + eps (one log2 and one
+    // reciprocal per product): G in [0, 1] and eps in [1e-9, 1] keep every
+    // product a normal FP32 number.
+    if (s->map->kind == kGridMap && !(p->eps >= 1e-9f && p->eps <= 1.0f))
+        return fail(MCS_EINVAL, "eps=%g outside [1e-9, 1]", (double)p->eps);
     if (p->rho_max < 0.0f || p->phi_max < 0.0f) return fail(MCS_EINVAL, "clamps must be >= 0");
     if (p->oob != MCS_OOB_FLOOR && p->oob != MCS_OOB_SKIP) return fail(MCS_EINVAL, "bad oob mode");
     if (p->resample < MCS_RESAMPLE_NEVER || p->resample > MCS_RESAMPLE_PRUNE)
@@ -275,6 +296,7 @@ StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float 
     d.scan_g = s->scan_g;
     d.hess = s->hess;
     d.origins = m->origins_dev;
+    d.zero_rec = m->zero_rec;
     d.nx = m->desc.nx; d.ny = m->desc.ny; d.nz = m->desc.nz;
     d.dtype = m->desc.dtype;
     d.ox = m->desc.origin[0]; d.oy = m->desc.origin[1]; d.oz = m->desc.origin[2];
@@ -442,6 +464,8 @@ mcs_status mcs_init_map(mcs_ctx *ctx, const mcs_grid_desc *desc, const float *va
     if (!ctx || !values || !map_id) return fail(MCS_EINVAL, "NULL argument");
     mcs_status s = validate_desc(desc);
     if (s != MCS_OK) return s;
+    if (!grid_supported(desc->nx, desc->ny, desc->nz, desc->dtype, false))
+        return fail(MCS_EINVAL, "grid records exceed a 32-bit byte range");
     if ((s = set_device(ctx)) != MCS_OK) return s;
     const float *v[1] = {values};
     return build_map(ctx, 0, desc, v, map_id);
@@ -460,6 +484,8 @@ mcs_status mcs_load_keyframes(mcs_ctx *ctx, int32_t K, const mcs_grid_desc *desc
             descs[k].res != descs[0].res || descs[k].dtype != descs[0].dtype)
             return fail(MCS_EINVAL, "keyframe grid %d differs in shape, res or dtype", k);
     }
+    if (!grid_supported(descs[0].nx, descs[0].ny, descs[0].nz, descs[0].dtype, true))
+        return fail(MCS_EINVAL, "keyframe grid too large (32-bit record offsets, 24-bit row and slab products)");
     mcs_status s = set_device(ctx);
     if (s != MCS_OK) return s;
     return build_map(ctx, K, descs, values, map_id);
@@ -482,9 +508,10 @@ mcs_status mcs_load_gicp_keyframes(mcs_ctx *ctx, int32_t K, const mcs_voxel_desc
             return fail(MCS_EINVAL, "voxel map %d differs in shape or edge", k);
         if (!voxels[k]) return fail(MCS_EINVAL, "voxel map %d is NULL", k);
     }
+    const int64_t recs = (int64_t)d0.nx * d0.ny * d0.nz;
+    if (recs >= (int64_t)1 << 31) return fail(MCS_EINVAL, "voxel map has 2^31 or more voxels");
     mcs_status s = set_device(ctx);
     if (s != MCS_OK) return s;
-    const int64_t recs = (int64_t)d0.nx * d0.ny * d0.nz;
     const size_t map_bytes = (size_t)recs * kVoxelRecordBytes;
     const size_t total = align_up(map_bytes) * K + align_up((size_t)K * 3 * sizeof(float));
     {
@@ -541,10 +568,13 @@ mcs_status mcs_create_keyframe_map(mcs_ctx *ctx, int32_t K_cap, const mcs_grid_d
     if (K_cap < 1 || K_cap > (1 << 16)) return fail(MCS_EINVAL, "K_cap=%d outside [1, 65536]", K_cap);
     mcs_status s = validate_desc(desc);
     if (s != MCS_OK) return s;
+    if (!grid_supported(desc->nx, desc->ny, desc->nz, desc->dtype, true))
+        return fail(MCS_EINVAL, "keyframe grid too large (32-bit record offsets, 24-bit row and slab products)");
     if ((s = set_device(ctx)) != MCS_OK) return s;
     const int64_t recs = (int64_t)(desc->nx - 1) * (desc->ny - 1) * (desc->nz - 1);
     const size_t grid_bytes = (size_t)recs * record_bytes(desc->dtype);
-    const size_t total = align_up(grid_bytes) * K_cap + align_up((size_t)K_cap * 3 * sizeof(float));
+    const size_t total =
+        align_up(grid_bytes) * K_cap + align_up((size_t)K_cap * 3 * sizeof(float)) + kZeroBytes;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (!budget_allows(ctx, total))
@@ -568,6 +598,15 @@ mcs_status mcs_create_keyframe_map(mcs_ctx *ctx, int32_t K_cap, const mcs_grid_d
         return hip_fail(e, "hipMalloc(map)");
     }
     m->origins_dev = reinterpret_cast<float *>((char *)m->cells + align_up(grid_bytes) * K_cap);
+    m->zero_rec = (char *)m->origins_dev + align_up((size_t)K_cap * 3 * sizeof(float));
+    e = hipMemset(m->zero_rec, 0, kZeroBytes);
+    if (e != hipSuccess) {
+        (void)hipFree(m->cells);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->in_use -= total;
+        delete m;
+        return hip_fail(e, "hipMemset(zero record)");
+    }
     std::lock_guard<std::mutex> lk(ctx->mu);
     m->id = ctx->next_id++;
     ctx->maps[m->id] = m;
@@ -597,6 +636,7 @@ mcs_status mcs_append_keyframe(mcs_ctx *ctx, int32_t map_id, const mcs_grid_desc
         k = m->K;
     }
     const size_t samples = (size_t)desc->nx * desc->ny * desc->nz;
+    if ((s = check_samples(values, samples, k)) != MCS_OK) return s;
     const size_t grid_bytes = (size_t)m->records * record_bytes(desc->dtype);
     float *tmp = nullptr;
     HIP_TRY(hipMalloc(&tmp, samples * sizeof(float)), "hipMalloc(grid staging)");

@@ -99,13 +99,42 @@ def test_keyframe_full_scale_sampled(ctx):
     check_weights_resample(c["logw"], out["loglik"], 1.0, p["u"], out, abi.RESAMPLE_ESS)
 
 
-def test_ambiguous_rooms_keep_several_modes(ctx):
-    """Repeated identical rooms: the filter keeps weight on more than one room."""
+def test_ambiguous_rooms_particles_over_room_shifts(ctx):
+    """Repeated identical rooms, particles spread over four copies of the initial
+    cloud shifted by whole rooms: every particle against the oracle, and the
+    weight held by each shift as the oracle's likelihoods give it."""
     c = configs.keyframes(N=4000, K=16, kf_points=4096, seed=33, ambiguous=True)
-    p = dict(c["params"], iters=1, u=0.5, beta=0.01, resample=abi.RESAMPLE_NEVER)
+    room = c["scene"].rooms["room"]
+    shift = np.repeat(np.arange(-2, 2), 1000)
+    poses = c["poses"].copy()
+    poses[:, 0] += (shift * room).astype(np.float32)
+    beta = 0.01
+    p = dict(c["params"], iters=1, u=0.5, beta=beta, resample=abi.RESAMPLE_NEVER)
+    out = kf_step(ctx, c, p, poses=poses)
+    ref = check_kf(c, out, p, poses=poses)
+    check_weights_resample(c["logw"], out["loglik"], beta, p["u"], out, abi.RESAMPLE_NEVER)
+
+    def masses(l):
+        lw = beta * np.asarray(l, np.float64)
+        w = np.exp(lw - lw.max())
+        w /= w.sum()
+        return np.array([w[shift == s].sum() for s in range(-2, 2)])
+
+    assert np.allclose(masses(out["loglik"]), masses(ref["loglik"]), atol=1e-2)
+
+
+def test_keyframe_grids_beyond_one_buffer(ctx):
+    """66 FP32 keyframe grids of 128^3 exceed one buffer's 32-bit byte range, so
+    the kernel reads them through 64-bit addresses (outside points read the
+    map's zero record): same bounds against the oracle."""
+    c = configs.keyframes(N=200, K=66, kf_points=2048, seed=38)
+    stride = -(-127 ** 3 * 32 // 256) * 256
+    assert stride * 66 > 0xFFFFFFE0
+    p = dict(c["params"], iters=1, u=0.3, beta=0.01, resample=abi.RESAMPLE_ALWAYS)
     out = kf_step(ctx, c, p)
-    check_kf(c, out, p, idx=np.arange(0, 4000, 40))
-    assert math.isfinite(out["stats"]["ess"])
+    check_kf(c, out, p)
+    anc = out["parents"]
+    check_step(c["poses"][anc], out["grad"][anc], out["poses"], p)
 
 
 def test_loop_closure_out_and_back(ctx):

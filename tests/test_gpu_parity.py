@@ -201,3 +201,35 @@ def test_corridors_full_scale_sampled(ctx):
     anc = out["parents"]
     check_step(c["poses"][anc], out["grad"][anc], out["poses"], p)
     check_weights_resample(c["logw"], out["loglik"], 1.0, p["u"], out, abi.RESAMPLE_ESS)
+
+
+def test_rejects_samples_outside_unit_range_and_tiny_eps(ctx, box_room):
+    """Samples are likelihoods in [0, 1] and eps lies in [1e-9, 1]: the point loop
+    multiplies up to four factors G + eps, which must stay normal FP32 numbers."""
+    c = box_room
+    desc = abi.grid_desc(c["dims"], c["origin"], c["h"])
+    for bad in (1.5, -0.25, float("nan")):
+        g = c["grid"].copy()
+        g[3, 4, 5] = bad
+        with pytest.raises(abi.McsError) as e:
+            abi.mcs_init_map(ctx, desc, g)
+        assert e.value.status == abi.MCS_EINVAL
+    mid = abi.mcs_init_map(ctx, desc, c["grid"])
+    sid = abi.mcs_session_create(ctx, mid, c["poses"], M_max=c["scan"].shape[0])
+    try:
+        for eps in (1e-12, 2.0):
+            with pytest.raises(abi.McsError) as e:
+                abi.mcs_filter_step(ctx, sid, c["scan"], dict(c["params"], eps=eps, u=0.5))
+            assert e.value.status == abi.MCS_EINVAL
+        # The smallest accepted eps: every factor is at least 1e-9 and the
+        # product of four still normal; outside points give exactly 4 ln(eps) per four.
+        p = dict(c["params"], eps=float(np.float32(1e-9)), u=0.5, beta=0.0,
+                 resample=abi.RESAMPLE_NEVER)
+        abi.mcs_filter_step(ctx, sid, c["scan"] + np.float32(500.0), p)
+        out = abi.mcs_get_particles(ctx, sid, c["poses"].shape[0])
+        expect = c["scan"].shape[0] * math.log(np.float32(1e-9))
+        assert np.allclose(out["loglik"], expect, rtol=1e-6)
+        assert np.all(np.isfinite(out["grad"])) and np.all(out["grad"] == 0)
+    finally:
+        abi.mcs_session_destroy(ctx, sid)
+        abi.mcs_release_map(ctx, mid)
