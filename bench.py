@@ -464,18 +464,22 @@ def main():
     passes = base["iters"]
     evals_per_step = N * M * passes
     value = evals_per_step * args.steps / wall
-    eval_s = prof["eval_ms"] * 1e-3 / max(1, prof["steps"])   # one eval launch per step
+    # The evaluation stage of a step: k_eval over the whole rounds of tiles and,
+    # when the last round is small, the tail kernels beside it (HIP events on
+    # the session stream around the stage).
+    eval_s = prof["eval_ms"] * 1e-3 / max(1, prof["steps"])
     ops = VALU_OPS_PER_EVAL[args.grid_dtype] * evals_per_step
     achieved = ops / eval_s / 1e12
     traffic = measured_traffic(args.grid_dtype)
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic,
-                "kernel": "k_eval", "eval_launch_ms": round(eval_s * 1e3, 4),
-                "note": "VALU lane-operations per second (FP32/FP64, FMA counted once): %.1f per "
-                        "evaluation x %d evaluations per launch; peak = 256 CU x 64 lanes x 2.4 GHz "
-                        "(no packed FP32). traffic = HBM bytes per launch from FETCH_SIZE/WRITE_SIZE "
-                        "(%s); the algorithmic gather is %d B per evaluation = %.2f GB per launch"
+                "kernel": "k_eval (with its tail kernels)", "eval_launch_ms": round(eval_s * 1e3, 4),
+                "note": "VALU lane-operations per second (FP32/FP64, FMA counted once): %.2f per "
+                        "evaluation x %d evaluations per step's evaluation stage; peak = 256 CU x 64 "
+                        "lanes x 2.4 GHz (no packed FP32). traffic = HBM bytes per stage from "
+                        "FETCH_SIZE/WRITE_SIZE (%s); the algorithmic gather is %d B per evaluation = "
+                        "%.2f GB per stage"
                         % (VALU_OPS_PER_EVAL[args.grid_dtype], evals_per_step,
                            os.path.relpath(PMC_SUMMARY, ROOT), BYTES_PER_EVAL[args.grid_dtype],
                            BYTES_PER_EVAL[args.grid_dtype] * evals_per_step / 1e9)}

@@ -77,12 +77,20 @@ struct StepDesc {
     float *hess;             // [21][N] H of the last pass (upper triangle, row-major)
     const void *zero_rec;    // keyframe grid maps: one zero record (read by outside points
                              // when the grids exceed one buffer's range)
+    // Single-grid tail tiles (eval_tail_tiles): per (tile, sub-chunk, particle)
+    // partial sums, [tail][kSubChunks][64] log sums and [tail][kSubChunks][6][64].
+    double *tail_l;
+    float *tail_g;
+    int32_t tail_tiles;      // tiles the session's tail buffers hold (0: no split)
 };
 
 constexpr int kWeightBlock = 256;
 constexpr int kPartPerBlock = 6;   // doubles of per-block partials
 constexpr int kParticleTile = 64;
 constexpr int kKfMaxNb = 8;
+// Sub-chunks of the scan in the single-grid evaluation's fixed summation order.
+constexpr int kSubChunks = 32;
+constexpr size_t kTailBytesPerTile = (size_t)kSubChunks * 64 * (8 + 6 * 4);
 
 __host__ __device__ inline int weight_blocks(int N) { return (N + kWeightBlock - 1) / kWeightBlock; }
 __host__ __device__ inline int particle_tiles(int N) { return (N + kParticleTile - 1) / kParticleTile; }
@@ -93,11 +101,21 @@ hipError_t launch_build_cells(const float *grid, void *cells, int nx, int ny, in
                               hipStream_t st);
 // The stages of one step of one session.
 hipError_t launch_pack_predict(const StepDesc &d, hipStream_t st);
-hipError_t launch_eval(const StepDesc &d, hipStream_t st);
+// aux: a second stream and two events of the session; with them the tail
+// tiles' kernels run beside the main launch (fork after the stages before,
+// join before the stages after).
+struct TailAux {
+    hipStream_t stream;
+    hipEvent_t fork, join;
+};
+hipError_t launch_eval(const StepDesc &d, hipStream_t st, const TailAux *aux = nullptr);
 hipError_t launch_weights(const StepDesc &d, hipStream_t st);
 hipError_t launch_resample(const StepDesc &d, hipStream_t st);
 // Whether the eval kernels accept this map (record buffer under 4 GiB).
 bool eval_supported(const StepDesc &d);
+// Tiles of a single-grid session of N particles that the evaluation spreads
+// over one wave per sub-chunk (the last, partly filled round of tiles), or 0.
+int eval_tail_tiles(int N, int dtype);
 bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe);
 
 // Batched steps of many sessions (the serving path).  Work lists in device

@@ -23,6 +23,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 namespace mcs {
 namespace {
@@ -35,6 +37,7 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 // Rotation matrix (row-major) of a unit quaternion (w, x, y, z).
 __device__ __forceinline__ void rot_of_quat(float w, float x, float y, float z, float R[9])
 {
+#pragma clang fp contract(off)
     const float x2 = x + x, y2 = y + y, z2 = z + z;
     const float wx = w * x2, wy = w * y2, wz = w * z2;
     const float xx = x * x2, xy = x * y2, xz = x * z2;
@@ -46,6 +49,7 @@ __device__ __forceinline__ void rot_of_quat(float w, float x, float y, float z, 
 
 __device__ __forceinline__ void normalize_quat(float &w, float &x, float &y, float &z)
 {
+#pragma clang fp contract(off)
     const float s = __builtin_amdgcn_rsqf(w * w + x * x + y * y + z * z);
     w *= s; x *= s; y *= s; z *= s;
     if (w < 0.0f) { w = -w; x = -x; y = -y; z = -z; }
@@ -79,6 +83,7 @@ __device__ __forceinline__ void exp_coeffs(float th2, float &a, float &b, float 
 __device__ __forceinline__ void right_exp(float t[3], float q[4], const float rho[3],
                                           const float phi[3])
 {
+#pragma clang fp contract(off)
     const float th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
     float a, b, c, cw;
     exp_coeffs(th2, a, b, c, cw);
@@ -109,6 +114,7 @@ __device__ __forceinline__ void right_exp(float t[3], float q[4], const float rh
 // Rotation matrix of a unit quaternion, FP64.
 __device__ __forceinline__ void rot_of_quat_d(double w, double x, double y, double z, double R[9])
 {
+#pragma clang fp contract(off)
     R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
     R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
     R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
@@ -164,6 +170,7 @@ __device__ __forceinline__ void right_exp_d(double t[3], double q[4], const doub
 __device__ __forceinline__ void load_pose_d(const float t[3], const float q[4], double td[3],
                                             double qd[4])
 {
+#pragma clang fp contract(off)
     for (int a = 0; a < 3; ++a) td[a] = t[a];
     const double n = 1.0 / sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] +
                                 (double)q[3] * q[3]);
@@ -185,6 +192,7 @@ __device__ __forceinline__ void store_pose_d(const double td[3], const double qd
 __device__ __forceinline__ void step_vector(const float g[6], float alpha_t, float alpha_r,
                                             float rho_max, float phi_max, float rho[3], float phi[3])
 {
+#pragma clang fp contract(off)
     rho[0] = alpha_t * g[0]; rho[1] = alpha_t * g[1]; rho[2] = alpha_t * g[2];
     phi[0] = alpha_r * g[3]; phi[1] = alpha_r * g[4]; phi[2] = alpha_r * g[5];
     const float nr = sqrtf(rho[0] * rho[0] + rho[1] * rho[1] + rho[2] * rho[2]);
@@ -202,6 +210,7 @@ __device__ __forceinline__ void step_vector(const float g[6], float alpha_t, flo
 __device__ __forceinline__ void take_step(float t[3], float q[4], const float g[6], float alpha_t,
                                           float alpha_r, float rho_max, float phi_max)
 {
+#pragma clang fp contract(off)
     float rho[3], phi[3];
     step_vector(g, alpha_t, alpha_r, rho_max, phi_max, rho, phi);
     right_exp(t, q, rho, phi);
@@ -300,6 +309,24 @@ struct Acc {
     float bx, by, bz;      // sum of v' x (dG/du / (G + eps)), v' = A p
 };
 
+__device__ __forceinline__ void add_acc(Acc &a, const Acc &b)
+{
+#pragma clang fp contract(off)
+    a.l += b.l;
+    a.ax += b.ax; a.ay += b.ay; a.az += b.az;
+    a.bx += b.bx; a.by += b.by; a.bz += b.bz;
+}
+
+// The single-grid scan is cut into kSubChunks sub-chunks of Q points (Q a
+// multiple of 4), each summed from zero on its own; a wave adds its
+// consecutive sub-chunks in order, and the W wave sums are added in wave
+// order.  This fixed order lets a tile's sub-chunks also be spread over
+// separate waves (the tail tiles of a launch) with bit-identical results.
+__host__ __device__ __forceinline__ int sub_chunk_len(int M)
+{
+    return 4 * ((M + 4 * kSubChunks - 1) / (4 * kSubChunks));
+}
+
 // Grid constants of one evaluation loop.
 struct GridK {
     __amdgpu_buffer_rsrc_t rs;
@@ -335,6 +362,7 @@ template <int DT>
 __device__ __forceinline__ void trilinear(const Cell<DT> &cell, float fx, float fy, float fz,
                                           float &G, float &gx, float &gy, float &gz)
 {
+#pragma clang fp contract(off)
     float c[8];
     decode<DT>(cell, c);
     // Corner records: lerps along x on the four y/z edges, then y, then z.
@@ -354,6 +382,7 @@ __device__ __forceinline__ void trilinear(const Cell<DT> &cell, float fx, float 
 // (hi * 1 - lo, rounded once: the FP32 difference of the decoded samples).
 __device__ __forceinline__ float half_hi_minus_lo(uint32_t c)
 {
+#pragma clang fp contract(off)
     float r;
     asm("v_fma_mix_f32 %0, %1, %2, -%1 op_sel:[1,0,0] op_sel_hi:[1,0,1]"
         : "=v"(r) : "v"(c), "s"(1.0f));
@@ -367,6 +396,7 @@ template <>
 __device__ __forceinline__ void trilinear<1>(const Cell<1> &cell, float fx, float fy, float fz,
                                              float &G, float &gx, float &gy, float &gz)
 {
+#pragma clang fp contract(off)
     const float d00 = half_hi_minus_lo(cell.a.x), d10 = half_hi_minus_lo(cell.a.y);
     const float d01 = half_hi_minus_lo(cell.a.z), d11 = half_hi_minus_lo(cell.a.w);
     const float e00 = fmaf(fx, d00, half_lo(cell.a.x)), e10 = fmaf(fx, d10, half_lo(cell.a.y));
@@ -387,6 +417,7 @@ template <>
 __device__ __forceinline__ void trilinear<0>(const Cell<0> &cell, float fx, float fy, float fz,
                                              float &G, float &gx, float &gy, float &gz)
 {
+#pragma clang fp contract(off)
     const float a0 = cell.a.x, a1 = cell.a.y, a2 = cell.a.z, a3 = cell.a.w;
     const float a4 = cell.b.x, a5 = cell.b.y, a6 = cell.b.z, a7 = cell.b.w;
     const float p = fmaf(a6, fy, a3);      // dG/dz at x = 0
@@ -403,6 +434,7 @@ __device__ __forceinline__ void trilinear<0>(const Cell<0> &cell, float fx, floa
 __device__ __forceinline__ void add_grad(const Pt &p, float gx, float gy, float gz, float inv,
                                          Acc &acc)
 {
+#pragma clang fp contract(off)
     const float dx = gx * inv, dy = gy * inv, dz = gz * inv;
     acc.ax += dx; acc.ay += dy; acc.az += dz;
     acc.bx = fmaf(p.vy, dz, fmaf(-p.vz, dy, acc.bx));
@@ -414,6 +446,7 @@ template <int DT, bool SKIP>
 __device__ __forceinline__ void accumulate1(const GridK &g, const Pt &p, const Cell<DT> &c,
                                             Acc &acc)
 {
+#pragma clang fp contract(off)
     float G, x, y, z;
     trilinear<DT>(c, p.fx, p.fy, p.fz, G, x, y, z);
     float d = G + g.eps;
@@ -440,6 +473,7 @@ struct GridMap64 {
 __device__ __forceinline__ void grid_map64(const float *t, const float *q, double ox, double oy,
                                            double oz, double h, GridMap64 &m)
 {
+#pragma clang fp contract(off)
     double w = q[0], x = q[1], y = q[2], z = q[3];
     const double n = 1.0 / sqrt(w * w + x * x + y * y + z * z);
     w *= n; x *= n; y *= n; z *= n;
@@ -466,6 +500,7 @@ template <int DT, bool BIG, bool KF = false>
 __device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, double px,
                                            double py, double pz)
 {
+#pragma clang fp contract(off)
     Pt p;
     const double *A = gm.A;
     const double vx = fma(A[0], px, fma(A[1], py, A[2] * pz));
@@ -494,6 +529,7 @@ __device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, 
 template <int DT, bool SKIP>
 __device__ __forceinline__ void accumulate4(const GridK &g, const Pt *p, const Cell<DT> *c, Acc &acc)
 {
+#pragma clang fp contract(off)
     float G[4], x[4], y[4], z[4], d[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -530,6 +566,7 @@ template <int DT, bool BIG, bool SKIP, bool KF = false, bool GLB = false>
 __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, int j0, int j1,
                                              const GridMap64 &gm, Acc &acc)
 {
+#pragma clang fp contract(off)
     int j = j0;
     constexpr int U = 4;
     for (; j + U <= j1; j += U) {
@@ -561,6 +598,7 @@ __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, in
 __device__ __forceinline__ void body_gradient(const float q[4], const float s[6], float inv_h,
                                               float gr[6])
 {
+#pragma clang fp contract(off)
     float qn[4] = {q[0], q[1], q[2], q[3]};
     normalize_quat(qn[0], qn[1], qn[2], qn[3]);
     float R[9];
@@ -577,6 +615,7 @@ __device__ __forceinline__ void body_gradient(const float q[4], const float s[6]
 // Load the tile's poses into LDS (normalised quaternions).
 __device__ __forceinline__ void load_tile_pose(const StepDesc &d, int i, int lane, float (*s_pose)[64])
 {
+#pragma clang fp contract(off)
     const int N = d.N;
     const int ic = i < N ? i : N - 1;
     float q[4] = {d.pose[3 * N + ic], d.pose[4 * N + ic], d.pose[5 * N + ic], d.pose[6 * N + ic]};
@@ -595,6 +634,7 @@ __device__ __forceinline__ void tile_epilogue(const StepDesc &d, int i, int lane
                                               float (*s_pose)[64], const int *s_loop = nullptr,
                                               float (*s_upd)[64] = nullptr)
 {
+#pragma clang fp contract(off)
     double l = 0.0;
     float s[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     for (int w = 0; w < W; ++w) {
@@ -639,6 +679,7 @@ __device__ __forceinline__ void tile_epilogue(const StepDesc &d, int i, int lane
 __device__ __forceinline__ void store_tile_pose(const StepDesc &d, int i, int lane,
                                                 const float (*s_pose)[64])
 {
+#pragma clang fp contract(off)
     const int N = d.N;
     if (i < N) {
         d.pose[i] = s_pose[0][lane]; d.pose[N + i] = s_pose[1][lane]; d.pose[2 * N + i] = s_pose[2][lane];
@@ -650,6 +691,7 @@ __device__ __forceinline__ void store_tile_pose(const StepDesc &d, int i, int la
 template <int DT, bool BIG, bool SKIP, int W>
 __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
 {
+#pragma clang fp contract(off)
     __shared__ double s_l[W][64];
     __shared__ float s_g[6][W][64];
     __shared__ float s_pose[7][64];
@@ -669,9 +711,8 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
     g.cxy = cxn * cyn;
     g.eps = d.eps;
     const int M = d.M;
-    const int chunk = (M + W - 1) / W;
-    const int j0 = min(M, wave * chunk);
-    const int j1 = min(M, j0 + chunk);
+    const int Q = sub_chunk_len(M);
+    constexpr int S = kSubChunks / W;      // sub-chunks per wave
     const int passes = d.iters + d.post_eval;
     __syncthreads();
 
@@ -682,7 +723,13 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
             const float q[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
             GridMap64 gm;
             grid_map64(t, q, d.ox, d.oy, d.oz, d.h, gm);
-            eval_range64<DT, BIG, SKIP>(g, (scan64_ptr)d.scan8, j0, j1, gm, acc);
+            for (int sc = 0; sc < S; ++sc) {
+                const int c = wave * S + sc;
+                Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                eval_range64<DT, BIG, SKIP>(g, (scan64_ptr)d.scan8, min(M, c * Q), min(M, (c + 1) * Q),
+                                            gm, part);
+                add_acc(acc, part);
+            }
         }
         s_l[wave][lane] = acc.l;
         s_g[0][wave][lane] = acc.ax; s_g[1][wave][lane] = acc.ay; s_g[2][wave][lane] = acc.az;
@@ -693,6 +740,86 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
     }
     if (wave == 0) store_tile_pose(d, i, lane, s_pose);
     __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Tail tiles: one wave per sub-chunk, then a per-tile reduce and step
+// ---------------------------------------------------------------------------
+
+// Pose of particle i as the tile holds it before pass `pass`: the input pose
+// with its quaternion normalised (pass 0, as load_tile_pose) or the pose the
+// previous pass's step stored.
+__device__ __forceinline__ void tail_pose(const StepDesc &d, int i, int pass, float t[3], float q[4])
+{
+#pragma clang fp contract(off)
+    const int N = d.N;
+    const int ic = i < N ? i : N - 1;
+    t[0] = d.pose[ic]; t[1] = d.pose[N + ic]; t[2] = d.pose[2 * N + ic];
+    q[0] = d.pose[3 * N + ic]; q[1] = d.pose[4 * N + ic]; q[2] = d.pose[5 * N + ic]; q[3] = d.pose[6 * N + ic];
+    if (pass == 0) normalize_quat(q[0], q[1], q[2], q[3]);
+}
+
+// One sub-chunk of one tail tile per wave: the same sub-chunk sums eval_tile forms.
+template <int DT, bool BIG, bool SKIP>
+__device__ __forceinline__ void tail_chunk(const StepDesc &d, int tile0, int pass, int rel, int c)
+{
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    const int i = (tile0 + rel) * 64 + lane;
+    GridK g;
+    const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
+    g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
+                                             (int)((cxn * cyn * czn) << record_shift<DT>()),
+                                             kRsrcWord3);
+    g.nxm = cxn; g.nym = cyn; g.nzm = czn;
+    g.cx = cxn;
+    g.cxy = cxn * cyn;
+    g.eps = d.eps;
+    const int M = d.M, Q = sub_chunk_len(M);
+    float t[3], q[4];
+    tail_pose(d, i, pass, t, q);
+    GridMap64 gm;
+    grid_map64(t, q, d.ox, d.oy, d.oz, d.h, gm);
+    Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    eval_range64<DT, BIG, SKIP>(g, (scan64_ptr)d.scan8, min(M, c * Q), min(M, (c + 1) * Q), gm, part);
+    const size_t r = (size_t)rel * kSubChunks + c;
+    d.tail_l[r * 64 + lane] = part.l;
+    float *tg = d.tail_g + r * 6 * 64 + lane;
+    tg[0] = part.ax; tg[64] = part.ay; tg[128] = part.az;
+    tg[192] = part.bx; tg[256] = part.by; tg[320] = part.bz;
+}
+
+// Reduce a tail tile's sub-chunk sums in eval_tile's order (W waves of
+// kSubChunks / W consecutive sub-chunks each), then the same epilogue; the
+// pose goes back to memory after every pass.  One wave per tile.
+template <int W>
+__device__ __forceinline__ void tail_step(const StepDesc &d, int tile0, int pass, int rel)
+{
+#pragma clang fp contract(off)
+    __shared__ double s_l[W][64];
+    __shared__ float s_g[6][W][64];
+    __shared__ float s_pose[7][64];
+    const int lane = threadIdx.x & 63;
+    const int i = (tile0 + rel) * 64 + lane;
+    float t[3], q[4];
+    tail_pose(d, i, pass, t, q);
+    s_pose[0][lane] = t[0]; s_pose[1][lane] = t[1]; s_pose[2][lane] = t[2];
+    s_pose[3][lane] = q[0]; s_pose[4][lane] = q[1]; s_pose[5][lane] = q[2]; s_pose[6][lane] = q[3];
+    constexpr int S = kSubChunks / W;
+    for (int w = 0; w < W; ++w) {
+        Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (int sc = 0; sc < S; ++sc) {
+            const size_t r = (size_t)rel * kSubChunks + w * S + sc;
+            const float *tg = d.tail_g + r * 6 * 64 + lane;
+            const Acc part = {d.tail_l[r * 64 + lane], tg[0], tg[64], tg[128], tg[192], tg[256], tg[320]};
+            add_acc(acc, part);
+        }
+        s_l[w][lane] = acc.l;
+        s_g[0][w][lane] = acc.ax; s_g[1][w][lane] = acc.ay; s_g[2][w][lane] = acc.az;
+        s_g[3][w][lane] = acc.bx; s_g[4][w][lane] = acc.by; s_g[5][w][lane] = acc.bz;
+    }
+    tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose);
+    store_tile_pose(d, i, lane, s_pose);
 }
 
 // ---------------------------------------------------------------------------
@@ -1758,6 +1885,23 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     eval_tile<DT, BIG, SKIP, W>(d, blockIdx.x);
 }
 
+// Eight waves per block, one sub-chunk each: block b covers tail tile
+// b / (kSubChunks / 8) and its sub-chunks (b % (kSubChunks / 8)) * 8 + wave.
+template <int DT, bool BIG, bool SKIP>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_tail(StepDesc d, int tile0,
+                                                                                          int pass)
+{
+    constexpr int G = kSubChunks / 8;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    tail_chunk<DT, BIG, SKIP>(d, tile0, pass, blockIdx.x / G, (blockIdx.x % G) * 8 + wave);
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void k_eval_tail_step(StepDesc d, int tile0, int pass)
+{
+    tail_step<W>(d, tile0, pass, blockIdx.x);
+}
+
 // Four waves per SIMD (at most 128 VGPRs; the few spills fall outside the
 // point loop) so that all 64-particle tiles of a 50,000-particle session fit
 // on the device at once.
@@ -1860,6 +2004,42 @@ bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe)
     return (n_rec << (dtype == 0 ? 5 : 4)) <= (uint64_t)kOutside && !(keyframe && slab);
 }
 
+// Tiles of the single-grid kernel resident on the device at once (cached per device).
+static int eval_round_tiles(int dtype)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({dev, dtype});
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    const void *fn = dtype == 0   ? reinterpret_cast<const void *>(&k_eval<0, false, false, kEvalW>)
+                     : dtype == 1 ? reinterpret_cast<const void *>(&k_eval<1, false, false, kEvalW>)
+                                  : reinterpret_cast<const void *>(&k_eval<2, false, false, kEvalW>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kEvalW, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const int r = per_cu * cus;
+    cache[{dev, dtype}] = r;
+    return r;
+}
+
+// The last round of tiles is split when it fills at most a quarter of the
+// device; a session of at most three quarters of one round is split whole
+// (its waves then fill the device instead of leaving a quarter of it idle
+// for a whole tile's time).
+int eval_tail_tiles(int N, int dtype)
+{
+    const int round = eval_round_tiles(dtype);
+    if (round <= 0) return 0;
+    const int tiles = particle_tiles(N);
+    if (tiles < round) return 4 * tiles <= 3 * round ? tiles : 0;
+    const int rem = tiles % round;
+    return rem > 0 && rem <= round / 4 ? rem : 0;
+}
+
 bool eval_supported(const StepDesc &d)
 {
     const bool nb_ok = d.n_nb >= 1 && d.n_nb <= kKfMaxNb && d.n_nb <= d.K;
@@ -1883,7 +2063,7 @@ static int eval_waves()
 }
 
 template <int DT, bool SKIP>
-static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st)
+static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st, const TailAux *aux)
 {
     const unsigned blocks = (unsigned)particle_tiles(d.N);
     if (d.K > 0) {
@@ -1894,14 +2074,45 @@ static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st)
             hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW, false>), dim3(blocks), dim3(64 * kKfW), 0, st, d);
         else
             hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW, true>), dim3(blocks), dim3(64 * kKfW), 0, st, d);
-    } else if (big_slab(d)) {
-        hipLaunchKernelGGL((k_eval<DT, true, SKIP, kEvalW>), dim3(blocks),
-                           dim3(64 * kEvalW), 0, st, d);
+    } else if (big_slab(d) || eval_waves() == kEvalW) {
+        // Whole rounds of tiles in one launch; a small last round (tail) with
+        // one wave per sub-chunk, pass by pass (the same sums and order).
+        const int tail = d.tail_l ? min(d.tail_tiles, particle_tiles(d.N)) : 0;
+        const unsigned main_tiles = blocks - (unsigned)tail;
+        // With a second stream the tail's passes run beside the main launch,
+        // whose whole rounds then absorb them.
+        const bool fork = tail > 0 && main_tiles > 0 && aux != nullptr;
+        const hipStream_t ts = fork ? aux->stream : st;
+        if (fork) {
+            hipError_t e = hipEventRecord(aux->fork, st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(ts, aux->fork, 0);
+            if (e != hipSuccess) return e;
+        }
+        for (int pass = 0; tail > 0 && pass < d.iters + d.post_eval; ++pass) {
+            const dim3 gb((unsigned)tail * (kSubChunks / 8));
+            if (big_slab(d))
+                hipLaunchKernelGGL((k_eval_tail<DT, true, SKIP>), gb, dim3(512), 0, ts, d, (int)main_tiles, pass);
+            else
+                hipLaunchKernelGGL((k_eval_tail<DT, false, SKIP>), gb, dim3(512), 0, ts, d, (int)main_tiles, pass);
+            hipLaunchKernelGGL((k_eval_tail_step<kEvalW>), dim3((unsigned)tail), dim3(64), 0, ts, d,
+                               (int)main_tiles, pass);
+        }
+        if (main_tiles > 0) {
+            if (big_slab(d))
+                hipLaunchKernelGGL((k_eval<DT, true, SKIP, kEvalW>), dim3(main_tiles), dim3(64 * kEvalW), 0,
+                                   st, d);
+            else
+                hipLaunchKernelGGL((k_eval<DT, false, SKIP, kEvalW>), dim3(main_tiles), dim3(64 * kEvalW), 0,
+                                   st, d);
+        }
+        if (fork) {
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess) e = hipEventRecord(aux->join, ts);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, aux->join, 0);
+            if (e != hipSuccess) return e;
+        }
     } else {
         switch (eval_waves()) {
-        case 8:
-            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 8>), dim3(blocks), dim3(64 * 8), 0, st, d);
-            break;
         case 16:
             hipLaunchKernelGGL((k_eval<DT, false, SKIP, 16>), dim3(blocks), dim3(64 * 16), 0, st, d);
             break;
@@ -1912,7 +2123,7 @@ static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_eval(const StepDesc &d, hipStream_t st)
+hipError_t launch_eval(const StepDesc &d, hipStream_t st, const TailAux *aux)
 {
     if (!eval_supported(d)) return hipErrorInvalidValue;
     if (d.gicp) {
@@ -1922,9 +2133,9 @@ hipError_t launch_eval(const StepDesc &d, hipStream_t st)
     }
     const bool skip = d.oob_skip != 0;
     switch (d.dtype) {
-    case 0: return skip ? launch_eval_dt<0, true>(d, st) : launch_eval_dt<0, false>(d, st);
-    case 1: return skip ? launch_eval_dt<1, true>(d, st) : launch_eval_dt<1, false>(d, st);
-    case 2: return skip ? launch_eval_dt<2, true>(d, st) : launch_eval_dt<2, false>(d, st);
+    case 0: return skip ? launch_eval_dt<0, true>(d, st, aux) : launch_eval_dt<0, false>(d, st, aux);
+    case 1: return skip ? launch_eval_dt<1, true>(d, st, aux) : launch_eval_dt<1, false>(d, st, aux);
+    case 2: return skip ? launch_eval_dt<2, true>(d, st, aux) : launch_eval_dt<2, false>(d, st, aux);
     default: return hipErrorInvalidValue;
     }
 }

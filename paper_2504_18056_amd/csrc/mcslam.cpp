@@ -40,11 +40,17 @@ mcs_status hip_fail(hipError_t e, const char *what)
 }
 
 struct Layout {
-    size_t off[20];
+    size_t off[21];
     size_t total;
 };
 
-Layout session_layout(int N, int M_max, int K, bool gicp)
+// Tail tiles of a session on map m (single grids only).
+int session_tail_tiles(const Map *m, int N)
+{
+    return (m->kind == kGridMap && m->K_cap == 0) ? eval_tail_tiles(N, m->desc.dtype) : 0;
+}
+
+Layout session_layout(int N, int M_max, int K, bool gicp, int tail)
 {
     const size_t n = (size_t)N, nb = (size_t)weight_blocks(N);
     const size_t sizes[] = {
@@ -68,6 +74,7 @@ Layout session_layout(int N, int M_max, int K, bool gicp)
         (gicp ? (size_t)M_max * kVoxelRecordBytes : 0),   // 17 scan_g
         (gicp ? (size_t)M_max * 6 * 4 : 0),                // 18 cov6
         (gicp ? 21 * n * 4 : 0),                           // 19 hess
+        (size_t)tail * kTailBytesPerTile,                  // 20 tail sub-chunk sums
     };
     Layout L{};
     size_t o = 0;
@@ -297,6 +304,9 @@ StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float 
     d.hess = s->hess;
     d.origins = m->origins_dev;
     d.zero_rec = m->zero_rec;
+    d.tail_l = s->tail_l;
+    d.tail_g = s->tail_g;
+    d.tail_tiles = s->tail_tiles;
     d.nx = m->desc.nx; d.ny = m->desc.ny; d.nz = m->desc.nz;
     d.dtype = m->desc.dtype;
     d.ox = m->desc.origin[0]; d.oy = m->desc.origin[1]; d.oz = m->desc.origin[2];
@@ -373,7 +383,8 @@ mcs_status enqueue_step(Session *s, const float *scan3_dev, int M, const float *
     PROF_MARK(0);
     HIP_TRY(launch_pack_predict(d, st), "pack/predict");
     PROF_MARK(1);
-    HIP_TRY(launch_eval(d, st), "eval");
+    const TailAux aux{s->tail_stream, s->tail_fork, s->tail_join};
+    HIP_TRY(launch_eval(d, st, s->tail_stream ? &aux : nullptr), "eval");
     if (s->K > 0) s->last_nb = p->n_neighbors;
     PROF_MARK(2);
     HIP_TRY(launch_weights(d, st), "weights");
@@ -704,16 +715,18 @@ mcs_status mcs_session_bytes(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M_
 {
     if (!ctx || !bytes) return fail(MCS_EINVAL, "NULL argument");
     if (N < 1 || M_max < 1) return fail(MCS_EINVAL, "N and M_max must be >= 1");
-    int K = 0;
+    int K = 0, tail = 0;
     bool gicp = false;
+    if (mcs_status s = set_device(ctx)) return s;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         auto it = ctx->maps.find(map_id);
         if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
         K = it->second->K_cap;
         gicp = it->second->kind == kVoxelMap;
+        tail = session_tail_tiles(it->second, N);
     }
-    *bytes = session_layout(N, M_max, K, gicp).total;
+    *bytes = session_layout(N, M_max, K, gicp, tail).total;
     return MCS_OK;
 }
 
@@ -735,7 +748,7 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
         if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
         m = it->second;
         if (m->K > 0 && !kf_poses) return fail(MCS_EINVAL, "keyframe map needs kf_poses");
-        L = session_layout(N, M_max, m->K_cap, m->kind == kVoxelMap);
+        L = session_layout(N, M_max, m->K_cap, m->kind == kVoxelMap, session_tail_tiles(m, N));
         Lp = &L;
         if (!budget_allows(ctx, L.total))
             return fail(MCS_EBUDGET, "session needs %zu bytes; budget %llu, in use %llu", L.total,
@@ -760,6 +773,9 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
         if (ss->block) (void)hipFree(ss->block);
         if (ss->stream) (void)hipStreamDestroy(ss->stream);
         if (ss->staged) (void)hipEventDestroy(ss->staged);
+        if (ss->tail_stream) (void)hipStreamDestroy(ss->tail_stream);
+        if (ss->tail_fork) (void)hipEventDestroy(ss->tail_fork);
+        if (ss->tail_join) (void)hipEventDestroy(ss->tail_join);
         if (ss->pinned) (void)hipHostFree(ss->pinned);
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->in_use -= L.total;
@@ -795,6 +811,18 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
         ss->scan_g = (float4 *)(b + L.off[17]);
         ss->cov6 = (float *)(b + L.off[18]);
         ss->hess = (float *)(b + L.off[19]);
+    }
+    if (L.off[20] < L.total) {
+        const int tail = session_tail_tiles(m, N);
+        ss->tail_tiles = tail;
+        ss->tail_l = (double *)(b + L.off[20]);
+        e = hipStreamCreateWithFlags(&ss->tail_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { ss->tail_stream = nullptr; return undo(hip_fail(e, "hipStreamCreate")); }
+        e = hipEventCreateWithFlags(&ss->tail_fork, hipEventDisableTiming);
+        if (e != hipSuccess) { ss->tail_fork = nullptr; return undo(hip_fail(e, "hipEventCreate")); }
+        e = hipEventCreateWithFlags(&ss->tail_join, hipEventDisableTiming);
+        if (e != hipSuccess) { ss->tail_join = nullptr; return undo(hip_fail(e, "hipEventCreate")); }
+        ss->tail_g = (float *)(b + L.off[20] + (size_t)tail * kSubChunks * 64 * 8);
     }
     e = hipMemsetAsync(ss->block, 0, L.total, ss->stream);
     if (e != hipSuccess) return undo(hip_fail(e, "hipMemset(session)"));
@@ -833,9 +861,15 @@ mcs_status mcs_session_destroy(mcs_ctx *ctx, int32_t sid)
     }
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(s->stream);
+    if (s->tail_stream) (void)hipStreamSynchronize(s->tail_stream);
     (void)hipFree(s->block);
     (void)hipStreamDestroy(s->stream);
     (void)hipEventDestroy(s->staged);
+    if (s->tail_stream) {
+        (void)hipStreamDestroy(s->tail_stream);
+        (void)hipEventDestroy(s->tail_fork);
+        (void)hipEventDestroy(s->tail_join);
+    }
     if (s->pinned) (void)hipHostFree(s->pinned);
     prof_release(s);
     std::lock_guard<std::mutex> lk(ctx->mu);

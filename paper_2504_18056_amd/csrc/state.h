@@ -64,6 +64,11 @@ struct Session {
     float4 *scan_g = nullptr;        // GICP: packed points and covariances
     float *cov6 = nullptr;           // GICP: uploaded covariances (host-pointer steps)
     float *hess = nullptr;           // GICP: [21][N] Gauss-Newton H
+    double *tail_l = nullptr;        // single grid: tail tiles' sub-chunk log sums
+    float *tail_g = nullptr;         // and gradient sums (null: no tail split)
+    int tail_tiles = 0;
+    hipStream_t tail_stream = nullptr;   // with tail tiles: the tail's passes run on it
+    hipEvent_t tail_fork = nullptr, tail_join = nullptr;
     float *pinned = nullptr;         // host staging for host-pointer steps
     size_t pinned_floats = 0;
     int last_nb = 0;                 // neighbours per particle in the last keyframe step
