@@ -77,8 +77,10 @@ struct StepDesc {
     float *hess;             // [21][N] H of the last pass (upper triangle, row-major)
     const void *zero_rec;    // keyframe grid maps: one zero record (read by outside points
                              // when the grids exceed one buffer's range)
-    // Single-grid tail tiles (eval_tail_tiles): per (tile, sub-chunk, particle)
-    // partial sums, [tail][kSubChunks][64] log sums and [tail][kSubChunks][6][64].
+    // Tail tiles (eval_tail_tiles).  Single grid: per (tile, sub-chunk,
+    // particle) partial sums, [tail][kSubChunks][64] log sums and
+    // [tail][kSubChunks][6][64].  Keyframe maps: tail_l is the base of the
+    // buffer kf_tail() lays out (kKfTailBytesPerTile per tile).
     double *tail_l;
     float *tail_g;
     int32_t tail_tiles;      // tiles the session's tail buffers hold (0: no split)
@@ -91,6 +93,8 @@ constexpr int kKfMaxNb = 8;
 // Sub-chunks of the scan in the single-grid evaluation's fixed summation order.
 constexpr int kSubChunks = 32;
 constexpr size_t kTailBytesPerTile = (size_t)kSubChunks * 64 * (8 + 6 * 4);
+constexpr size_t kKfTailBytesPerTile =
+    (size_t)(kKfMaxNb + 1) * 64 * 4 + (size_t)kSubChunks * kKfMaxNb * 64 * (8 + 6 * 4);
 
 __host__ __device__ inline int weight_blocks(int N) { return (N + kWeightBlock - 1) / kWeightBlock; }
 __host__ __device__ inline int particle_tiles(int N) { return (N + kParticleTile - 1) / kParticleTile; }
@@ -115,7 +119,7 @@ hipError_t launch_resample(const StepDesc &d, hipStream_t st);
 bool eval_supported(const StepDesc &d);
 // Tiles of a single-grid session of N particles that the evaluation spreads
 // over one wave per sub-chunk (the last, partly filled round of tiles), or 0.
-int eval_tail_tiles(int N, int dtype);
+int eval_tail_tiles(int N, int dtype, bool keyframes);
 bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe);
 
 // Batched steps of many sessions (the serving path).  Work lists in device

@@ -856,6 +856,7 @@ __device__ __forceinline__ void kf_propagate(const StepDesc &d, int i, int lane,
                                              const int *s_loop, const float (*s_upd)[64],
                                              float (*s_seg)[64])
 {
+#pragma clang fp contract(off)
     constexpr int B = 4;
     const int N = d.N, K = d.K;
     const int o = s_loop[lane];
@@ -933,6 +934,7 @@ __device__ __forceinline__ void kf_propagate(const StepDesc &d, int i, int lane,
 __device__ __forceinline__ void kf_select(const StepDesc &d, int i, int lane, float (*s_pose)[64],
                                           int (*s_nb)[64], int *s_loop)
 {
+#pragma clang fp contract(off)
     const int N = d.N, K = d.K, n_nb = d.n_nb;
     const int ic = i < N ? i : N - 1;
     load_tile_pose(d, i, lane, s_pose);
@@ -1233,6 +1235,51 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
     __syncthreads();
 }
 
+// Relative grid map of keyframe k for a particle at (tf, qf): T_k^-1 T (Eq. 4)
+// in FP64, R' = R_k^T R, t' = R_k^T (t - t_k), as A' = R'/h and
+// b' = (t' - o_k)/h - 1/2 of keyframe k's grid.
+__device__ __forceinline__ void kf_grid_map(const StepDesc &d, int k, int ic, const float tf[3],
+                                            const float qf[4], double ih, GridMap64 &gm)
+{
+#pragma clang fp contract(off)
+    const int N = d.N;
+    double tp[3], qp[4], Rp[9];
+    load_pose_d(tf, qf, tp, qp);
+    rot_of_quat_d(qp[0], qp[1], qp[2], qp[3], Rp);
+    const size_t r = (size_t)k * 7 * N + ic;
+    const float ktf[3] = {d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]};
+    const float kqf[4] = {d.kf_pose[r + 3 * N], d.kf_pose[r + 4 * N], d.kf_pose[r + 5 * N],
+                          d.kf_pose[r + 6 * N]};
+    double kt[3], kq[4], Rk[9];
+    load_pose_d(ktf, kqf, kt, kq);
+    rot_of_quat_d(kq[0], kq[1], kq[2], kq[3], Rk);
+    const double dt[3] = {tp[0] - kt[0], tp[1] - kt[1], tp[2] - kt[2]};
+    for (int row = 0; row < 3; ++row) {
+        for (int col = 0; col < 3; ++col)
+            gm.A[3 * row + col] =
+                (Rk[row] * Rp[col] + Rk[3 + row] * Rp[3 + col] + Rk[6 + row] * Rp[6 + col]) * ih;
+        const double tr = Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2];
+        gm.b[row] = (tr - (double)d.origins[3 * k + row]) * ih - 0.5;
+    }
+}
+
+// Add one neighbour's sums, rotated into the body frame: R'^T A_n / h = A'^T A_n,
+// R'^T B_n = h A'^T B_n.
+__device__ __forceinline__ void kf_add_neighbour(const GridMap64 &gm, float h, const Acc &acc, double &l,
+                                                 float gsum[6])
+{
+#pragma clang fp contract(off)
+    l += acc.l;
+    float A[9];
+    for (int e = 0; e < 9; ++e) A[e] = (float)gm.A[e];
+    gsum[0] += A[0] * acc.ax + A[3] * acc.ay + A[6] * acc.az;
+    gsum[1] += A[1] * acc.ax + A[4] * acc.ay + A[7] * acc.az;
+    gsum[2] += A[2] * acc.ax + A[5] * acc.ay + A[8] * acc.az;
+    gsum[3] += h * (A[0] * acc.bx + A[3] * acc.by + A[6] * acc.bz);
+    gsum[4] += h * (A[1] * acc.bx + A[4] * acc.by + A[7] * acc.bz);
+    gsum[5] += h * (A[2] * acc.bx + A[5] * acc.by + A[8] * acc.bz);
+}
+
 // Keyframe tile with the single-grid point loop.  When all K keyframe grids
 // fit one buffer's 32-bit range, each lane adds the byte offset of its
 // neighbour's grid to the record offsets, and an outside point still reads
@@ -1243,6 +1290,7 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
 template <int DT, bool SKIP, int W, bool GLB>
 __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
 {
+#pragma clang fp contract(off)
     __shared__ double s_l[W][64];
     __shared__ float s_g[6][W][64];
     __shared__ float s_pose[7][64];
@@ -1270,9 +1318,8 @@ __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
     const double ih = 1.0 / (double)d.h;
 
     if (wave == 0) kf_select(d, i, lane, s_pose, s_nb, s_loop);
-    const int chunk = (d.M + W - 1) / W;
-    const int j0 = min(d.M, wave * chunk);
-    const int j1 = min(d.M, j0 + chunk);
+    const int M = d.M, Q = sub_chunk_len(M);
+    constexpr int S = kSubChunks / W;      // sub-chunks per wave
     const int passes = d.iters + d.post_eval;
     __syncthreads();
 
@@ -1284,43 +1331,20 @@ __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
             // holds no registers during the point loop.
             const float tf[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
             const float qf[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
-            double tp[3], qp[4], Rp[9];
-            load_pose_d(tf, qf, tp, qp);
-            rot_of_quat_d(qp[0], qp[1], qp[2], qp[3], Rp);
-            // Relative pose T_k^-1 T (Eq. 4): R' = R_k^T R, t' = R_k^T (t - t_k), as the grid
-            // map A' = R'/h, b' = (t' - o_k)/h - 1/2 of keyframe k's grid.
             const int k = s_nb[s][lane];
-            const size_t r = (size_t)k * 7 * N + ic;
-            const float ktf[3] = {d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]};
-            const float kqf[4] = {d.kf_pose[r + 3 * N], d.kf_pose[r + 4 * N], d.kf_pose[r + 5 * N],
-                                  d.kf_pose[r + 6 * N]};
-            double kt[3], kq[4], Rk[9];
-            load_pose_d(ktf, kqf, kt, kq);
-            rot_of_quat_d(kq[0], kq[1], kq[2], kq[3], Rk);
-            const double dt[3] = {tp[0] - kt[0], tp[1] - kt[1], tp[2] - kt[2]};
             GridMap64 gm;
-            for (int row = 0; row < 3; ++row) {
-                for (int col = 0; col < 3; ++col)
-                    gm.A[3 * row + col] =
-                        (Rk[row] * Rp[col] + Rk[3 + row] * Rp[3 + col] + Rk[6 + row] * Rp[6 + col]) * ih;
-                const double tr = Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2];
-                gm.b[row] = (tr - (double)d.origins[3 * k + row]) * ih - 0.5;
-            }
+            kf_grid_map(d, k, ic, tf, qf, ih, gm);
             gm.base = GLB ? 0u : (uint32_t)k * (uint32_t)d.grid_stride;
             if (GLB) g.gbase = static_cast<const char *>(d.cells) + (uint64_t)k * (uint64_t)d.grid_stride;
             Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            eval_range64<DT, false, SKIP, !GLB, GLB>(g, (scan64_ptr)d.scan8, j0, j1, gm, acc);
-            l += acc.l;
-            // Body-frame gradient of this neighbour: R'^T A_n / h = A'^T A_n, R'^T B_n = h A'^T B_n.
-            float A[9];
-            for (int e = 0; e < 9; ++e) A[e] = (float)gm.A[e];
-            const float h = d.h;
-            gsum[0] += A[0] * acc.ax + A[3] * acc.ay + A[6] * acc.az;
-            gsum[1] += A[1] * acc.ax + A[4] * acc.ay + A[7] * acc.az;
-            gsum[2] += A[2] * acc.ax + A[5] * acc.ay + A[8] * acc.az;
-            gsum[3] += h * (A[0] * acc.bx + A[3] * acc.by + A[6] * acc.bz);
-            gsum[4] += h * (A[1] * acc.bx + A[4] * acc.by + A[7] * acc.bz);
-            gsum[5] += h * (A[2] * acc.bx + A[5] * acc.by + A[8] * acc.bz);
+            for (int sc = 0; sc < S; ++sc) {
+                const int c = wave * S + sc;
+                Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                eval_range64<DT, false, SKIP, !GLB, GLB>(g, (scan64_ptr)d.scan8, min(M, c * Q),
+                                                         min(M, (c + 1) * Q), gm, part);
+                add_acc(acc, part);
+            }
+            kf_add_neighbour(gm, d.h, acc, l, gsum);
         }
         s_l[wave][lane] = l;
         for (int c = 0; c < 6; ++c) s_g[c][wave][lane] = gsum[c];
@@ -1339,6 +1363,146 @@ __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
     }
     if (wave == 0) store_tile_pose(d, i, lane, s_pose);
     __syncthreads();
+}
+
+// Keyframe-map tail tiles (the last, small round of a launch): per tile the
+// neighbours in keyframe order and the loop flag, then per (sub-chunk,
+// neighbour) the seven sums; the step adds them in kf_tile_buf's order.
+struct KfTail {
+    int32_t *nb;        // [tile][kKfMaxNb][64]
+    int32_t *loop;      // [tile][64]
+    double *l;          // [tile][kSubChunks][kKfMaxNb][64]
+    float *g;           // [tile][kSubChunks][kKfMaxNb][6][64]
+};
+__device__ __forceinline__ KfTail kf_tail(const StepDesc &d)
+{
+    const size_t T = (size_t)d.tail_tiles;
+    char *b = reinterpret_cast<char *>(d.tail_l);
+    KfTail t;
+    t.nb = reinterpret_cast<int32_t *>(b);
+    t.loop = t.nb + T * kKfMaxNb * 64;
+    t.l = reinterpret_cast<double *>(b + T * (kKfMaxNb + 1) * 64 * 4);
+    t.g = reinterpret_cast<float *>(t.l + T * kSubChunks * kKfMaxNb * 64);
+    return t;
+}
+
+// Neighbours (in keyframe order) and loop flags of the tail tiles, once per step.
+__device__ __forceinline__ void kf_tail_select(const StepDesc &d, int tile0, int rel)
+{
+    __shared__ float s_pose[7][64];
+    __shared__ int s_nb[kKfMaxNb][64];
+    __shared__ int s_loop[64];
+    const int lane = threadIdx.x & 63;
+    const int i = (tile0 + rel) * 64 + lane;
+    kf_select(d, i, lane, s_pose, s_nb, s_loop);
+    const KfTail t = kf_tail(d);
+    for (int s = 0; s < kKfMaxNb; ++s) t.nb[((size_t)rel * kKfMaxNb + s) * 64 + lane] = s_nb[s][lane];
+    t.loop[(size_t)rel * 64 + lane] = s_loop[lane];
+}
+
+// One sub-chunk c of one tail tile for every neighbour (the sums kf_tile_buf forms).
+template <int DT, bool SKIP, bool GLB>
+__device__ __forceinline__ void kf_tail_chunk(const StepDesc &d, int tile0, int pass, int rel, int c)
+{
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    const int N = d.N, n_nb = d.n_nb;
+    const int i = (tile0 + rel) * 64 + lane;
+    const int ic = i < N ? i : N - 1;
+    GridK g;
+    const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
+    g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
+                                             GLB ? 0 : (int)((uint32_t)d.grid_stride * (uint32_t)d.K),
+                                             kRsrcWord3);
+    g.gbase = static_cast<const char *>(d.cells);
+    g.zero = static_cast<const char *>(d.zero_rec);
+    g.nxm = cxn; g.nym = cyn; g.nzm = czn;
+    g.cx = cxn;
+    g.cxy = cxn * cyn;
+    g.eps = d.eps;
+    const double ih = 1.0 / (double)d.h;
+    const int M = d.M, Q = sub_chunk_len(M);
+    float tf[3], qf[4];
+    tail_pose(d, i, pass, tf, qf);
+    const KfTail t = kf_tail(d);
+    for (int s = 0; s < n_nb; ++s) {
+        const int k = t.nb[((size_t)rel * kKfMaxNb + s) * 64 + lane];
+        GridMap64 gm;
+        kf_grid_map(d, k, ic, tf, qf, ih, gm);
+        gm.base = GLB ? 0u : (uint32_t)k * (uint32_t)d.grid_stride;
+        if (GLB) g.gbase = static_cast<const char *>(d.cells) + (uint64_t)k * (uint64_t)d.grid_stride;
+        Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        eval_range64<DT, false, SKIP, !GLB, GLB>(g, (scan64_ptr)d.scan8, min(M, c * Q), min(M, (c + 1) * Q),
+                                                 gm, part);
+        const size_t r = ((size_t)rel * kSubChunks + c) * kKfMaxNb + s;
+        t.l[r * 64 + lane] = part.l;
+        float *tg = t.g + r * 6 * 64 + lane;
+        tg[0] = part.ax; tg[64] = part.ay; tg[128] = part.az;
+        tg[192] = part.bx; tg[256] = part.by; tg[320] = part.bz;
+    }
+}
+
+// Reduce one tail tile's sums in kf_tile_buf's order (wave w: neighbour by
+// neighbour, its kSubChunks / W sub-chunks each), the same epilogue and
+// keyframe propagation, and the pose back to memory.  W waves per tile.
+template <int W>
+__device__ __forceinline__ void kf_tail_step(const StepDesc &d, int tile0, int pass, int rel)
+{
+#pragma clang fp contract(off)
+    __shared__ double s_l[W][64];
+    __shared__ float s_g[6][W][64];
+    __shared__ float s_pose[7][64];
+    __shared__ int s_loop[64];
+    __shared__ float s_upd[9][64];
+    __shared__ float s_seg[W][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int N = d.N, n_nb = d.n_nb;
+    const int i = (tile0 + rel) * 64 + lane;
+    const int ic = i < N ? i : N - 1;
+    const KfTail t = kf_tail(d);
+    if (wave == 0) {
+        float tf[3], qf[4];
+        tail_pose(d, i, pass, tf, qf);
+        s_pose[0][lane] = tf[0]; s_pose[1][lane] = tf[1]; s_pose[2][lane] = tf[2];
+        s_pose[3][lane] = qf[0]; s_pose[4][lane] = qf[1]; s_pose[5][lane] = qf[2]; s_pose[6][lane] = qf[3];
+        s_loop[lane] = t.loop[(size_t)rel * 64 + lane];
+    }
+    __syncthreads();
+    const double ih = 1.0 / (double)d.h;
+    constexpr int S = kSubChunks / W;
+    double l = 0.0;
+    float gsum[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int s = 0; s < n_nb; ++s) {
+        const float tf[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
+        const float qf[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
+        const int k = t.nb[((size_t)rel * kKfMaxNb + s) * 64 + lane];
+        GridMap64 gm;
+        kf_grid_map(d, k, ic, tf, qf, ih, gm);
+        Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (int sc = 0; sc < S; ++sc) {
+            const size_t r = ((size_t)rel * kSubChunks + wave * S + sc) * kKfMaxNb + s;
+            const float *tg = t.g + r * 6 * 64 + lane;
+            const Acc part = {t.l[r * 64 + lane], tg[0], tg[64], tg[128], tg[192], tg[256], tg[320]};
+            add_acc(acc, part);
+        }
+        kf_add_neighbour(gm, d.h, acc, l, gsum);
+    }
+    s_l[wave][lane] = l;
+    for (int c = 0; c < 6; ++c) s_g[c][wave][lane] = gsum[c];
+    __syncthreads();
+    if (wave == 0) {
+        if (d.kf_loop)
+            tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose, s_loop, s_upd);
+        else
+            tile_epilogue<W>(d, i, lane, pass, s_l, s_g, s_pose);
+    }
+    __syncthreads();
+    if (d.kf_loop && pass < d.iters) {
+        kf_propagate<W>(d, i, lane, wave, s_loop, s_upd, s_seg);
+        __syncthreads();
+    }
+    if (wave == 0) store_tile_pose(d, i, lane, s_pose);
 }
 
 // ---------------------------------------------------------------------------
@@ -1911,6 +2075,27 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     kf_tile_buf<DT, SKIP, W, GLB>(d, blockIdx.x);
 }
 
+__global__ __launch_bounds__(64) void k_kf_tail_select(StepDesc d, int tile0)
+{
+    kf_tail_select(d, tile0, blockIdx.x);
+}
+
+// Eight waves per block, one sub-chunk each (as k_eval_tail).
+template <int DT, bool SKIP, bool GLB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_kf_tail_chunk(StepDesc d, int tile0,
+                                                                                              int pass)
+{
+    constexpr int G = kSubChunks / 8;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    kf_tail_chunk<DT, SKIP, GLB>(d, tile0, pass, blockIdx.x / G, (blockIdx.x % G) * 8 + wave);
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_kf_tail_step(StepDesc d, int tile0, int pass)
+{
+    kf_tail_step<W>(d, tile0, pass, blockIdx.x);
+}
+
 // Four waves per SIMD (128 VGPRs): the spills this costs are cheaper than the
 // latency hiding that fewer waves give up.
 template <int W>
@@ -1970,8 +2155,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
 // ---------------------------------------------------------------------------
 
 constexpr int kEvalW = 8;   // waves per workgroup
-constexpr int kKfW = 4;
-constexpr int kGicpW = 4;
+constexpr int kKfW = 8;
+constexpr int kGicpW = 8;
 
 hipError_t launch_build_cells(const float *grid, void *cells, int nx, int ny, int nz, int dtype,
                               hipStream_t st)
@@ -2004,40 +2189,62 @@ bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe)
     return (n_rec << (dtype == 0 ? 5 : 4)) <= (uint64_t)kOutside && !(keyframe && slab);
 }
 
-// Tiles of the single-grid kernel resident on the device at once (cached per device).
-static int eval_round_tiles(int dtype)
+// Tiles of the evaluation kernel (single grid, or keyframe map) resident on
+// the device at once, and the compute units (cached per device).
+static void eval_round(int dtype, bool kf, int &round, int &cus)
 {
     static std::mutex mu;
-    static std::map<std::pair<int, int>, int> cache;
+    static std::map<std::pair<int, int>, std::pair<int, int>> cache;
+    round = cus = 0;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    const int key = dtype + (kf ? 3 : 0);
     std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find({dev, dtype});
-    if (it != cache.end()) return it->second;
-    int per_cu = 0, cus = 0;
-    const void *fn = dtype == 0   ? reinterpret_cast<const void *>(&k_eval<0, false, false, kEvalW>)
-                     : dtype == 1 ? reinterpret_cast<const void *>(&k_eval<1, false, false, kEvalW>)
-                                  : reinterpret_cast<const void *>(&k_eval<2, false, false, kEvalW>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kEvalW, 0) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    const int r = per_cu * cus;
-    cache[{dev, dtype}] = r;
-    return r;
+    auto it = cache.find({dev, key});
+    if (it != cache.end()) {
+        round = it->second.first;
+        cus = it->second.second;
+        return;
+    }
+    const void *fn;
+    int threads;
+    if (kf) {
+        fn = dtype == 0   ? reinterpret_cast<const void *>(&k_kf_eval<0, false, kKfW, false>)
+             : dtype == 1 ? reinterpret_cast<const void *>(&k_kf_eval<1, false, kKfW, false>)
+                          : reinterpret_cast<const void *>(&k_kf_eval<2, false, kKfW, false>);
+        threads = 64 * kKfW;
+    } else {
+        fn = dtype == 0   ? reinterpret_cast<const void *>(&k_eval<0, false, false, kEvalW>)
+             : dtype == 1 ? reinterpret_cast<const void *>(&k_eval<1, false, false, kEvalW>)
+                          : reinterpret_cast<const void *>(&k_eval<2, false, false, kEvalW>);
+        threads = 64 * kEvalW;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        cus = 0;
+        return;
+    }
+    round = per_cu * cus;
+    cache[{dev, key}] = {round, cus};
 }
 
-// The last round of tiles is split when it fills at most a quarter of the
-// device; a session of at most three quarters of one round is split whole
-// (its waves then fill the device instead of leaving a quarter of it idle
-// for a whole tile's time).
-int eval_tail_tiles(int N, int dtype)
+// A launch of at least one full round leaves its tiles unevenly spread over
+// the compute units when the count is not a multiple of their number: the
+// remainder is split when it is at most a quarter of the units.  A single-grid
+// session of at most three quarters of one round is split whole (its waves
+// then fill the device instead of leaving a quarter of it idle for a whole
+// tile's time).
+int eval_tail_tiles(int N, int dtype, bool keyframes)
 {
-    const int round = eval_round_tiles(dtype);
-    if (round <= 0) return 0;
+    int round = 0, cus = 0;
+    eval_round(dtype, keyframes, round, cus);
+    if (round <= 0 || cus <= 0) return 0;
     const int tiles = particle_tiles(N);
-    if (tiles < round) return 4 * tiles <= 3 * round ? tiles : 0;
-    const int rem = tiles % round;
-    return rem > 0 && rem <= round / 4 ? rem : 0;
+    if (keyframes && tiles < cus) return 0;
+    if (!keyframes && tiles < round) return 4 * tiles <= 3 * round ? tiles : 0;
+    const int rem = tiles % cus;
+    return rem > 0 && rem <= cus / 4 ? rem : 0;
 }
 
 bool eval_supported(const StepDesc &d)
@@ -2068,12 +2275,46 @@ static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st, const TailAu
     const unsigned blocks = (unsigned)particle_tiles(d.N);
     if (d.K > 0) {
         // One buffer can address all keyframe grids when they fit its 32-bit
-        // range; larger maps are read through 64-bit addresses.
+        // range; larger maps are read through 64-bit addresses.  As for single
+        // grids, a small last round of tiles runs as one wave per sub-chunk.
         const bool one_buffer = (uint64_t)d.grid_stride * (uint64_t)d.K <= (uint64_t)kOutside;
-        if (one_buffer)
-            hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW, false>), dim3(blocks), dim3(64 * kKfW), 0, st, d);
-        else
-            hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW, true>), dim3(blocks), dim3(64 * kKfW), 0, st, d);
+        const int tail = d.tail_l ? min(d.tail_tiles, particle_tiles(d.N)) : 0;
+        const unsigned main_tiles = blocks - (unsigned)tail;
+        const bool fork = tail > 0 && main_tiles > 0 && aux != nullptr;
+        const hipStream_t ts = fork ? aux->stream : st;
+        if (fork) {
+            hipError_t e = hipEventRecord(aux->fork, st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(ts, aux->fork, 0);
+            if (e != hipSuccess) return e;
+        }
+        if (tail > 0) {
+            const dim3 gb((unsigned)tail * (kSubChunks / 8));
+            hipLaunchKernelGGL(k_kf_tail_select, dim3((unsigned)tail), dim3(64), 0, ts, d, (int)main_tiles);
+            for (int pass = 0; pass < d.iters + d.post_eval; ++pass) {
+                if (one_buffer)
+                    hipLaunchKernelGGL((k_kf_tail_chunk<DT, SKIP, false>), gb, dim3(512), 0, ts, d,
+                                       (int)main_tiles, pass);
+                else
+                    hipLaunchKernelGGL((k_kf_tail_chunk<DT, SKIP, true>), gb, dim3(512), 0, ts, d,
+                                       (int)main_tiles, pass);
+                hipLaunchKernelGGL((k_kf_tail_step<kKfW>), dim3((unsigned)tail), dim3(64 * kKfW), 0, ts, d,
+                                   (int)main_tiles, pass);
+            }
+        }
+        if (main_tiles > 0) {
+            if (one_buffer)
+                hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW, false>), dim3(main_tiles), dim3(64 * kKfW), 0,
+                                   st, d);
+            else
+                hipLaunchKernelGGL((k_kf_eval<DT, SKIP, kKfW, true>), dim3(main_tiles), dim3(64 * kKfW), 0,
+                                   st, d);
+        }
+        if (fork) {
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess) e = hipEventRecord(aux->join, ts);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, aux->join, 0);
+            if (e != hipSuccess) return e;
+        }
     } else if (big_slab(d) || eval_waves() == kEvalW) {
         // Whole rounds of tiles in one launch; a small last round (tail) with
         // one wave per sub-chunk, pass by pass (the same sums and order).

@@ -44,13 +44,18 @@ struct Layout {
     size_t total;
 };
 
-// Tail tiles of a session on map m (single grids only).
+// Tail tiles of a session on grid map m (single grid or keyframes), and their buffer.
 int session_tail_tiles(const Map *m, int N)
 {
-    return (m->kind == kGridMap && m->K_cap == 0) ? eval_tail_tiles(N, m->desc.dtype) : 0;
+    return m->kind == kGridMap ? eval_tail_tiles(N, m->desc.dtype, m->K_cap > 0) : 0;
 }
 
-Layout session_layout(int N, int M_max, int K, bool gicp, int tail)
+size_t tail_bytes(const Map *m, int tail)
+{
+    return (size_t)tail * (m->K_cap > 0 ? kKfTailBytesPerTile : kTailBytesPerTile);
+}
+
+Layout session_layout(int N, int M_max, int K, bool gicp, size_t tail_size)
 {
     const size_t n = (size_t)N, nb = (size_t)weight_blocks(N);
     const size_t sizes[] = {
@@ -74,7 +79,7 @@ Layout session_layout(int N, int M_max, int K, bool gicp, int tail)
         (gicp ? (size_t)M_max * kVoxelRecordBytes : 0),   // 17 scan_g
         (gicp ? (size_t)M_max * 6 * 4 : 0),                // 18 cov6
         (gicp ? 21 * n * 4 : 0),                           // 19 hess
-        (size_t)tail * kTailBytesPerTile,                  // 20 tail sub-chunk sums
+        tail_size,                                         // 20 tail sub-chunk sums
     };
     Layout L{};
     size_t o = 0;
@@ -725,8 +730,8 @@ mcs_status mcs_session_bytes(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M_
         K = it->second->K_cap;
         gicp = it->second->kind == kVoxelMap;
         tail = session_tail_tiles(it->second, N);
+        *bytes = session_layout(N, M_max, K, gicp, tail_bytes(it->second, tail)).total;
     }
-    *bytes = session_layout(N, M_max, K, gicp, tail).total;
     return MCS_OK;
 }
 
@@ -748,7 +753,7 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
         if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
         m = it->second;
         if (m->K > 0 && !kf_poses) return fail(MCS_EINVAL, "keyframe map needs kf_poses");
-        L = session_layout(N, M_max, m->K_cap, m->kind == kVoxelMap, session_tail_tiles(m, N));
+        L = session_layout(N, M_max, m->K_cap, m->kind == kVoxelMap, tail_bytes(m, session_tail_tiles(m, N)));
         Lp = &L;
         if (!budget_allows(ctx, L.total))
             return fail(MCS_EBUDGET, "session needs %zu bytes; budget %llu, in use %llu", L.total,
@@ -822,7 +827,7 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
         if (e != hipSuccess) { ss->tail_fork = nullptr; return undo(hip_fail(e, "hipEventCreate")); }
         e = hipEventCreateWithFlags(&ss->tail_join, hipEventDisableTiming);
         if (e != hipSuccess) { ss->tail_join = nullptr; return undo(hip_fail(e, "hipEventCreate")); }
-        ss->tail_g = (float *)(b + L.off[20] + (size_t)tail * kSubChunks * 64 * 8);
+        if (m->K_cap == 0) ss->tail_g = (float *)(b + L.off[20] + (size_t)tail * kSubChunks * 64 * 8);
     }
     e = hipMemsetAsync(ss->block, 0, L.total, ss->stream);
     if (e != hipSuccess) return undo(hip_fail(e, "hipMemset(session)"));

@@ -94,7 +94,9 @@ def test_keyframe_full_scale_sampled(ctx):
     c = configs.keyframes(N=50000, K=64)
     p = dict(c["params"], iters=1, u=c["u"], beta=1.0, resample=abi.RESAMPLE_ESS)
     out = kf_step(ctx, c, p)
-    idx = np.sort(np.random.default_rng(0).choice(50000, 128, replace=False))
+    # 128 random particles and the last 64 (on MI355X the last 14 tiles are
+    # spread over one wave per sub-chunk).
+    idx = np.union1d(np.random.default_rng(0).choice(50000, 128, replace=False), np.arange(50000 - 64, 50000))
     check_kf(c, out, p, idx=idx)
     check_weights_resample(c["logw"], out["loglik"], 1.0, p["u"], out, abi.RESAMPLE_ESS)
 
@@ -149,6 +151,27 @@ def test_loop_closure_out_and_back(ctx):
     assert np.all(ref["loop"] >= 0)
     moved = np.abs(out["kf_poses"][:, 1:, :3] - c["kf_poses"][:, 1:, :3]).max()
     assert moved > 1e-3
+
+
+def test_loop_closure_with_tail_tiles(ctx):
+    """261 tiles of 64 particles: 256 in the main launch and, on a 256-CU device,
+    5 spread over one wave per sub-chunk; the loop-gated correction and its
+    keyframe propagation run in both."""
+    N = 261 * 64
+    c = configs.keyframes(N=N, K=16, kf_points=4096, seed=39, out_and_back=True)
+    p = dict(c["params"], iters=2, u=0.3, beta=0.01, resample=abi.RESAMPLE_NEVER,
+             kf_update=abi.KF_LOOP, n_recent=4)
+    out = kf_step(ctx, c, p)
+    idx = np.union1d(np.arange(0, N, 97), np.arange(N - 5 * 64, N))
+    # The first pass's likelihood and gradient at the input poses and keyframes.
+    p1 = dict(p, iters=1)
+    out1 = kf_step(ctx, c, p1)
+    check_kf(c, out1, p1, idx=idx)
+    check_loop_update(c["poses"], c["kf_poses"], out1, p1, n_recent=4)
+    # Two passes: deterministic, and the same as a second run.
+    again = kf_step(ctx, c, p)
+    for k in ("poses", "kf_poses", "loglik", "grad", "neighbors"):
+        assert np.array_equal(out[k], again[k]), k
 
 
 def test_loop_gate_mixed_particles(ctx):
