@@ -70,6 +70,25 @@ def cpu_cores():
         return os.cpu_count() or 1
 
 
+def device_copy_gbps(torch, mib=1024, reps=10):
+    """HBM bandwidth of a plain device-to-device copy (bytes read + written per
+    second), the stream-copy figure beside the evaluation's gather rate."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    secs = a.elapsed_time(b) * 1e-3 / reps
+    del src, dst
+    return 2.0 * n * 4 / secs / 1e9
+
+
 def run_cpu_baseline(c, frame, n_sample, threads=None):
     """The FP64 oracle on one frame for n_sample particles (all host threads by default)."""
     import oracle
@@ -460,6 +479,8 @@ def main():
     host_ms = 1e3 * (time.perf_counter() - t0) / n_host
     log("host-buffer entry point: %.3f ms/step" % host_ms)
     abi.mcs_destroy(ctx)
+    copy_gbps = device_copy_gbps(torch)
+    log("device copy: %.0f GB/s (read + write)" % copy_gbps)
 
     passes = base["iters"]
     evals_per_step = N * M * passes
@@ -543,6 +564,8 @@ def main():
         "trilinear_samples_per_s": round(value, 1),
         "grid_element_gathers_per_s": round(8 * value, 1),
         "host_buffers_ms_per_step": round(host_ms, 4),
+        "device_copy_GBps": round(copy_gbps, 1),
+        "hbm_equivalent_gather_evals_per_s": round(copy_gbps * 1e9 / BYTES_PER_EVAL[args.grid_dtype], 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cpu_baseline_one_thread": cpu1,

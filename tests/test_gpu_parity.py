@@ -235,3 +235,24 @@ def test_rejects_samples_outside_unit_range_and_tiny_eps(ctx, box_room):
     finally:
         abi.mcs_session_destroy(ctx, sid)
         abi.mcs_release_map(ctx, mid)
+
+
+@pytest.mark.parametrize("N,dtype,oob", [(40000, abi.GRID_FP16, abi.OOB_FLOOR),
+                                          (40000, abi.GRID_BF16, abi.OOB_SKIP),
+                                          (33000, abi.GRID_FP16, abi.OOB_SKIP),
+                                          (33000, abi.GRID_FP32, abi.OOB_FLOOR)])
+def test_whole_rounds_and_tail_all_record_types(ctx, N, dtype, oob):
+    """Sessions large enough for the main launch (N = 40,000: 625 tiles, no
+    split on a 256-CU device; N = 33,000: 516 tiles, the last 4 split), every
+    record type and both outside-point modes, sampled particles incl. the last."""
+    c = configs.box_room(N=N, seed=91)
+    p = dict(c["params"], u=0.61, beta=0.002, oob=oob, resample=abi.RESAMPLE_ESS)
+    out = one_step(ctx, c, p, dtype=dtype)
+    idx = np.union1d(np.arange(0, N, 211), np.arange(N - 300, N))
+    g = grid_for(c, dtype)
+    ref = oracle.evaluate(g, c["dims"], c["origin"], c["h"], p["eps"], c["scan"], c["poses"][idx],
+                          oob_skip=oob == abi.OOB_SKIP, delta=DELTA)
+    check_eval(out["loglik"][idx], out["grad"][idx], ref)
+    anc = out["parents"]
+    check_step(c["poses"][anc], out["grad"][anc], out["poses"], p)
+    check_weights_resample(np.full(N, -math.log(N)), out["loglik"], p["beta"], p["u"], out, abi.RESAMPLE_ESS)
