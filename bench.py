@@ -321,6 +321,51 @@ def run_keyframes(abi, steps=5):
     return res
 
 
+def run_precision(abi, torch, c, scans, noise, slot, frames, base, steps=30, warm=5):
+    """FP16 and BF16 grid records (corridors, the same frames): ms per step, the
+    evaluation stage, and the log-likelihoods of the first frame against the
+    FP32 records' (the quantisation error of the stored grid, stated)."""
+    N, M = c["poses"].shape[0], c["scans"].shape[1]
+    out, l32 = {}, None
+    for dt, name in ((0, "fp32"), (1, "fp16"), (2, "bf16")):
+        ctx = abi.mcs_create(0)
+        mid = abi.mcs_init_map(ctx, abi.grid_desc(c["dims"], c["origin"], c["h"], dt), c["grid"])
+        sid = abi.mcs_session_create(ctx, mid, c["poses"], M_max=M)
+
+        def step(f, resample=abi.RESAMPLE_ESS):
+            p = dict(base, u=float(c["u"][f]), delta_T=c["odometry"][f], resample=resample)
+            abi.mcs_filter_step_dev(ctx, sid, scans[f].data_ptr(), M, p,
+                                    noise_dev_ptr=noise[slot[f]].data_ptr())
+
+        step(frames[0], abi.RESAMPLE_NEVER)
+        l = abi.mcs_get_particles(ctx, sid, N)["loglik"].astype(np.float64)
+        abi.mcs_set_particles(ctx, sid, poses=c["poses"], logw=np.full(N, -math.log(N)))
+        for k in range(warm):
+            step(frames[k % len(frames)])
+        torch.cuda.synchronize()
+        abi.mcs_session_profile(ctx, sid, True)
+        t0 = time.perf_counter()
+        for k in range(warm, warm + steps):
+            step(frames[k % len(frames)])
+        abi.mcs_session_sync(ctx, sid)
+        wall = time.perf_counter() - t0
+        prof = abi.mcs_session_profile_read(ctx, sid)
+        abi.mcs_destroy(ctx)
+        r = {"ms_per_step": round(1e3 * wall / steps, 4),
+             "eval_ms": round(prof["eval_ms"] / max(1, prof["steps"]), 4),
+             "evals_per_s": round(N * M * base["iters"] * steps / wall, 1)}
+        if l32 is None:
+            l32 = l
+        else:
+            rel = np.abs(l - l32) / np.abs(l32)
+            r["loglik_rel_diff_vs_fp32_records"] = {"max": float("%.3g" % rel.max()),
+                                                    "median": float("%.3g" % np.median(rel))}
+        out[name] = r
+    return {"workload": "corridors records in FP32, FP16 and BF16 (RNE from the FP32 grid): N=%d, "
+                        "M=%d, 3 passes; first-frame log-likelihoods compared with the FP32 records'"
+                        % (N, M), **out}
+
+
 def run_ambiguous_rooms(abi):
     """Keyframe map of a row of identical rooms (translated copies), K = 64, N = 50,000,
     M = 2,048: the initial cloud copied at four room shifts (12,500 particles each), one step
@@ -481,6 +526,10 @@ def main():
     abi.mcs_destroy(ctx)
     copy_gbps = device_copy_gbps(torch)
     log("device copy: %.0f GB/s (read + write)" % copy_gbps)
+    precision = None
+    if args.extras and args.grid_dtype == 0:
+        precision = run_precision(abi, torch, c, scans, noise, slot, frames, base)
+        log("precision: %s" % precision)
 
     passes = base["iters"]
     evals_per_step = N * M * passes
@@ -573,6 +622,7 @@ def main():
         "p99_session_ms": (min(serving["batched"]["p99_ms"], serving["concurrent"]["p99_ms"])
                            if serving else None),
         "serving": serving,
+        "grid_record_precision": precision,
         "keyframes": keyframes,
         "gicp": gicp,
         "repeated_floors": floors,
