@@ -126,7 +126,7 @@ typedef struct {
     float alpha_r;          /* rotation gain a_r (rad per unit gradient) */
     float rho_max;          /* clamp of |psi_rho| per pass (m) */
     float phi_max;          /* clamp of |psi_phi| per pass (rad) */
-    float eps;              /* likelihood floor in ln(G + eps), in [1e-9, 1] on
+    float eps;              /* likelihood floor in ln(G + eps), in [1e-5, 1] on
                                grid maps (MCS_EINVAL otherwise) */
     float beta;             /* weight exponent: logw += beta * l */
     int32_t oob;            /* MCS_OOB_* */

@@ -524,8 +524,8 @@ __device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, 
 // Four points share one log2 and one reciprocal:
 //   log2(d0 d1 d2 d3),  r = 1 / (d0 d1 d2 d3),  1/(d0 d1) = d2 d3 r,  1/(d2 d3) = d0 d1 r,
 // then 1/d0 = d1 / (d0 d1) and so on.  With grid values in [0, 1] and
-// eps >= 1e-9 every d lies in [1e-9, 1 + eps], so the product of four stays a
-// normal FP32 number.
+// eps >= 1e-5 every d lies in [eps - 3e-6, 1 + eps] (the interpolant's rounding
+// error stays below 3e-6), so the product of four stays a normal FP32 number.
 template <int DT, bool SKIP>
 __device__ __forceinline__ void accumulate4(const GridK &g, const Pt *p, const Cell<DT> *c, Acc &acc)
 {

@@ -250,10 +250,12 @@ mcs_status validate_params(const Session *s, const mcs_step_params *p, int M)
         if (!std::isfinite(f)) return fail(MCS_EINVAL, "non-finite step parameter");
     if (!(p->eps > 0.0f)) return fail(MCS_EINVAL, "eps must be > 0");
     // The point loop multiplies up to four factors G + eps (one log2 and one
-    // reciprocal per product): G in [0, 1] and eps in [1e-9, 1] keep every
-    // product a normal FP32 number.
-    if (s->map->kind == kGridMap && !(p->eps >= 1e-9f && p->eps <= 1.0f))
-        return fail(MCS_EINVAL, "eps=%g outside [1e-9, 1]", (double)p->eps);
+    // reciprocal per product).  The interpolant of samples in [0, 1] is
+    // evaluated with an error below 3e-6 (coefficient rounding and the FMA
+    // chain, worst case), so eps >= 1e-5 keeps every factor positive, and
+    // eps <= 1 keeps the product of four a normal FP32 number.
+    if (s->map->kind == kGridMap && !(p->eps >= 1e-5f && p->eps <= 1.0f))
+        return fail(MCS_EINVAL, "eps=%g outside [1e-5, 1]", (double)p->eps);
     if (p->rho_max < 0.0f || p->phi_max < 0.0f) return fail(MCS_EINVAL, "clamps must be >= 0");
     if (p->oob != MCS_OOB_FLOOR && p->oob != MCS_OOB_SKIP) return fail(MCS_EINVAL, "bad oob mode");
     if (p->resample < MCS_RESAMPLE_NEVER || p->resample > MCS_RESAMPLE_PRUNE)
