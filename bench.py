@@ -29,12 +29,12 @@ sys.path.insert(0, ROOT)
 METRIC = "particle×point lik+grad evals/s; ms/step @100k particles; p99 session ms"
 # The evaluation kernel is bound by VALU issue.  Its algorithmic work is
 # counted in VALU lane-operations (FP32 or FP64, an FMA counting once): the
-# compiled inner loop (gfx950) issues 245 VALU instructions per 4 evaluations
-# with FP32 cell records, 289 with FP16 and 321 with BF16 records.  Peak: 256 CU x 4 SIMD x 16
+# compiled inner loop (gfx950) issues 233 VALU instructions per 4 evaluations
+# with FP32 cell records, 277 with FP16 and 309 with BF16 records.  Peak: 256 CU x 4 SIMD x 16
 # lanes x 2.4 GHz = 39.3e12 lane-ops/s without packed FP32 (disabled in this
 # build); the 157.3 TFLOP/s vector figure counts a packed FMA as 4 flops per
 # lane and cycle.
-VALU_OPS_PER_EVAL = {0: 61.25, 1: 72.25, 2: 80.25}
+VALU_OPS_PER_EVAL = {0: 58.25, 1: 69.25, 2: 77.25}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 BYTES_PER_EVAL = {0: 32, 1: 16, 2: 16}    # one cell record per evaluation
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_corridors_100k_counters.txt")

@@ -309,6 +309,18 @@ struct Acc {
     float bx, by, bz;      // sum of v' x (dG/du / (G + eps)), v' = A p
 };
 
+// Point-loop form of the sums: with d = dG/du / (G + eps) per point, the
+// loop keeps sum d and the outer products S = sum d p^T (p the scan point,
+// sensor frame) instead of sum v' x d.  Since v' = A p, the cross-product sum
+// is recovered per range of points as B_a = e_abc A_be S_ce (e_abc the
+// permutation symbol), so the loop needs neither v' nor a separate
+// translation add.
+struct PtAcc {
+    double l;
+    float ax, ay, az;
+    float s[9];            // s[3c + e] = sum d_c p_e
+};
+
 __device__ __forceinline__ void add_acc(Acc &a, const Acc &b)
 {
 #pragma clang fp contract(off)
@@ -341,17 +353,8 @@ struct GridK {
 // record loads return zeros (G = 0, dG = 0).  Record bytes are < 2^32 - 32.
 constexpr uint32_t kOutside = 0xFFFFFFE0u;
 
-// floor(x) as int32 in one instruction (saturating for out-of-range x).
-__device__ __forceinline__ int cvt_floor(float x)
-{
-    int r;
-    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
-}
-
-// Transformed point, cell fractions and record offset.
+// Cell fractions and record offset of a transformed point.
 struct Pt {
-    float vx, vy, vz;      // v' = A p (grid units)
     float fx, fy, fz;      // position inside the cell
     uint32_t off;          // byte offset of the cell record, kOutside when outside
     bool inside;
@@ -430,21 +433,25 @@ __device__ __forceinline__ void trilinear<0>(const Cell<0> &cell, float fx, floa
     gy = fmaf(fmaf(a7, fx, a6), fz, fmaf(a4, fx, a2));
 }
 
-// Gradient sums of one point given 1/(G + eps).
-__device__ __forceinline__ void add_grad(const Pt &p, float gx, float gy, float gz, float inv,
-                                         Acc &acc)
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) f4v *scan32_ptr;
+
+// Gradient sums of one point (scan point pf, uniform over the wave) given
+// 1/(G + eps).
+__device__ __forceinline__ void add_grad(const f4v &pf, float gx, float gy, float gz, float inv,
+                                         PtAcc &acc)
 {
 #pragma clang fp contract(off)
     const float dx = gx * inv, dy = gy * inv, dz = gz * inv;
     acc.ax += dx; acc.ay += dy; acc.az += dz;
-    acc.bx = fmaf(p.vy, dz, fmaf(-p.vz, dy, acc.bx));
-    acc.by = fmaf(p.vz, dx, fmaf(-p.vx, dz, acc.by));
-    acc.bz = fmaf(p.vx, dy, fmaf(-p.vy, dx, acc.bz));
+    acc.s[0] = fmaf(dx, pf.x, acc.s[0]); acc.s[1] = fmaf(dx, pf.y, acc.s[1]); acc.s[2] = fmaf(dx, pf.z, acc.s[2]);
+    acc.s[3] = fmaf(dy, pf.x, acc.s[3]); acc.s[4] = fmaf(dy, pf.y, acc.s[4]); acc.s[5] = fmaf(dy, pf.z, acc.s[5]);
+    acc.s[6] = fmaf(dz, pf.x, acc.s[6]); acc.s[7] = fmaf(dz, pf.y, acc.s[7]); acc.s[8] = fmaf(dz, pf.z, acc.s[8]);
 }
 
 template <int DT, bool SKIP>
-__device__ __forceinline__ void accumulate1(const GridK &g, const Pt &p, const Cell<DT> &c,
-                                            Acc &acc)
+__device__ __forceinline__ void accumulate1(const GridK &g, const Pt &p, const f4v &pf,
+                                            const Cell<DT> &c, PtAcc &acc)
 {
 #pragma clang fp contract(off)
     float G, x, y, z;
@@ -452,17 +459,18 @@ __device__ __forceinline__ void accumulate1(const GridK &g, const Pt &p, const C
     float d = G + g.eps;
     if (SKIP) d = p.inside ? d : 1.0f;
     acc.l += (double)fast_log2(d);
-    add_grad(p, x, y, z, fast_rcp(d), acc);
+    add_grad(pf, x, y, z, fast_rcp(d), acc);
 }
 
 // The per-point transform runs in FP64: the grid map A = R/h, b stays in
 // FP64, points arrive as FP64 (scalar loads of the FP64 copy of the scan), and
 // u = A p + b, floor(u) and the fraction are computed in FP64; only the
-// fraction and v' are rounded to FP32.  An FP32 A would carry one rounding
+// fraction is rounded to FP32.  An FP32 A would carry one rounding
 // shared by every point of the particle, a systematic error that the peaked
 // likelihood turns into gradient errors of order 1e-4 of the summation scale.
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) d4v *scan64_ptr;
+typedef double d16v __attribute__((ext_vector_type(16)));
 
 struct GridMap64 {
     double A[9];
@@ -503,11 +511,9 @@ __device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, 
 #pragma clang fp contract(off)
     Pt p;
     const double *A = gm.A;
-    const double vx = fma(A[0], px, fma(A[1], py, A[2] * pz));
-    const double vy = fma(A[3], px, fma(A[4], py, A[5] * pz));
-    const double vz = fma(A[6], px, fma(A[7], py, A[8] * pz));
-    const double ux = vx + gm.b[0], uy = vy + gm.b[1], uz = vz + gm.b[2];
-    p.vx = (float)vx; p.vy = (float)vy; p.vz = (float)vz;
+    const double ux = fma(A[0], px, fma(A[1], py, fma(A[2], pz, gm.b[0])));
+    const double uy = fma(A[3], px, fma(A[4], py, fma(A[5], pz, gm.b[1])));
+    const double uz = fma(A[6], px, fma(A[7], py, fma(A[8], pz, gm.b[2])));
     const int ix = cvt_floor_d(ux), iy = cvt_floor_d(uy), iz = cvt_floor_d(uz);
     p.fx = (float)__builtin_amdgcn_fract(ux);
     p.fy = (float)__builtin_amdgcn_fract(uy);
@@ -527,7 +533,8 @@ __device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, 
 // eps >= 1e-5 every d lies in [eps - 3e-6, 1 + eps] (the interpolant's rounding
 // error stays below 3e-6), so the product of four stays a normal FP32 number.
 template <int DT, bool SKIP>
-__device__ __forceinline__ void accumulate4(const GridK &g, const Pt *p, const Cell<DT> *c, Acc &acc)
+__device__ __forceinline__ void accumulate4(const GridK &g, const Pt *p, const f4v *pf,
+                                            const Cell<DT> *c, PtAcc &acc)
 {
 #pragma clang fp contract(off)
     float G[4], x[4], y[4], z[4], d[4];
@@ -542,10 +549,10 @@ __device__ __forceinline__ void accumulate4(const GridK &g, const Pt *p, const C
     acc.l += (double)fast_log2(prod);
     const float r = fast_rcp(prod);
     const float r01 = p23 * r, r23 = p01 * r;
-    add_grad(p[0], x[0], y[0], z[0], d[1] * r01, acc);
-    add_grad(p[1], x[1], y[1], z[1], d[0] * r01, acc);
-    add_grad(p[2], x[2], y[2], z[2], d[3] * r23, acc);
-    add_grad(p[3], x[3], y[3], z[3], d[2] * r23, acc);
+    add_grad(pf[0], x[0], y[0], z[0], d[1] * r01, acc);
+    add_grad(pf[1], x[1], y[1], z[1], d[0] * r01, acc);
+    add_grad(pf[2], x[2], y[2], z[2], d[3] * r23, acc);
+    add_grad(pf[3], x[3], y[3], z[3], d[2] * r23, acc);
 }
 
 // Record of a prepared point: from the buffer (an outside point's offset lies
@@ -561,32 +568,55 @@ __device__ __forceinline__ void fetch(const GridK &g, const Pt &p, Cell<DT> &c)
 }
 
 // Points [j0, j1) of the scan against one pose, four at a time: the four
-// record loads are issued before any of their arithmetic.
+// points' FP64 coordinates arrive in one 128 B scalar load, and each point's
+// record loads are issued as soon as its offset is known (a scheduling
+// barrier keeps them ahead of the next point's transform), before any of the
+// four points' arithmetic.  The range's sums are stored in acc (l, sum d and
+// B = sum v' x d, v' = A p).
 template <int DT, bool BIG, bool SKIP, bool KF = false, bool GLB = false>
-__device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, int j0, int j1,
-                                             const GridMap64 &gm, Acc &acc)
+__device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, scan32_ptr scanf,
+                                             int j0, int j1, const GridMap64 &gm, Acc &acc)
 {
 #pragma clang fp contract(off)
+    PtAcc pa = {0.0, 0.0f, 0.0f, 0.0f, {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f}};
     int j = j0;
     constexpr int U = 4;
     for (; j + U <= j1; j += U) {
         Pt p[U];
+        f4v pf[U];
         Cell<DT> c[U];
+        const d16v sq = *(const __attribute__((address_space(4))) d16v *)(scan + j);
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            const d4v s = scan[j + k];
-            p[k] = prep_point64<DT, BIG, KF>(g, gm, s.x, s.y, s.z);
+            p[k] = prep_point64<DT, BIG, KF>(g, gm, sq[4 * k], sq[4 * k + 1], sq[4 * k + 2]);
             fetch<DT, GLB>(g, p[k], c[k]);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        accumulate4<DT, SKIP>(g, p, c, acc);
+#pragma unroll
+        for (int k = 0; k < U; ++k) pf[k] = scanf[j + k];
+        accumulate4<DT, SKIP>(g, p, pf, c, pa);
     }
     for (; j < j1; ++j) {
         const d4v s = scan[j];
+        const f4v pf = scanf[j];
         const Pt p = prep_point64<DT, BIG, KF>(g, gm, s.x, s.y, s.z);
         Cell<DT> c;
         fetch<DT, GLB>(g, p, c);
-        accumulate1<DT, SKIP>(g, p, c, acc);
+        accumulate1<DT, SKIP>(g, p, pf, c, pa);
     }
+    // B_a = e_abc A_be S_ce, in FP64 from the FP32 sums.
+    const double *A = gm.A;
+    double S[9];
+    for (int e = 0; e < 9; ++e) S[e] = (double)pa.s[e];
+    double B[3] = {0.0, 0.0, 0.0};
+    for (int e = 0; e < 3; ++e) {
+        B[0] = fma(A[3 + e], S[6 + e], fma(-A[6 + e], S[3 + e], B[0]));
+        B[1] = fma(A[6 + e], S[e], fma(-A[e], S[6 + e], B[1]));
+        B[2] = fma(A[e], S[3 + e], fma(-A[3 + e], S[e], B[2]));
+    }
+    acc.l = pa.l;
+    acc.ax = pa.ax; acc.ay = pa.ay; acc.az = pa.az;
+    acc.bx = (float)B[0]; acc.by = (float)B[1]; acc.bz = (float)B[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -726,7 +756,7 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
             for (int sc = 0; sc < S; ++sc) {
                 const int c = wave * S + sc;
                 Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                eval_range64<DT, BIG, SKIP>(g, (scan64_ptr)d.scan8, min(M, c * Q), min(M, (c + 1) * Q),
+                eval_range64<DT, BIG, SKIP>(g, (scan64_ptr)d.scan8, (scan32_ptr)d.scan4, min(M, c * Q), min(M, (c + 1) * Q),
                                             gm, part);
                 add_acc(acc, part);
             }
@@ -781,7 +811,7 @@ __device__ __forceinline__ void tail_chunk(const StepDesc &d, int tile0, int pas
     GridMap64 gm;
     grid_map64(t, q, d.ox, d.oy, d.oz, d.h, gm);
     Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    eval_range64<DT, BIG, SKIP>(g, (scan64_ptr)d.scan8, min(M, c * Q), min(M, (c + 1) * Q), gm, part);
+    eval_range64<DT, BIG, SKIP>(g, (scan64_ptr)d.scan8, (scan32_ptr)d.scan4, min(M, c * Q), min(M, (c + 1) * Q), gm, part);
     const size_t r = (size_t)rel * kSubChunks + c;
     d.tail_l[r * 64 + lane] = part.l;
     float *tg = d.tail_g + r * 6 * 64 + lane;
@@ -1340,7 +1370,7 @@ __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
             for (int sc = 0; sc < S; ++sc) {
                 const int c = wave * S + sc;
                 Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                eval_range64<DT, false, SKIP, !GLB, GLB>(g, (scan64_ptr)d.scan8, min(M, c * Q),
+                eval_range64<DT, false, SKIP, !GLB, GLB>(g, (scan64_ptr)d.scan8, (scan32_ptr)d.scan4, min(M, c * Q),
                                                          min(M, (c + 1) * Q), gm, part);
                 add_acc(acc, part);
             }
@@ -1432,7 +1462,7 @@ __device__ __forceinline__ void kf_tail_chunk(const StepDesc &d, int tile0, int 
         gm.base = GLB ? 0u : (uint32_t)k * (uint32_t)d.grid_stride;
         if (GLB) g.gbase = static_cast<const char *>(d.cells) + (uint64_t)k * (uint64_t)d.grid_stride;
         Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        eval_range64<DT, false, SKIP, !GLB, GLB>(g, (scan64_ptr)d.scan8, min(M, c * Q), min(M, (c + 1) * Q),
+        eval_range64<DT, false, SKIP, !GLB, GLB>(g, (scan64_ptr)d.scan8, (scan32_ptr)d.scan4, min(M, c * Q), min(M, (c + 1) * Q),
                                                  gm, part);
         const size_t r = ((size_t)rel * kSubChunks + c) * kKfMaxNb + s;
         t.l[r * 64 + lane] = part.l;
