@@ -416,7 +416,9 @@ def main():
     ap.add_argument("--serving-load", type=float, default=1.0,
                     help="multiplier on the 10 Hz per-session arrival rate")
     ap.add_argument("--extras", type=int, default=1,
-                    help="1: also report the keyframe-map timing and the repeated-floors demo")
+                    help="1: also report the record-precision table, the keyframe-map and GICP "
+                         "timings and the repeated-floors demo; 2: only the keyframe-map and GICP "
+                         "timings (for profiling those kernels)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -527,7 +529,7 @@ def main():
     copy_gbps = device_copy_gbps(torch)
     log("device copy: %.0f GB/s (read + write)" % copy_gbps)
     precision = None
-    if args.extras and args.grid_dtype == 0:
+    if args.extras == 1 and args.grid_dtype == 0:
         precision = run_precision(abi, torch, c, scans, noise, slot, frames, base)
         log("precision: %s" % precision)
 
@@ -576,14 +578,16 @@ def main():
         log("keyframe-map timing")
         keyframes = run_keyframes(abi)
         log("keyframes: %s" % keyframes)
-        keyframes["ambiguous_rooms"] = run_ambiguous_rooms(abi)
-        log("ambiguous rooms: %s" % keyframes["ambiguous_rooms"])
+        if args.extras == 1:
+            keyframes["ambiguous_rooms"] = run_ambiguous_rooms(abi)
+            log("ambiguous rooms: %s" % keyframes["ambiguous_rooms"])
         log("GICP timing")
         gicp = run_gicp(abi)
         log("gicp: %s" % gicp)
-        log("repeated-floors demo")
-        floors = run_floors(abi)
-        log("floors: %s" % floors)
+        if args.extras == 1:
+            log("repeated-floors demo")
+            floors = run_floors(abi)
+            log("floors: %s" % floors)
     serving = None
     if args.serving_seconds > 0:
         serving = run_serving(args, abi, torch, prepared)
