@@ -281,19 +281,10 @@ __device__ __forceinline__ float half_lo(uint32_t v)
 {
     return (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu));
 }
-__device__ __forceinline__ float half_hi(uint32_t v)
-{
-    return (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
-}
 
-// Corner samples of a 16-bit record (FP32 records hold polynomial
-// coefficients instead and are not decoded).
+// Corner samples of a BF16 record (FP32 records hold polynomial coefficients
+// and FP16 records feed mixed-precision FMAs, so neither is decoded).
 template <int DT> __device__ __forceinline__ void decode(const Cell<DT> &c, float v[8]);
-template <> __device__ __forceinline__ void decode<1>(const Cell<1> &c, float v[8])
-{
-    v[0] = half_lo(c.a.x); v[1] = half_hi(c.a.x); v[2] = half_lo(c.a.y); v[3] = half_hi(c.a.y);
-    v[4] = half_lo(c.a.z); v[5] = half_hi(c.a.z); v[6] = half_lo(c.a.w); v[7] = half_hi(c.a.w);
-}
 template <> __device__ __forceinline__ void decode<2>(const Cell<2> &c, float v[8])
 {
     v[0] = __uint_as_float(c.a.x << 16); v[1] = __uint_as_float(c.a.x & 0xffff0000u);
@@ -394,7 +385,7 @@ __device__ __forceinline__ float half_hi_minus_lo(uint32_t c)
 
 // FP16 corners: the first x lerps read the packed samples directly through
 // mixed-precision FMAs, so no sample is decoded separately.  Same arithmetic,
-// and results, as the generic form.
+// and results, as the generic form applied to the decoded FP16 samples.
 template <>
 __device__ __forceinline__ void trilinear<1>(const Cell<1> &cell, float fx, float fy, float fz,
                                              float &G, float &gx, float &gy, float &gz)
