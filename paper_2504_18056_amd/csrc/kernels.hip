@@ -2276,20 +2276,6 @@ bool eval_supported(const StepDesc &d)
     return grid_supported(d.nx, d.ny, d.nz, d.dtype, false);
 }
 
-// Waves per workgroup of the evaluation kernel: each wave takes a contiguous
-// share of the scan for the block's 64 particles.  MCSLAM_EVAL_WAVES (4, 8 or
-// 16) overrides the default for measurement.
-static int eval_waves()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("MCSLAM_EVAL_WAVES");
-        const int w = e ? atoi(e) : 0;
-        v = (w == 4 || w == 8 || w == 16) ? w : kEvalW;
-    }
-    return v;
-}
-
 template <int DT, bool SKIP>
 static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st, const TailAux *aux)
 {
@@ -2336,7 +2322,7 @@ static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st, const TailAu
             if (e == hipSuccess) e = hipStreamWaitEvent(st, aux->join, 0);
             if (e != hipSuccess) return e;
         }
-    } else if (big_slab(d) || eval_waves() == kEvalW) {
+    } else {
         // Whole rounds of tiles in one launch; a small last round (tail) with
         // one wave per sub-chunk, pass by pass (the same sums and order).
         const int tail = d.tail_l ? min(d.tail_tiles, particle_tiles(d.N)) : 0;
@@ -2372,14 +2358,6 @@ static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st, const TailAu
             if (e == hipSuccess) e = hipEventRecord(aux->join, ts);
             if (e == hipSuccess) e = hipStreamWaitEvent(st, aux->join, 0);
             if (e != hipSuccess) return e;
-        }
-    } else {
-        switch (eval_waves()) {
-        case 16:
-            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 16>), dim3(blocks), dim3(64 * 16), 0, st, d);
-            break;
-        default:
-            hipLaunchKernelGGL((k_eval<DT, false, SKIP, 4>), dim3(blocks), dim3(64 * 4), 0, st, d);
         }
     }
     return hipGetLastError();
