@@ -623,3 +623,28 @@ def repeated_floors(N=20000, floors=4, true_floor=2, n_frames=80, M_rings=8, n_a
                 floors=floors, true_floor=true_floor, storey=storey, feature_frame=fk,
                 first_seen=first_seen,
                 floor_of_start=floor_of, scene=scene)
+
+
+def wide_slab(N=33000, M=300, seed=1007, n_xy=4098, h=0.05, sigma=0.1):
+    """A grid whose row-by-column slab holds 2^24 or more cells (n_xy = 4098:
+    4097^2 cells per slab), three samples thick, with a smooth field in [0.1,
+    0.9]; particles near the far corner (cell indices near 3,800-3,900), level
+    within 0.1 deg, at mid-slab height; a planar scan of radius <= 5 m."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(n_xy, dtype=np.float64)
+    fx = np.sin(0.07 * i + 0.3)
+    fy = np.cos(0.05 * i)
+    fz = np.array([-0.1, 0.0, 0.1])
+    grid = (0.5 + 0.3 * fy[None, :, None] * fx[None, None, :] + fz[:, None, None]).astype(np.float32)
+    r = rng.uniform(0.5, 5.0, M)
+    a = rng.uniform(0.0, 2.0 * np.pi, M)
+    scan = np.stack([r * np.cos(a), r * np.sin(a), np.zeros(M)], axis=1).astype(np.float32)
+    t = np.stack([190.0 + rng.normal(0.0, 0.5, N), 195.0 + rng.normal(0.0, 0.5, N),
+                  1.5 * h + rng.normal(0.0, 0.1 * h, N)], axis=1)
+    phi = rng.normal(0.0, math.radians(0.1), (N, 3))
+    q = geo.quat_mul(np.asarray(geo.quat_yaw(0.7))[None, :], geo.quat_from_axis_angle(phi))
+    q = q / np.linalg.norm(q, axis=-1, keepdims=True)
+    q = np.where(q[:, :1] < 0, -q, q)
+    poses = np.concatenate([t, q], axis=1).astype(np.float32)
+    return dict(name="wide_slab", grid=grid, dims=(n_xy, n_xy, 3), origin=(0.0, 0.0, 0.0), h=h,
+                sigma=sigma, scan=scan, poses=poses, params=step_params(scan, h, sigma, iters=1))
