@@ -258,16 +258,18 @@ def test_whole_rounds_and_tail_all_record_types(ctx, N, dtype, oob):
     check_weights_resample(np.full(N, -math.log(N)), out["loglik"], p["beta"], p["u"], out, abi.RESAMPLE_ESS)
 
 
-@pytest.mark.parametrize("dtype", [abi.GRID_FP32, abi.GRID_FP16])
-def test_grid_slab_beyond_24_bits(ctx, dtype):
+@pytest.mark.parametrize("dtype,oob", [(abi.GRID_FP32, abi.OOB_FLOOR), (abi.GRID_FP16, abi.OOB_FLOOR),
+                                       (abi.GRID_BF16, abi.OOB_SKIP)])
+def test_grid_slab_beyond_24_bits(ctx, dtype, oob):
     # (nx - 1)(ny - 1) >= 2^24 cells per slab: record offsets take full 32-bit
     # products; N = 33,000 runs whole rounds and a split tail, so both the main
     # launch and the tail kernels take that path.
     c = configs.wide_slab()
     nx, ny, _ = c["dims"]
     assert (nx - 1) * (ny - 1) >= 1 << 24
-    p = dict(c["params"], u=0.61, beta=0.01, resample=abi.RESAMPLE_ALWAYS)
-    print("wide slab dtype %d N=%d M=%d" % (dtype, c["poses"].shape[0], c["scan"].shape[0]), flush=True)
+    p = dict(c["params"], u=0.61, beta=0.01, resample=abi.RESAMPLE_ALWAYS, oob=oob)
+    print("wide slab dtype %d oob %d N=%d M=%d" % (dtype, oob, c["poses"].shape[0], c["scan"].shape[0]),
+          flush=True)
     out = one_step(ctx, c, p, dtype=dtype)
     rep = {}
     full_check(c, out, p, dtype=dtype, report=rep)
