@@ -201,3 +201,35 @@ def test_server_rejects_other_dtype(ctx):
     finally:
         abi.mcs_session_destroy(ctx, s["sid"])
         abi.mcs_release_map(ctx, s["mid"])
+
+
+def test_skip_server_sessions_same_alone_and_batched(ctx):
+    # A server whose sessions skip outside points: the batched kernels' skip
+    # variant against each session stepped alone.
+    frames = 2
+    sessions = make_sessions(ctx, [(1000, 8, 64, 211), (257, 12, 64, 212), (3000, 16, 96, 213)],
+                             frames=frames)
+    for s in sessions:
+        for q in s["params"]:
+            q["oob"] = abi.OOB_SKIP
+    try:
+        ref = run_alone(ctx, sessions, frames)
+        for s in sessions:
+            reset(ctx, s)
+        srv = abi.mcs_server_create(ctx, mode=abi.SERVE_BATCHED, dtype=abi.GRID_FP16,
+                                    oob=abi.OOB_SKIP, max_batch=8)
+        try:
+            for f in range(frames):
+                for s in sessions:
+                    abi.mcs_server_submit(srv, s["sid"], s["scans"][f].data_ptr(), s["M"], s["params"][f],
+                                          noise_dev_ptr=s["noise"][f].data_ptr())
+                abi.mcs_server_drain(srv)
+                for k, s in enumerate(sessions):
+                    assert_same(ref[k][f], snapshot(ctx, s), "skip session %d frame %d" % (k, f))
+            assert abi.mcs_server_stats_get(srv)["max_batch_seen"] > 1
+        finally:
+            abi.mcs_server_destroy(srv)
+    finally:
+        for s in sessions:
+            abi.mcs_session_destroy(ctx, s["sid"])
+            abi.mcs_release_map(ctx, s["mid"])
