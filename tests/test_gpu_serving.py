@@ -203,21 +203,22 @@ def test_server_rejects_other_dtype(ctx):
         abi.mcs_release_map(ctx, s["mid"])
 
 
-def test_skip_server_sessions_same_alone_and_batched(ctx):
-    # A server whose sessions skip outside points: the batched kernels' skip
-    # variant against each session stepped alone.
+@pytest.mark.parametrize("dtype,oob", [(abi.GRID_FP16, abi.OOB_SKIP), (abi.GRID_FP32, abi.OOB_FLOOR),
+                                       (abi.GRID_BF16, abi.OOB_FLOOR)])
+def test_batched_record_types_and_skip_same_alone(ctx, dtype, oob):
+    # Servers of the other record types, and one whose sessions skip outside
+    # points: the batched kernels' variants against each session stepped alone.
     frames = 2
     sessions = make_sessions(ctx, [(1000, 8, 64, 211), (257, 12, 64, 212), (3000, 16, 96, 213)],
-                             frames=frames)
+                             dtype=dtype, frames=frames)
     for s in sessions:
         for q in s["params"]:
-            q["oob"] = abi.OOB_SKIP
+            q["oob"] = oob
     try:
         ref = run_alone(ctx, sessions, frames)
         for s in sessions:
             reset(ctx, s)
-        srv = abi.mcs_server_create(ctx, mode=abi.SERVE_BATCHED, dtype=abi.GRID_FP16,
-                                    oob=abi.OOB_SKIP, max_batch=8)
+        srv = abi.mcs_server_create(ctx, mode=abi.SERVE_BATCHED, dtype=dtype, oob=oob, max_batch=8)
         try:
             for f in range(frames):
                 for s in sessions:
@@ -225,7 +226,7 @@ def test_skip_server_sessions_same_alone_and_batched(ctx):
                                           noise_dev_ptr=s["noise"][f].data_ptr())
                 abi.mcs_server_drain(srv)
                 for k, s in enumerate(sessions):
-                    assert_same(ref[k][f], snapshot(ctx, s), "skip session %d frame %d" % (k, f))
+                    assert_same(ref[k][f], snapshot(ctx, s), "dtype %d oob %d session %d frame %d" % (dtype, oob, k, f))
             assert abi.mcs_server_stats_get(srv)["max_batch_seen"] > 1
         finally:
             abi.mcs_server_destroy(srv)
