@@ -551,7 +551,8 @@ def main():
                         "evaluation x %d evaluations per step's evaluation stage; peak = 256 CU x 64 "
                         "lanes x 2.4 GHz (no packed FP32). traffic = HBM bytes per stage from "
                         "FETCH_SIZE/WRITE_SIZE (%s); the algorithmic gather is %d B per evaluation = "
-                        "%.2f GB per stage"
+                        "%.2f GB per stage, served almost entirely from the caches; VALU issue and the "
+                        "cache-resident gather co-limit the stage"
                         % (VALU_OPS_PER_EVAL[args.grid_dtype], evals_per_step,
                            os.path.relpath(PMC_SUMMARY, ROOT), BYTES_PER_EVAL[args.grid_dtype],
                            BYTES_PER_EVAL[args.grid_dtype] * evals_per_step / 1e9)}
