@@ -433,7 +433,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: this implementation has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     prepared = prepare_serving(args) if args.serving_seconds > 0 else None
