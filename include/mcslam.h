@@ -254,6 +254,20 @@ mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t session_id, const float *sc
                                int32_t M, const float *noise_dev, const mcs_step_params *p,
                                void *stream);
 
+/* Measurement aid: the gather floor of the evaluation passes.  Enqueues, like
+ * mcs_filter_step_dev without prediction, weighting or resampling, p->iters
+ * passes over the session's current poses with the same tiling, the same
+ * transformed coordinates (FP64, Sec. III-C.1's u = (R p + t - o)/h - 1/2)
+ * and the same grid-record loads as the likelihood passes, but with the
+ * arithmetic cut to a checksum of the gathered words: its time is what the
+ * record loads alone cost.  The session's l becomes that checksum and g zero;
+ * translations are unchanged and quaternions renormalised.  With per-stage
+ * timing on (mcs_session_profile) the passes count as the evaluation stage.
+ * Single-grid sessions only (MCS_EINVAL otherwise); p is validated as for
+ * mcs_filter_step (only iters and M are used). */
+mcs_status mcs_gather_floor_dev(mcs_ctx *ctx, int32_t session_id, const float *scan_dev,
+                                int32_t M, const mcs_step_params *p, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* GICP likelihood and Gauss-Newton correction (Sec. III-C, Eq. 2-7)          */
 /* ------------------------------------------------------------------------ */
@@ -317,6 +331,36 @@ mcs_status mcs_get_particles(mcs_ctx *ctx, int32_t session_id, float *poses, dou
  * indexed before resampling.  *n_neighbors receives the count (may be NULL). */
 mcs_status mcs_get_neighbors(mcs_ctx *ctx, int32_t session_id, int32_t *out,
                              int32_t *n_neighbors);
+
+/* Sizes of a session: N particles, K keyframes the session has (0 on a
+ * single grid), M_max, and the neighbours per particle of its last keyframe
+ * step (0 before one).  Any output may be NULL.  The outputs of
+ * mcs_get_particles (N*7, N, N*6, N*K*7) and mcs_get_neighbors
+ * (N*last_nb) must be sized from these; K grows with
+ * mcs_session_add_keyframe and last_nb with each keyframe step. */
+mcs_status mcs_session_info(mcs_ctx *ctx, int32_t session_id, int32_t *N, int32_t *K,
+                            int32_t *M_max, int32_t *last_nb);
+
+/* Pass trace, for checking the passes of a step one at a time (Sec. III-C.2,
+ * Eq. 7: each pass evaluates l and g at the pose the previous pass stepped
+ * to).  With max_passes >= 1 every later step of the session records, for
+ * each of its passes (iters gradient passes, then the likelihood-only pass of
+ * post_eval), the pose the pass evaluated, its l and its body-frame g;
+ * max_passes = 0 stops recording and frees the record.  The record is
+ * max_passes * 14 * N * 4 bytes of device memory, counted against the
+ * budget (MCS_EBUDGET).  While it is on, a step with more than max_passes
+ * passes returns MCS_EINVAL.  Likelihood-grid maps only (MCS_EINVAL on a
+ * GICP map); 1 <= max_passes <= 65. */
+mcs_status mcs_session_trace(mcs_ctx *ctx, int32_t session_id, int32_t max_passes);
+
+/* Pass `pass` (0-based) of the last traced step, after waiting for it:
+ * poses N*7 (the pose as the pass held it: pass 0 sees the input pose, or the
+ * predicted one, with its quaternion normalised in FP32; the sign of the
+ * quaternion is left as it is), loglik N and grad N*6, indexed before
+ * resampling.  Any output may be NULL.  MCS_EINVAL without a trace or for a
+ * pass outside [0, max_passes). */
+mcs_status mcs_get_pass_trace(mcs_ctx *ctx, int32_t session_id, int32_t pass, float *poses,
+                              float *loglik, float *grad);
 
 /* Wait for the session's queued work. */
 mcs_status mcs_session_sync(mcs_ctx *ctx, int32_t session_id);

@@ -63,8 +63,8 @@ def lib():
         L.oracle_resample.argtypes = [_dp, i32, f64, _ip, _opt("d")]
         L.oracle_resample.restype = i32
         L.oracle_kf_eval.argtypes = [_fp, i32, i32, i32, i32, _dp, f64, f64, i32, _fp, i32, _fp,
-                                     _fp, i32, i32, f64, _dp, _dp, _opt("d"), _opt("d"),
-                                     _opt("d"), _opt("i"), _opt("i"), i32]
+                                     _fp, i32, i32, f64, _opt("i"), _dp, _dp, _opt("d"), _opt("d"),
+                                     _opt("d"), _opt("i"), _opt("i"), _opt("d"), i32]
         L.oracle_kf_eval.restype = i32
         u64 = C.c_uint64
         L.oracle_splitmix64.argtypes = [u64, i32, np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")]
@@ -74,8 +74,8 @@ def lib():
         L.oracle_prune.argtypes = [_dp, _dp, i32, f64, f64, f64, _ip, _dp, C.POINTER(i32), _opt("d")]
         L.oracle_prune.restype = i32
         L.oracle_gicp_eval.argtypes = [_fp, i32, i32, i32, i32, _dp, f64, _fp, _fp, i32, _fp, _fp, i32,
-                                       i32, f64, _dp, _dp, _dp, _opt("d"), _opt("d"), _opt("i"),
-                                       _opt("i"), _opt("i"), i32]
+                                       i32, f64, _opt("i"), _dp, _dp, _dp, _opt("d"), _opt("d"),
+                                       _opt("i"), _opt("d"), _opt("i"), _opt("i"), i32]
         L.oracle_gicp_eval.restype = i32
         L.oracle_gn_step.argtypes = [_fp, _dp, _dp, i32, f64, f64, _dp, _opt("d")]
         L.oracle_gn_step.restype = i32
@@ -218,11 +218,21 @@ def resample(logw_norm, u):
     return a, m
 
 
+def _force(neighbors, N, n_nb):
+    if neighbors is None:
+        return None
+    nb = np.ascontiguousarray(neighbors, dtype=np.int32).reshape(N, n_nb)
+    return nb
+
+
 def kf_evaluate(grids, dims, origins, h, eps, scan, poses, kf_poses, n_nb=4, oob_skip=False,
-                delta=0.0, nthreads=0):
+                delta=0.0, nthreads=0, neighbors=None):
     """Sum over the n_nb nearest keyframes (Eq. 2) of the grid log-likelihood
     under the relative pose T_k^-1 T (Eq. 4).  grids (K, nz, ny, nx) in each
-    keyframe's frame, origins (K, 3), kf_poses (N, K, 7)."""
+    keyframe's frame, origins (K, 3), kf_poses (N, K, 7).  The neighbours are
+    ranked on FP64 distances; nb_margin (N,) is the ranking's smallest relative
+    gap between consecutive ranks (up to the first keyframe left out).
+    neighbors (N, n_nb), if given, replaces the choice."""
     nx, ny, nz = (int(v) for v in dims)
     g = _f32(grids).reshape(-1)
     K = g.size // (nx * ny * nz)
@@ -232,12 +242,13 @@ def kf_evaluate(grids, dims, origins, h, eps, scan, poses, kf_poses, n_nb=4, oob
     kf = _f32(kf_poses).reshape(N, K, 7)
     ll, gr, ga = np.empty(N), np.empty((N, 6)), np.empty((N, 6))
     al, ag, na = np.empty(N), np.empty((N, 6)), np.empty(N, np.int32)
-    nb = np.empty((N, n_nb), np.int32)
+    nb, mg = np.empty((N, n_nb), np.int32), np.empty(N)
     _check(lib().oracle_kf_eval(g, K, nx, ny, nz, _f64(origins).reshape(-1), float(h), float(eps),
                                 int(bool(oob_skip)), scan, scan.shape[0], poses, kf, N, int(n_nb),
-                                float(delta), ll, gr, ga, al, ag, na, nb, int(nthreads)),
-           "oracle_kf_eval")
-    return dict(loglik=ll, grad=gr, gabs=ga, amb_l=al, amb_g=ag, n_amb=na, neighbors=nb)
+                                float(delta), _force(neighbors, N, n_nb), ll, gr, ga, al, ag, na,
+                                nb, mg, int(nthreads)), "oracle_kf_eval")
+    return dict(loglik=ll, grad=gr, gabs=ga, amb_l=al, amb_g=ag, n_amb=na, neighbors=nb,
+                nb_margin=mg)
 
 
 def splitmix64(seed, n):
@@ -275,7 +286,8 @@ def prune(logw, loglik, tau_post, tau_lik, u):
     return dict(parents=par, logw=lw, n_dead=nd.value, margin=mg)
 
 
-def gicp_evaluate(vox, dims, origins, vs, mu, cov, poses, kf_poses, n_nb=4, delta=0.0, nthreads=0):
+def gicp_evaluate(vox, dims, origins, vs, mu, cov, poses, kf_poses, n_nb=4, delta=0.0, nthreads=0,
+                  neighbors=None):
     """GICP likelihood (Eq. 2-4) over the n_nb nearest keyframes with voxel
     correspondences, and the Gauss-Newton system of Eq. 6: H (N, 21) upper
     triangle row-major, b (N, 6).  vox (K, nz, ny, nx, 12) voxel Gaussians in
@@ -291,12 +303,14 @@ def gicp_evaluate(vox, dims, origins, vs, mu, cov, poses, kf_poses, n_nb=4, delt
     kf = _f32(kf_poses).reshape(N, K, 7)
     ll, H, b = np.empty(N), np.empty((N, 21)), np.empty((N, 6))
     ha, ba = np.empty((N, 21)), np.empty((N, 6))
-    nb = np.empty((N, n_nb), np.int32)
+    nb, mg = np.empty((N, n_nb), np.int32), np.empty(N)
     nc, na = np.empty(N, np.int32), np.empty(N, np.int32)
     _check(lib().oracle_gicp_eval(v, K, nx, ny, nz, _f64(origins).reshape(-1), float(vs), mu, cov,
-                                  mu.shape[0], poses, kf, N, int(n_nb), float(delta), ll, H, b, ha, ba,
-                                  nb, nc, na, int(nthreads)), "oracle_gicp_eval")
-    return dict(loglik=ll, H=H, b=b, habs=ha, babs=ba, neighbors=nb, n_corr=nc, n_amb=na)
+                                  mu.shape[0], poses, kf, N, int(n_nb), float(delta),
+                                  _force(neighbors, N, n_nb), ll, H, b, ha, ba, nb, mg, nc, na,
+                                  int(nthreads)), "oracle_gicp_eval")
+    return dict(loglik=ll, H=H, b=b, habs=ha, babs=ba, neighbors=nb, nb_margin=mg, n_corr=nc,
+                n_amb=na)
 
 
 def gn_step(poses, H, b, rho_max, phi_max):

@@ -785,27 +785,44 @@ int oracle_prune(const double *logw, const double *loglik, int N, double tau_pos
 /* ------------------------------------------------------------------------ */
 
 /* Neighbour keyframes of one particle: the n_nb smallest translation
- * distances |t - t_k| (Sec. III-C.1), ties to the smaller k.  The choice is an
- * integer decision, so it is taken in the kernel's precision: squared
- * distance in FP32 as ((dx*dx + dy*dy) + dz*dz) with dx = t_x - t_k,x, each
- * operation rounded once. */
-static void select_neighbors(const float *t, const float *kf, int K, int n_nb, int *nb)
+ * distances |t - t_k| (Sec. III-C.1), ties to the smaller k, ranked on FP64
+ * squared distances of the FP32 translations.  *margin receives the smallest
+ * relative gap (d_b - d_a) / d_b between consecutive ranks 0 .. n_nb (the
+ * last selected and the first left out included) whose translations differ:
+ * an implementation that ranks in lower precision can only order such a pair
+ * differently when the gap is below its rounding error.  Pairs with bitwise
+ * equal translations tie exactly in any precision and are skipped. */
+static void select_neighbors(const float *t, const float *kf, int K, int n_nb, int *nb,
+                             double *margin)
 {
+    const int n_rank = n_nb < K ? n_nb + 1 : n_nb;
     char *used = (char *)calloc((size_t)K, 1);
-    for (int s = 0; s < n_nb; ++s) {
+    int rank[65];
+    double dist[65];
+    for (int s = 0; s < n_rank; ++s) {
         int best = -1;
-        float bd = INFINITY;
+        double bd = INFINITY;
         for (int k = 0; k < K; ++k) {
             if (used[k]) continue;
-            float dx = t[0] - kf[7 * k], dy = t[1] - kf[7 * k + 1], dz = t[2] - kf[7 * k + 2];
-            float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-            float s2 = xx + yy;
-            float d = s2 + zz;
-            if (d < bd || best < 0) { bd = d; best = k; }
+            double dx = (double)t[0] - (double)kf[7 * k];
+            double dy = (double)t[1] - (double)kf[7 * k + 1];
+            double dz = (double)t[2] - (double)kf[7 * k + 2];
+            double d = dx * dx + dy * dy + dz * dz;
+            if (best < 0 || d < bd) { bd = d; best = k; }
         }
-        nb[s] = best;
+        rank[s] = best;
+        dist[s] = bd;
         if (best >= 0) used[best] = 1;
     }
+    for (int s = 0; s < n_nb; ++s) nb[s] = rank[s];
+    double m = INFINITY;
+    for (int s = 0; s + 1 < n_rank; ++s) {
+        const float *a = kf + 7 * rank[s], *b = kf + 7 * rank[s + 1];
+        if (a[0] == b[0] && a[1] == b[1] && a[2] == b[2]) continue;
+        double gap = dist[s + 1] > 0.0 ? (dist[s + 1] - dist[s]) / dist[s + 1] : 0.0;
+        if (gap < m) m = gap;
+    }
+    *margin = m;
     free(used);
 }
 
@@ -813,14 +830,19 @@ static void select_neighbors(const float *t, const float *kf, int K, int n_nb, i
  * log-likelihood of the scan under the relative pose kT = T_k^-1 T
  * (Eq. 2 and 4): R' = R_k^T R, t' = R_k^T (t - t_k).  The keyframe grids
  * share dims; grid k starts at grids + k*nx*ny*nz, origin at origins + 3k,
- * both in the keyframe's own frame.  kf_poses is (N, K, 7). */
+ * both in the keyframe's own frame.  kf_poses is (N, K, 7).  neighbors
+ * (N, n_nb) receives the neighbours used and nb_margin (N) the ranking's
+ * smallest relative gap (select_neighbors); a non-NULL nb_force (N, n_nb)
+ * evaluates against those keyframes instead of the chosen ones (to check an
+ * implementation's likelihood where its choice is one of several valid ones). */
 int oracle_kf_eval(const float *grids, int K, int nx, int ny, int nz, const double *origins,
                    double h, double eps, int oob_skip, const float *scan, int M,
                    const float *poses, const float *kf_poses, int N, int n_nb, double delta,
-                   double *loglik, double *grad, double *gabs, double *amb_l, double *amb_g,
-                   int *n_amb, int *neighbors, int nthreads)
+                   const int *nb_force, double *loglik, double *grad, double *gabs,
+                   double *amb_l, double *amb_g, int *n_amb, int *neighbors, double *nb_margin,
+                   int nthreads)
 {
-    if (K <= 0 || n_nb <= 0 || n_nb > K || N < 0 || M < 0) return -1;
+    if (K <= 0 || n_nb <= 0 || n_nb > K || n_nb > 64 || N < 0 || M < 0) return -1;
     size_t gsz = (size_t)nx * ny * nz;
     set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -830,9 +852,12 @@ int oracle_kf_eval(const float *grids, int K, int nx, int ny, int nz, const doub
         double q[4] = {pose[3], pose[4], pose[5], pose[6]};
         quat_to_rot(q, R);
         const float *kf = kf_poses + (size_t)7 * K * i;
-        int nb[64];
-        int *nbp = (n_nb <= 64) ? nb : (int *)malloc(sizeof(int) * (size_t)n_nb);
-        select_neighbors(poses + 7 * (size_t)i, kf, K, n_nb, nbp);
+        int nbp[64];
+        double margin;
+        select_neighbors(poses + 7 * (size_t)i, kf, K, n_nb, nbp, &margin);
+        if (nb_margin) nb_margin[i] = margin;
+        if (nb_force)
+            for (int s = 0; s < n_nb; ++s) nbp[s] = nb_force[(size_t)n_nb * i + s];
         eval_out o;
         memset(&o, 0, sizeof o);
         for (int s = 0; s < n_nb; ++s) {
@@ -859,7 +884,6 @@ int oracle_kf_eval(const float *grids, int K, int nx, int ny, int nz, const doub
         if (amb_l) amb_l[i] = o.amb_l;
         if (amb_g) for (int c = 0; c < 6; ++c) amb_g[6 * (size_t)i + c] = o.amb_g[c];
         if (n_amb) n_amb[i] = o.n_amb;
-        if (nbp != nb) free(nbp);
     }
     return 0;
 }
@@ -1087,14 +1111,15 @@ static void gicp_terms(const voxmap_t *m, const double R[9], const double t[3], 
  * system H (21, upper triangle row-major) and b (6) of Eq. 6.  vox holds the
  * K voxel maps back to back (each nx*ny*nz*12 floats), origins (K, 3) in each
  * keyframe's frame; scan means (M, 3) and covariances (M, 6).  n_corr counts
- * the points with a correspondence, n_amb those within delta of a voxel face. */
+ * the points with a correspondence, n_amb those within delta of a voxel face.
+ * nb_force (N, n_nb) or NULL, nb_margin (N) or NULL as for oracle_kf_eval. */
 int oracle_gicp_eval(const float *vox, int K, int nx, int ny, int nz, const double *origins,
                      double vs, const float *mu, const float *cov, int M, const float *poses,
-                     const float *kf_poses, int N, int n_nb, double delta, double *loglik,
-                     double *H, double *b, double *habs, double *babs, int *neighbors, int *n_corr,
-                     int *n_amb, int nthreads)
+                     const float *kf_poses, int N, int n_nb, double delta, const int *nb_force,
+                     double *loglik, double *H, double *b, double *habs, double *babs,
+                     int *neighbors, double *nb_margin, int *n_corr, int *n_amb, int nthreads)
 {
-    if (K <= 0 || n_nb <= 0 || n_nb > K || N < 0 || M < 0) return -1;
+    if (K <= 0 || n_nb <= 0 || n_nb > K || n_nb > 64 || N < 0 || M < 0) return -1;
     const size_t vsz = (size_t)nx * ny * nz * 12;
     set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -1104,9 +1129,12 @@ int oracle_gicp_eval(const float *vox, int K, int nx, int ny, int nz, const doub
         double qq[4] = {pose[3], pose[4], pose[5], pose[6]};
         quat_to_rot(qq, R);
         const float *kf = kf_poses + (size_t)7 * K * i;
-        int nb[64];
-        int *nbp = (n_nb <= 64) ? nb : (int *)malloc(sizeof(int) * (size_t)n_nb);
-        select_neighbors(poses + 7 * (size_t)i, kf, K, n_nb, nbp);
+        int nbp[64];
+        double margin;
+        select_neighbors(poses + 7 * (size_t)i, kf, K, n_nb, nbp, &margin);
+        if (nb_margin) nb_margin[i] = margin;
+        if (nb_force)
+            for (int s = 0; s < n_nb; ++s) nbp[s] = nb_force[(size_t)n_nb * i + s];
         gicp_out o;
         memset(&o, 0, sizeof o);
         for (int s = 0; s < n_nb; ++s) {
@@ -1138,7 +1166,6 @@ int oracle_gicp_eval(const float *vox, int K, int nx, int ny, int nz, const doub
         if (babs) for (int c = 0; c < 6; ++c) babs[6 * (size_t)i + c] = o.babs[c];
         if (n_corr) n_corr[i] = o.n_corr;
         if (n_amb) n_amb[i] = o.n_amb;
-        if (nbp != nb) free(nbp);
     }
     return 0;
 }

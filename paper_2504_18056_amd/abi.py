@@ -125,6 +125,10 @@ def lib():
             "mcs_filter_step_gicp": (i32, [vp, i32, vp, vp, i32, vp, P(StepParams)]),
             "mcs_filter_step_gicp_dev": (i32, [vp, i32, vp, vp, i32, vp, P(StepParams), vp]),
             "mcs_get_gicp_system": (i32, [vp, i32, vp, vp]),
+            "mcs_session_info": (i32, [vp, i32, P(i32), P(i32), P(i32), P(i32)]),
+            "mcs_gather_floor_dev": (i32, [vp, i32, vp, i32, P(StepParams), vp]),
+            "mcs_session_trace": (i32, [vp, i32, i32]),
+            "mcs_get_pass_trace": (i32, [vp, i32, i32, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -347,8 +351,34 @@ def mcs_filter_step_dev(ctx, sid, scan_dev_ptr, M, params, noise_dev_ptr=None, s
                                      C.byref(p), None if stream is None else C.c_void_p(int(stream))))
 
 
-def mcs_get_particles(ctx, sid, N, K=0, poses=True, logw=True, parents=True, loglik=True,
+def mcs_gather_floor_dev(ctx, sid, scan_dev_ptr, M, params, stream=None):
+    """Gather-floor passes over the session's poses (measurement aid)."""
+    p = params if isinstance(params, StepParams) else step_params(params)
+    _check(lib().mcs_gather_floor_dev(ctx, int(sid), C.c_void_p(int(scan_dev_ptr)), int(M), C.byref(p),
+                                      None if stream is None else C.c_void_p(int(stream))))
+
+
+def mcs_session_info(ctx, sid):
+    """Sizes of a session: dict(N, K, M_max, last_nb)."""
+    v = [C.c_int32() for _ in range(4)]
+    _check(lib().mcs_session_info(ctx, int(sid), *[C.byref(x) for x in v]))
+    return dict(N=v[0].value, K=v[1].value, M_max=v[2].value, last_nb=v[3].value)
+
+
+def _sizes(ctx, sid, N, K=None):
+    """Output sizes from the session itself; N and K given by the caller must match."""
+    info = mcs_session_info(ctx, sid)
+    if N is not None and int(N) != info["N"]:
+        raise McsError(MCS_EINVAL, "session %d has N=%d, asked for %d" % (sid, info["N"], N))
+    if K is not None and int(K) != info["K"]:
+        raise McsError(MCS_EINVAL, "session %d has K=%d, asked for %d" % (sid, info["K"], K))
+    return info
+
+
+def mcs_get_particles(ctx, sid, N=None, K=None, poses=True, logw=True, parents=True, loglik=True,
                       grad=True, kf_poses=False, stats=True):
+    info = _sizes(ctx, sid, N, K)
+    N, K = info["N"], info["K"]
     out = {}
     P = np.empty((N, 7), np.float32) if poses else None
     W = np.empty(N, np.float64) if logw else None
@@ -365,6 +395,20 @@ def mcs_get_particles(ctx, sid, N, K=0, poses=True, logw=True, parents=True, log
                             best_pose=np.array(st.best_pose[:], np.float32),
                             degenerate=bool(st.degenerate), pruned=int(st.pruned))
     return out
+
+
+def mcs_session_trace(ctx, sid, max_passes):
+    _check(lib().mcs_session_trace(ctx, int(sid), int(max_passes)))
+
+
+def mcs_get_pass_trace(ctx, sid, pass_):
+    """Pass `pass_` of the last traced step: dict(poses (N, 7), loglik (N,), grad (N, 6))."""
+    N = mcs_session_info(ctx, sid)["N"]
+    P = np.empty((N, 7), np.float32)
+    Lk = np.empty(N, np.float32)
+    G = np.empty((N, 6), np.float32)
+    _check(lib().mcs_get_pass_trace(ctx, int(sid), int(pass_), _ptr(P), _ptr(Lk), _ptr(G)))
+    return dict(poses=P, loglik=Lk, grad=G)
 
 
 def mcs_session_sync(ctx, sid):
@@ -387,12 +431,15 @@ def mcs_session_profile_read(ctx, sid):
     return {f: getattr(p, f) for f, _ in Profile._fields_}
 
 
-def mcs_get_neighbors(ctx, sid, N, n_nb):
-    out = np.empty((N, n_nb), np.int32)
+def mcs_get_neighbors(ctx, sid, N=None, n_nb=None):
+    info = _sizes(ctx, sid, N)
+    if n_nb is not None and int(n_nb) != info["last_nb"]:
+        raise McsError(MCS_EINVAL, "session used %d neighbours, asked for %d" % (info["last_nb"], n_nb))
+    out = np.empty((info["N"], info["last_nb"]), np.int32)
     k = C.c_int32()
     _check(lib().mcs_get_neighbors(ctx, int(sid), _ptr(out), C.byref(k)))
-    if k.value != n_nb:
-        raise McsError(MCS_EINVAL, "session used %d neighbours, asked for %d" % (k.value, n_nb))
+    if k.value != info["last_nb"]:
+        raise McsError(MCS_EINVAL, "neighbour count changed from %d to %d" % (info["last_nb"], k.value))
     return out
 
 

@@ -84,7 +84,16 @@ struct StepDesc {
     double *tail_l;
     float *tail_g;
     int32_t tail_tiles;      // tiles the session's tail buffers hold (0: no split)
+    // Pass trace (null: off): per pass, [pass][kTraceRows][N] with the pose the
+    // pass evaluates (7 rows), its l (1) and its body-frame gradient (6).
+    float *trace;
+    // Gather-floor measurement (1): the evaluation passes keep the transform
+    // and the record loads and replace the arithmetic by a checksum of the
+    // gathered words (l = checksum, g = 0, so the poses stay put).
+    int32_t floor_only;
 };
+
+constexpr int kTraceRows = 14;
 
 constexpr int kWeightBlock = 256;
 constexpr int kPartPerBlock = 6;   // doubles of per-block partials

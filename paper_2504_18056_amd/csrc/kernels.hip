@@ -546,6 +546,25 @@ __device__ __forceinline__ void accumulate4(const GridK &g, const Pt *p, const f
     add_grad(pf[3], x[3], y[3], z[3], d[2] * r23, acc);
 }
 
+// Gather floor: the words of a record folded into one (keeps the loads live
+// with the least arithmetic).
+template <int DT> __device__ __forceinline__ uint32_t cell_xor(const Cell<DT> &c);
+template <> __device__ __forceinline__ uint32_t cell_xor<0>(const Cell<0> &c)
+{
+    return (__float_as_uint(c.a.x) ^ __float_as_uint(c.a.y) ^ __float_as_uint(c.a.z) ^
+            __float_as_uint(c.a.w)) ^
+           (__float_as_uint(c.b.x) ^ __float_as_uint(c.b.y) ^ __float_as_uint(c.b.z) ^
+            __float_as_uint(c.b.w));
+}
+template <> __device__ __forceinline__ uint32_t cell_xor<1>(const Cell<1> &c)
+{
+    return c.a.x ^ c.a.y ^ c.a.z ^ c.a.w;
+}
+template <> __device__ __forceinline__ uint32_t cell_xor<2>(const Cell<2> &c)
+{
+    return c.a.x ^ c.a.y ^ c.a.z ^ c.a.w;
+}
+
 // Record of a prepared point: from the buffer (an outside point's offset lies
 // beyond its range and reads zeros) or, with GLB, through a 64-bit address
 // (an outside point reads the zero record).
@@ -564,12 +583,13 @@ __device__ __forceinline__ void fetch(const GridK &g, const Pt &p, Cell<DT> &c)
 // barrier keeps them ahead of the next point's transform), before any of the
 // four points' arithmetic.  The range's sums are stored in acc (l, sum d and
 // B = sum v' x d, v' = A p).
-template <int DT, bool BIG, bool SKIP, bool KF = false, bool GLB = false>
+template <int DT, bool BIG, bool SKIP, bool KF = false, bool GLB = false, bool FLOOR = false>
 __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, scan32_ptr scanf,
                                              int j0, int j1, const GridMap64 &gm, Acc &acc)
 {
 #pragma clang fp contract(off)
     PtAcc pa = {0.0, 0.0f, 0.0f, 0.0f, {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f}};
+    uint32_t fl = 0;                      // FLOOR: checksum of the gathered words
     int j = j0;
     constexpr int U = 4;
     for (; j + U <= j1; j += U) {
@@ -588,17 +608,30 @@ __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, sc
             __builtin_amdgcn_sched_barrier(0);
         }
         __builtin_amdgcn_s_setprio(0);
+        if constexpr (FLOOR) {
 #pragma unroll
-        for (int k = 0; k < U; ++k) pf[k] = scanf[j + k];
-        accumulate4<DT, SKIP>(g, p, pf, c, pa);
+            for (int k = 0; k < U; ++k) fl ^= cell_xor<DT>(c[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < U; ++k) pf[k] = scanf[j + k];
+            accumulate4<DT, SKIP>(g, p, pf, c, pa);
+        }
     }
     for (; j < j1; ++j) {
         const d4v s = scan[j];
-        const f4v pf = scanf[j];
         const Pt p = prep_point64<DT, BIG, KF>(g, gm, s.x, s.y, s.z);
         Cell<DT> c;
         fetch<DT, GLB>(g, p, c);
-        accumulate1<DT, SKIP>(g, p, pf, c, pa);
+        if constexpr (FLOOR) {
+            fl ^= cell_xor<DT>(c);
+        } else {
+            const f4v pf = scanf[j];
+            accumulate1<DT, SKIP>(g, p, pf, c, pa);
+        }
+    }
+    if constexpr (FLOOR) {
+        acc = {(double)fl, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        return;
     }
     // B_a = e_abc A_be S_ce, in FP64 from the FP32 sums.
     const double *A = gm.A;
@@ -638,16 +671,14 @@ __device__ __forceinline__ void body_gradient(const float q[4], const float s[6]
     gr[5] = R[2] * s[3] + R[5] * s[4] + R[8] * s[5];
 }
 
-// Load the tile's poses into LDS (normalised quaternions).
+// Load the tile's poses into LDS as stored: the first pass evaluates the
+// pose itself (its quaternion normalised in FP64 by the grid map); the FP32
+// normalisation happens before the first step.
 __device__ __forceinline__ void load_tile_pose(const StepDesc &d, int i, int lane, float (*s_pose)[64])
 {
-#pragma clang fp contract(off)
     const int N = d.N;
     const int ic = i < N ? i : N - 1;
-    float q[4] = {d.pose[3 * N + ic], d.pose[4 * N + ic], d.pose[5 * N + ic], d.pose[6 * N + ic]};
-    normalize_quat(q[0], q[1], q[2], q[3]);
-    s_pose[0][lane] = d.pose[ic]; s_pose[1][lane] = d.pose[N + ic]; s_pose[2][lane] = d.pose[2 * N + ic];
-    s_pose[3][lane] = q[0]; s_pose[4][lane] = q[1]; s_pose[5][lane] = q[2]; s_pose[6][lane] = q[3];
+    for (int c = 0; c < 7; ++c) s_pose[c][lane] = d.pose[c * N + ic];
 }
 
 // Reduce the W partial sums (fixed order), store l and g, take the step.
@@ -681,7 +712,17 @@ __device__ __forceinline__ void tile_epilogue(const StepDesc &d, int i, int lane
         d.loglik[i] = (float)(l * kLn2);
         if (stepping)
             for (int c = 0; c < 6; ++c) d.grad[c * N + i] = gr[c];
+        if (d.trace) {
+            float *tr = d.trace + (size_t)pass * kTraceRows * N + i;
+            for (int c = 0; c < 3; ++c) tr[(size_t)c * N] = t[c];
+            for (int c = 0; c < 4; ++c) tr[(size_t)(3 + c) * N] = q[c];
+            tr[(size_t)7 * N] = (float)(l * kLn2);
+            for (int c = 0; c < 6; ++c) tr[(size_t)(8 + c) * N] = gr[c];
+        }
     }
+    // The stored pose may carry any nonzero quaternion; the step composes
+    // with its normalisation (later passes hold the step's own unit result).
+    if (stepping && pass == 0) normalize_quat(q[0], q[1], q[2], q[3]);
     if (stepping && s_upd) {
         if (s_loop[lane] >= 0) {
             float rho[3], phi[3];
@@ -714,7 +755,7 @@ __device__ __forceinline__ void store_tile_pose(const StepDesc &d, int i, int la
     }
 }
 
-template <int DT, bool BIG, bool SKIP, int W>
+template <int DT, bool BIG, bool SKIP, int W, bool FLOOR = false>
 __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
 {
 #pragma clang fp contract(off)
@@ -752,8 +793,8 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
             for (int sc = 0; sc < S; ++sc) {
                 const int c = wave * S + sc;
                 Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                eval_range64<DT, BIG, SKIP>(g, (scan64_ptr)d.scan8, (scan32_ptr)d.scan4, min(M, c * Q), min(M, (c + 1) * Q),
-                                            gm, part);
+                eval_range64<DT, BIG, SKIP, false, false, FLOOR>(g, (scan64_ptr)d.scan8, (scan32_ptr)d.scan4,
+                                                                 min(M, c * Q), min(M, (c + 1) * Q), gm, part);
                 add_acc(acc, part);
             }
         }
@@ -773,20 +814,19 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
 // ---------------------------------------------------------------------------
 
 // Pose of particle i as the tile holds it before pass `pass`: the input pose
-// with its quaternion normalised (pass 0, as load_tile_pose) or the pose the
-// previous pass's step stored.
+// as stored (pass 0, as load_tile_pose) or the pose the previous pass's step
+// stored.
 __device__ __forceinline__ void tail_pose(const StepDesc &d, int i, int pass, float t[3], float q[4])
 {
-#pragma clang fp contract(off)
+    (void)pass;
     const int N = d.N;
     const int ic = i < N ? i : N - 1;
     t[0] = d.pose[ic]; t[1] = d.pose[N + ic]; t[2] = d.pose[2 * N + ic];
     q[0] = d.pose[3 * N + ic]; q[1] = d.pose[4 * N + ic]; q[2] = d.pose[5 * N + ic]; q[3] = d.pose[6 * N + ic];
-    if (pass == 0) normalize_quat(q[0], q[1], q[2], q[3]);
 }
 
 // One sub-chunk of one tail tile per wave: the same sub-chunk sums eval_tile forms.
-template <int DT, bool BIG, bool SKIP>
+template <int DT, bool BIG, bool SKIP, bool FLOOR = false>
 __device__ __forceinline__ void tail_chunk(const StepDesc &d, int tile0, int pass, int rel, int c)
 {
 #pragma clang fp contract(off)
@@ -807,7 +847,8 @@ __device__ __forceinline__ void tail_chunk(const StepDesc &d, int tile0, int pas
     GridMap64 gm;
     grid_map64(t, q, d.ox, d.oy, d.oz, d.h, gm);
     Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    eval_range64<DT, BIG, SKIP>(g, (scan64_ptr)d.scan8, (scan32_ptr)d.scan4, min(M, c * Q), min(M, (c + 1) * Q), gm, part);
+    eval_range64<DT, BIG, SKIP, false, false, FLOOR>(g, (scan64_ptr)d.scan8, (scan32_ptr)d.scan4,
+                                                     min(M, c * Q), min(M, (c + 1) * Q), gm, part);
     const size_t r = (size_t)rel * kSubChunks + c;
     d.tail_l[r * 64 + lane] = part.l;
     float *tg = d.tail_g + r * 6 * 64 + lane;
@@ -1235,6 +1276,7 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
                 }
                 float t3[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
                 float q4[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
+                if (pass == 0) normalize_quat(q4[0], q4[1], q4[2], q4[3]);   // the stored quaternion
                 for (int c = 0; c < 3; ++c) {
                     s_upd[c][lane] = rho[c];
                     s_upd[3 + c][lane] = phi[c];
@@ -2069,21 +2111,21 @@ __global__ __launch_bounds__(kWeightBlock) void k_pack_predict(StepDesc d)
         predict_blk(d, blockIdx.x - ns);
 }
 
-template <int DT, bool BIG, bool SKIP, int W>
+template <int DT, bool BIG, bool SKIP, int W, bool FLOOR = false>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_eval(StepDesc d)
 {
-    eval_tile<DT, BIG, SKIP, W>(d, blockIdx.x);
+    eval_tile<DT, BIG, SKIP, W, FLOOR>(d, blockIdx.x);
 }
 
 // Eight waves per block, one sub-chunk each: block b covers tail tile
 // b / (kSubChunks / 8) and its sub-chunks (b % (kSubChunks / 8)) * 8 + wave.
-template <int DT, bool BIG, bool SKIP>
+template <int DT, bool BIG, bool SKIP, bool FLOOR = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_tail(StepDesc d, int tile0,
                                                                                           int pass)
 {
     constexpr int G = kSubChunks / 8;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    tail_chunk<DT, BIG, SKIP>(d, tile0, pass, blockIdx.x / G, (blockIdx.x % G) * 8 + wave);
+    tail_chunk<DT, BIG, SKIP, FLOOR>(d, tile0, pass, blockIdx.x / G, (blockIdx.x % G) * 8 + wave);
 }
 
 template <int W>
@@ -2281,7 +2323,7 @@ bool eval_supported(const StepDesc &d)
     return grid_supported(d.nx, d.ny, d.nz, d.dtype, false);
 }
 
-template <int DT, bool SKIP>
+template <int DT, bool SKIP, bool FLOOR = false>
 static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st, const TailAux *aux)
 {
     const unsigned blocks = (unsigned)particle_tiles(d.N);
@@ -2344,19 +2386,21 @@ static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st, const TailAu
         for (int pass = 0; tail > 0 && pass < d.iters + d.post_eval; ++pass) {
             const dim3 gb((unsigned)tail * (kSubChunks / 8));
             if (big_slab(d))
-                hipLaunchKernelGGL((k_eval_tail<DT, true, SKIP>), gb, dim3(512), 0, ts, d, (int)main_tiles, pass);
+                hipLaunchKernelGGL((k_eval_tail<DT, true, SKIP, FLOOR>), gb, dim3(512), 0, ts, d, (int)main_tiles,
+                                   pass);
             else
-                hipLaunchKernelGGL((k_eval_tail<DT, false, SKIP>), gb, dim3(512), 0, ts, d, (int)main_tiles, pass);
+                hipLaunchKernelGGL((k_eval_tail<DT, false, SKIP, FLOOR>), gb, dim3(512), 0, ts, d, (int)main_tiles,
+                                   pass);
             hipLaunchKernelGGL((k_eval_tail_step<kEvalW>), dim3((unsigned)tail), dim3(64), 0, ts, d,
                                (int)main_tiles, pass);
         }
         if (main_tiles > 0) {
             if (big_slab(d))
-                hipLaunchKernelGGL((k_eval<DT, true, SKIP, kEvalW>), dim3(main_tiles), dim3(64 * kEvalW), 0,
-                                   st, d);
+                hipLaunchKernelGGL((k_eval<DT, true, SKIP, kEvalW, FLOOR>), dim3(main_tiles), dim3(64 * kEvalW),
+                                   0, st, d);
             else
-                hipLaunchKernelGGL((k_eval<DT, false, SKIP, kEvalW>), dim3(main_tiles), dim3(64 * kEvalW), 0,
-                                   st, d);
+                hipLaunchKernelGGL((k_eval<DT, false, SKIP, kEvalW, FLOOR>), dim3(main_tiles), dim3(64 * kEvalW),
+                                   0, st, d);
         }
         if (fork) {
             hipError_t e = hipGetLastError();
@@ -2377,6 +2421,15 @@ hipError_t launch_eval(const StepDesc &d, hipStream_t st, const TailAux *aux)
         return hipGetLastError();
     }
     const bool skip = d.oob_skip != 0;
+    if (d.floor_only) {
+        if (d.K > 0) return hipErrorInvalidValue;
+        switch (d.dtype) {
+        case 0: return launch_eval_dt<0, false, true>(d, st, aux);
+        case 1: return launch_eval_dt<1, false, true>(d, st, aux);
+        case 2: return launch_eval_dt<2, false, true>(d, st, aux);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (d.dtype) {
     case 0: return skip ? launch_eval_dt<0, true>(d, st, aux) : launch_eval_dt<0, false>(d, st, aux);
     case 1: return skip ? launch_eval_dt<1, true>(d, st, aux) : launch_eval_dt<1, false>(d, st, aux);

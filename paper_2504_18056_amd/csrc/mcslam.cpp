@@ -292,6 +292,9 @@ mcs_status validate_params(const Session *s, const mcs_step_params *p, int M)
         return fail(MCS_EINVAL, "MCS_KF_LOOP needs a keyframe map");
     if (p->kf_update == MCS_KF_LOOP && p->n_recent < 0)
         return fail(MCS_EINVAL, "n_recent=%d must be >= 0", p->n_recent);
+    if (s->trace && p->iters + (p->post_eval ? 1 : 0) > s->trace_passes)
+        return fail(MCS_EINVAL, "%d passes exceed the trace's %d", p->iters + (p->post_eval ? 1 : 0),
+                    s->trace_passes);
     return MCS_OK;
 }
 
@@ -350,6 +353,7 @@ StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float 
     d.ess_frac = p->ess_frac;
     d.u = p->u;
     for (int c = 0; c < 7; ++c) d.dT[c] = p->delta_T[c];
+    d.trace = s->trace;
     return d;
 }
 
@@ -878,9 +882,10 @@ mcs_status mcs_session_destroy(mcs_ctx *ctx, int32_t sid)
         (void)hipEventDestroy(s->tail_join);
     }
     if (s->pinned) (void)hipHostFree(s->pinned);
+    if (s->trace) (void)hipFree(s->trace);
     prof_release(s);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->in_use -= s->bytes;
+    ctx->in_use -= s->bytes + s->trace_bytes;
     s->map->users--;
     delete s;
     return MCS_OK;
@@ -1006,6 +1011,45 @@ mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev,
                                const float *noise_dev, const mcs_step_params *p, void *stream)
 {
     return filter_step_dev(ctx, sid, scan_dev, nullptr, M, noise_dev, p, stream);
+}
+
+mcs_status mcs_gather_floor_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev, int32_t M,
+                                const mcs_step_params *p, void *stream)
+{
+    if (!ctx || !scan_dev) return fail(MCS_EINVAL, "NULL argument");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    if (s->map->kind != kGridMap || s->K_cap > 0)
+        return fail(MCS_EINVAL, "the gather floor runs on single-grid sessions only");
+    mcs_status st = validate_params(s, p, M);
+    if (st != MCS_OK) return st;
+    if ((st = set_device(ctx)) != MCS_OK) return st;
+    hipStream_t hs = stream ? (hipStream_t)stream : s->stream;
+    StepDesc d = make_desc(s, scan_dev, M, nullptr, p);
+    d.predict = 0;
+    d.noise = nullptr;
+    d.post_eval = 0;
+    d.oob_skip = 0;
+    d.trace = nullptr;
+    d.floor_only = 1;
+    if (!eval_supported(d)) return fail(MCS_EINVAL, "map not supported");
+    std::array<hipEvent_t, 5> *ev = nullptr;
+    if ((st = prof_begin(s, ev)) != MCS_OK) return st;
+    if (ev) s->prof_evals += (int64_t)s->N * M * p->iters;
+#define FLOOR_MARK(k)                                                        \
+    do {                                                                     \
+        if (ev) HIP_TRY(hipEventRecord((*ev)[k], hs), "hipEventRecord");     \
+    } while (0)
+    FLOOR_MARK(0);
+    HIP_TRY(launch_pack_predict(d, hs), "pack");
+    FLOOR_MARK(1);
+    const TailAux aux{s->tail_stream, s->tail_fork, s->tail_join};
+    HIP_TRY(launch_eval(d, hs, s->tail_stream ? &aux : nullptr), "gather floor");
+    FLOOR_MARK(2);
+    FLOOR_MARK(3);
+    FLOOR_MARK(4);
+#undef FLOOR_MARK
+    return MCS_OK;
 }
 
 mcs_status mcs_filter_step_gicp(mcs_ctx *ctx, int32_t sid, const float *mu, const float *cov,
@@ -1143,6 +1187,86 @@ mcs_status mcs_get_particles(mcs_ctx *ctx, int32_t sid, float *poses, double *lo
             for (int c = 3; c < 7; ++c) stats->best_pose[c] = -stats->best_pose[c];
         stats->degenerate = d.degenerate;
         stats->pruned = d.pruned;
+    }
+    return MCS_OK;
+}
+
+mcs_status mcs_session_info(mcs_ctx *ctx, int32_t sid, int32_t *N, int32_t *K, int32_t *M_max,
+                            int32_t *last_nb)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    if (N) *N = s->N;
+    if (K) *K = s->K;
+    if (M_max) *M_max = s->M_max;
+    if (last_nb) *last_nb = s->last_nb;
+    return MCS_OK;
+}
+
+mcs_status mcs_session_trace(mcs_ctx *ctx, int32_t sid, int32_t max_passes)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    if (max_passes < 0 || max_passes > 65) return fail(MCS_EINVAL, "max_passes=%d outside [0, 65]", max_passes);
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    if (max_passes > 0 && s->map->kind != kGridMap)
+        return fail(MCS_EINVAL, "pass traces are for likelihood-grid maps only");
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s->stream), "sync");
+    if (s->tail_stream) HIP_TRY(hipStreamSynchronize(s->tail_stream), "sync");
+    if (s->trace) {
+        (void)hipFree(s->trace);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->in_use -= s->trace_bytes;
+        s->trace = nullptr;
+        s->trace_bytes = 0;
+        s->trace_passes = 0;
+    }
+    if (max_passes == 0) return MCS_OK;
+    const size_t bytes = (size_t)max_passes * kTraceRows * s->N * sizeof(float);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!budget_allows(ctx, bytes)) return fail(MCS_EBUDGET, "trace needs %zu bytes", bytes);
+        ctx->in_use += bytes;
+    }
+    hipError_t e = hipMalloc((void **)&s->trace, bytes);
+    if (e == hipSuccess) e = hipMemset(s->trace, 0, bytes);
+    if (e != hipSuccess) {
+        if (s->trace) (void)hipFree(s->trace);
+        s->trace = nullptr;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->in_use -= bytes;
+        return hip_fail(e, "hipMalloc(trace)");
+    }
+    s->trace_bytes = bytes;
+    s->trace_passes = max_passes;
+    return MCS_OK;
+}
+
+mcs_status mcs_get_pass_trace(mcs_ctx *ctx, int32_t sid, int32_t pass, float *poses,
+                              float *loglik, float *grad)
+{
+    if (!ctx) return fail(MCS_EINVAL, "NULL context");
+    Session *s = find_session(ctx, sid);
+    if (!s) return fail(MCS_ENOTFOUND, "no session %d", sid);
+    if (!s->trace) return fail(MCS_EINVAL, "session %d has no pass trace", sid);
+    if (pass < 0 || pass >= s->trace_passes)
+        return fail(MCS_EINVAL, "pass=%d outside [0, %d)", pass, s->trace_passes);
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    const size_t N = s->N;
+    std::vector<float> soa(kTraceRows * N);
+    HIP_TRY(hipMemcpy(soa.data(), s->trace + (size_t)pass * kTraceRows * N, soa.size() * 4,
+                      hipMemcpyDeviceToHost), "trace");
+    for (size_t i = 0; i < N; ++i) {
+        if (poses)
+            for (int c = 0; c < 7; ++c) poses[7 * i + c] = soa[c * N + i];
+        if (loglik) loglik[i] = soa[7 * N + i];
+        if (grad)
+            for (int c = 0; c < 6; ++c) grad[6 * i + c] = soa[(8 + c) * N + i];
     }
     return MCS_OK;
 }

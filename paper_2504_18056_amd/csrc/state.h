@@ -72,6 +72,9 @@ struct Session {
     float *pinned = nullptr;         // host staging for host-pointer steps
     size_t pinned_floats = 0;
     int last_nb = 0;                 // neighbours per particle in the last keyframe step
+    float *trace = nullptr;          // pass trace [trace_passes][kTraceRows][N] (null: off)
+    int trace_passes = 0;
+    size_t trace_bytes = 0;
     hipEvent_t staged = nullptr;     // last upload from `pinned` done
     bool staged_pending = false;
     // Stage timing: 5 events per profiled step (start, after predict, after

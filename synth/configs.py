@@ -41,6 +41,14 @@ GRID_FP32, GRID_FP16, GRID_BF16 = 0, 1, 2
 # Scans, particles and step parameters
 # ---------------------------------------------------------------------------
 
+def f32(x):
+    """x rounded to the nearest FP32 value.  Grid geometry (voxel edge,
+    origins) crosses the C ABI as FP32, so the inputs use values that FP32
+    holds exactly: both the library and the FP64 oracle then see the same
+    numbers."""
+    return float(np.float32(x))
+
+
 def lidar_scan(scene, t, q, elevations_deg, n_az, rmax, noise_sigma, rng, el_range=None):
     """Ray-cast a ring-by-azimuth scan from pose (t, q); returns (M, 3) FP32, sensor frame.
 
@@ -137,6 +145,7 @@ def box_room_scene(rng, n_boxes=20, size=25.6, floor_z=1.0):
 def box_room(N=1024, seed=1001, grid_n=128, h=0.2, sigma=0.1, n_rings=8, n_az=64,
              grid_dtype=GRID_FP32):
     """The single-step box-room workload (N particles, n_rings x n_az point scan)."""
+    h = f32(h)
     rng = np.random.default_rng(seed)
     size = grid_n * h
     scene = box_room_scene(rng, size=size)
@@ -288,6 +297,7 @@ def relative_motion(t0, q0, t1, q1):
 def corridors(N=100000, M_rings=32, n_az=64, n_frames=200, seed=1002, grid=(512, 512, 128),
               h=0.2, sigma=0.1, iters=3, ess_frac=0.5, with_noise=True, grid_dtype=GRID_FP32):
     """The paper-scale corridor workload; per-frame scans, odometry and noise."""
+    h = f32(h)
     rng = np.random.default_rng(seed)
     size_xy, size_z = grid[0] * h, grid[2] * h
     scene = corridor_scene(rng, size_xy=size_xy, size_z=size_z)
@@ -383,6 +393,7 @@ def keyframes(N=50000, K=64, kf_points=16384, M_rings=32, n_az=64, grid_n=128, h
     Gaussians of edge vox_edge centred on the keyframe (synth.gicp), and the
     current scan gets per-point covariances (10 nearest neighbours).
     """
+    h, vox_edge = f32(h), f32(vox_edge)     # the origins below are then FP32 values too
     rng = np.random.default_rng(seed)
     if ambiguous:
         scene = repeated_rooms_scene(rng)
@@ -520,7 +531,7 @@ def serving_sessions(n_sessions=64, seed=1005, n_scans=8, n_lo=1000, n_hi=200000
 def serving_session_inputs(desc):
     """Map, scans, particles and step parameters of one serving session."""
     nx, ny, nz = desc["dims"]
-    h, sigma = desc["h"], desc["sigma"]
+    h, sigma = f32(desc["h"]), desc["sigma"]
     rng = np.random.default_rng(desc["seed"])
     cell = 5.0
     cx, cy = max(2, int(nx * h // cell) - 1), max(2, int(ny * h // cell) - 1)
@@ -569,6 +580,7 @@ def repeated_floors(N=20000, floors=4, true_floor=2, n_frames=80, M_rings=8, n_a
     drawn uniformly, the rest is the true start pose with 0.3 m / 3 deg of
     spread.  Until the box comes into view every storey explains the scans
     equally well.  The range sensor reaches rmax metres."""
+    h = f32(h)
     rng = np.random.default_rng(seed)
     size_xy, size_z = grid[0] * h, grid[2] * h
     cells = int(size_xy // 5.0) - 1
@@ -630,6 +642,7 @@ def wide_slab(N=33000, M=300, seed=1007, n_xy=4098, h=0.05, sigma=0.1):
     4097^2 cells per slab), three samples thick, with a smooth field in [0.1,
     0.9]; particles near the far corner (cell indices near 3,800-3,900), level
     within 0.1 deg, at mid-slab height; a planar scan of radius <= 5 m."""
+    h = f32(h)
     rng = np.random.default_rng(seed)
     i = np.arange(n_xy, dtype=np.float64)
     fx = np.sin(0.07 * i + 0.3)

@@ -4,14 +4,21 @@ Tolerances (stated per result):
 * log-likelihood: |l_gpu - l_ref| <= 1e-5 |l_ref| + amb_l
 * gradient:       |g_gpu,c - g_ref,c| <= 1e-4 sum_j |dl_j/dxi_c| + amb_g,c
   where amb_* is the oracle's allowance for points whose index coordinate is
-  within DELTA of a cell face: FP32 rounding of u in the kernel may put them
-  in the neighbouring cell, where the interpolant's one-sided derivative
-  differs.  Their count is reported.
+  within DELTA of a cell face, where the two sides' cell choices could differ
+  and the interpolant's one-sided derivative with it.  The kernel forms u in
+  FP64 from the same FP32 inputs, so the two agree on u to about 1e-12 index
+  units and DELTA = 1e-9 covers that; such points are counted (none is
+  expected) and the reported errors are taken over every particle.
 * pose step (oracle fed the GPU's own gradient): translation within 4 FP32
   ulps of |t| plus 1e-7 m, rotation within 2e-6 rad.
 * log-sum-exp: relative 1e-13; ESS: relative 1e-10.
 * resampled indices: bit-exact except where the oracle's CDF is within 1e-12
   of u_k (counted).
+* neighbour keyframes: bit-exact except for particles whose FP64 ranking has
+  two consecutive squared distances (of distinct translations) within a
+  relative NB_TIE of each other (counted); there the kernel's FP32 ranking may
+  order them either way, so its choice is checked to be a valid nearest set
+  and the likelihood is compared with the oracle evaluated on that choice.
 """
 
 import math
@@ -20,8 +27,13 @@ import numpy as np
 
 import oracle
 
-DELTA = 5e-4          # index units; bound on the kernel's FP32 rounding of u
+DELTA = 1e-9          # index units; bound on |u_kernel - u_oracle| (both FP64 transforms)
 TIE = 1e-12
+# An FP32 squared distance ((dx^2 + dy^2) + dz^2), dx rounded from the FP32
+# translations, carries at most about 5 rounding errors of 2^-24 relative to
+# the exact value (every term is non-negative); two such errors apart is below
+# 6e-7, so a relative gap of 1e-6 cannot be reordered.
+NB_TIE = 1e-6
 
 
 def quat_angle(qa, qb):
@@ -52,15 +64,17 @@ def check_eval(loglik, grad, ref, idx=None, report=None):
     bad_g = np.nonzero(np.any(dg > tol_g, axis=1))[0]
     if report is not None:
         rel_l = dl / np.maximum(np.abs(l_ref), 1e-30)
-        clean = ref["n_amb"][idx] == 0
-        rel_g = (dg / np.maximum(ref["gabs"][idx], 1e-30))
-        report.update(max_rel_l=float(rel_l.max()),
-                      max_rel_g_clean=float(rel_g[clean].max()) if clean.any() else 0.0,
+        rel_g = dg / np.maximum(ref["gabs"][idx], 1e-30)
+        report.update(max_rel_l=float(rel_l.max()), max_rel_g=float(rel_g.max()),
                       n_amb=int(ref["n_amb"][idx].sum()), n=len(idx))
     assert bad_l.size == 0, "loglik off for %d particles, first %d: %r vs %r (tol %r)" % (
         bad_l.size, idx[bad_l[0]], loglik[bad_l[0]], l_ref[bad_l[0]], tol_l[bad_l[0]])
-    assert bad_g.size == 0, "grad off for %d particles, first %d: %r vs %r" % (
-        bad_g.size, idx[bad_g[0]], grad[bad_g[0]], g_ref[bad_g[0]])
+    if bad_g.size:
+        rel = dg / np.maximum(ref["gabs"][idx], 1e-30)
+        w = int(np.argmax(rel.max(axis=1)))
+        raise AssertionError("grad off for %d particles, first %d: %r vs %r; worst %d: rel %r "
+                             "(scale %r)" % (bad_g.size, idx[bad_g[0]], grad[bad_g[0]],
+                                             g_ref[bad_g[0]], idx[w], rel[w], ref["gabs"][idx][w]))
 
 
 def check_step(poses_in, grad_gpu, poses_gpu, params):
@@ -155,3 +169,21 @@ def check_prune(logw_in, loglik_gpu, beta, u, out, tau_post, tau_lik):
     assert np.array_equal(out["poses"][dead], out["poses"][par[dead]])
     assert abs(np.sum(np.exp(out["logw"])) - 1.0) < 1e-10
     return r
+
+
+def check_neighbors(nb_gpu, ref, poses, kf_poses):
+    """Neighbour choice: bit-exact away from counted near-ties, else a valid
+    nearest set (each chosen keyframe within NB_TIE of the n-th FP64 distance).
+    Returns the boolean mask of particles whose choice differs from the oracle's."""
+    nb_gpu = np.asarray(nb_gpu)
+    tie = ref["nb_margin"] < NB_TIE
+    diff = np.any(nb_gpu != ref["neighbors"], axis=1)
+    assert not np.any(diff & ~tie), "neighbours differ away from near-ties at %s" % (
+        np.flatnonzero(diff & ~tie)[:10])
+    n = nb_gpu.shape[1]
+    for i in np.flatnonzero(diff):
+        t = np.asarray(poses[i, :3], np.float64)
+        d2 = np.sum((np.asarray(kf_poses[i, :, :3], np.float64) - t) ** 2, axis=1)
+        lim = np.sort(d2)[n - 1] * (1 + NB_TIE)
+        assert len(set(nb_gpu[i].tolist())) == n and np.all(d2[nb_gpu[i]] <= lim), i
+    return diff

@@ -137,3 +137,44 @@ int main(void) {
                         "-L", libdir, "-lmcslam", "-Wl,-rpath," + libdir, "-o", exe], check=True)
         r = subprocess.run([exe], stdout=subprocess.PIPE, text=True)
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.returncode
+
+
+def test_outputs_are_sized_from_the_session(monkeypatch):
+    """The getters allocate from mcs_session_info, never from caller sizes: a
+    stale N, K or neighbour count is refused before the library writes."""
+    import ctypes as C
+
+    from paper_2504_18056_amd import abi
+
+    calls = []
+
+    class FakeLib:
+        def mcs_session_info(self, ctx, sid, n, k, m, nb):
+            for ref, v in ((n, 10), (k, 3), (m, 64), (nb, 4)):
+                C.cast(ref, C.POINTER(C.c_int32))[0] = v
+            return abi.MCS_OK
+
+        def mcs_get_particles(self, ctx, sid, *ptrs):
+            calls.append("particles")
+            return abi.MCS_OK
+
+        def mcs_get_neighbors(self, ctx, sid, out, k):
+            calls.append("neighbors")
+            C.cast(k, C.POINTER(C.c_int32))[0] = 4
+            return abi.MCS_OK
+
+        def mcs_last_error(self):
+            return b"fake"
+
+    monkeypatch.setattr(abi, "_lib", FakeLib())
+    for bad in (dict(N=12), dict(N=10, K=5), dict(N=8)):
+        with pytest.raises(abi.McsError) as e:
+            abi.mcs_get_particles(None, 1, kf_poses=True, **bad)
+        assert e.value.status == abi.MCS_EINVAL
+    with pytest.raises(abi.McsError):
+        abi.mcs_get_neighbors(None, 1, 10, 3)
+    assert calls == []
+    out = abi.mcs_get_particles(None, 1, kf_poses=True)
+    assert out["poses"].shape == (10, 7) and out["kf_poses"].shape == (10, 3, 7)
+    assert abi.mcs_get_neighbors(None, 1).shape == (10, 4)
+    assert calls == ["particles", "neighbors"]

@@ -15,7 +15,7 @@ import oracle
 from paper_2504_18056_amd import abi
 from synth import configs
 
-from parity import check_loop_update, quat_angle, ulp32
+from parity import check_loop_update, check_neighbors, quat_angle, ulp32
 
 pytestmark = pytest.mark.gpu
 
@@ -50,9 +50,16 @@ def gicp_step(ctx, c, p, poses=None, kf=None, frames=1):
 def check_gicp(c, out, p, poses=None, kf=None):
     poses = c["poses"] if poses is None else poses
     kf = c["kf_poses"] if kf is None else kf
-    ref = oracle.gicp_evaluate(c["vox"], c["vox_dims"], c["vox_origins"], c["vox_edge"], c["scan"],
-                               c["scan_cov"], poses, kf, n_nb=p["n_neighbors"], delta=1e-9)
-    assert np.array_equal(out["neighbors"], ref["neighbors"])
+    args = (c["vox"], c["vox_dims"], c["vox_origins"], c["vox_edge"], c["scan"], c["scan_cov"],
+            poses, kf)
+    ref = oracle.gicp_evaluate(*args, n_nb=p["n_neighbors"], delta=1e-9)
+    diff = check_neighbors(out["neighbors"], ref, poses, kf)
+    if diff.any():
+        # Near-ties ranked the other way: compare with the oracle on the kernel's choice.
+        forced = oracle.gicp_evaluate(*args, n_nb=p["n_neighbors"], delta=1e-9,
+                                      neighbors=out["neighbors"])
+        for k in ("loglik", "H", "b", "habs", "babs", "n_amb"):
+            ref[k][diff] = forced[k][diff]
     ok = ref["n_amb"] == 0
     assert ok.mean() > 0.95
     dl = np.abs(out["loglik"][ok] - ref["loglik"][ok])

@@ -1,7 +1,7 @@
 """GPU parity of the keyframe-map step (Eq. 2-4 with per-particle keyframe poses).
 
-Neighbour choice is compared bit for bit (both sides rank FP32 squared
-distances); the likelihood and gradient use the stage-wise tolerances of
+Neighbour choice is compared bit for bit except at counted near-ties (the
+kernel ranks FP32 squared distances, the oracle FP64 ones); the likelihood and gradient use the stage-wise tolerances of
 parity.py, summed over the neighbours; resampling also permutes every
 particle's keyframe poses.
 """
@@ -15,7 +15,8 @@ import oracle
 from paper_2504_18056_amd import abi
 from synth import configs
 
-from parity import DELTA, check_loop_update, check_step, check_weights_resample, quat_angle
+from parity import (DELTA, NB_TIE, check_loop_update, check_neighbors, check_step,
+                    check_weights_resample, quat_angle)
 
 pytestmark = pytest.mark.gpu
 
@@ -55,10 +56,18 @@ def check_kf(c, out, p, dtype=abi.GRID_FP32, poses=None, kf=None, idx=None):
     elif dtype == abi.GRID_BF16:
         grids = oracle.quantize_bf16(grids)
     idx = np.arange(N) if idx is None else idx
+    ev = dict(n_nb=p["n_neighbors"], oob_skip=p.get("oob", 0) == abi.OOB_SKIP, delta=DELTA)
     ref = oracle.kf_evaluate(grids, c["dims"], c["origins"], c["h"], p["eps"], c["scan"],
-                             poses[idx], kf[idx], n_nb=p["n_neighbors"],
-                             oob_skip=p.get("oob", 0) == abi.OOB_SKIP, delta=DELTA)
-    assert np.array_equal(out["neighbors"][idx], ref["neighbors"])
+                             poses[idx], kf[idx], **ev)
+    diff = check_neighbors(out["neighbors"][idx], ref, poses[idx], kf[idx])
+    if diff.any():
+        # Near-ties ranked the other way: compare with the oracle on the kernel's choice.
+        forced = oracle.kf_evaluate(grids, c["dims"], c["origins"], c["h"], p["eps"], c["scan"],
+                                    poses[idx], kf[idx], neighbors=out["neighbors"][idx], **ev)
+        for k in ("loglik", "grad", "gabs", "amb_l", "amb_g"):
+            ref[k][diff] = forced[k][diff]
+    print("neighbour near-ties: %d of %d particles, %d ranked differently" % (
+        int(np.sum(ref["nb_margin"] < NB_TIE)), idx.size, int(diff.sum())))
     dl = np.abs(out["loglik"][idx] - ref["loglik"])
     assert np.all(dl <= 1e-5 * np.abs(ref["loglik"]) + ref["amb_l"]), dl.max()
     dg = np.abs(out["grad"][idx] - ref["grad"])

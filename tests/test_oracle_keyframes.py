@@ -7,6 +7,7 @@ over neighbours.
 """
 
 import numpy as np
+import pytest
 from scipy.spatial.transform import Rotation
 
 import oracle
@@ -60,12 +61,44 @@ def test_neighbours_are_nearest_by_translation_with_stable_ties():
     r = oracle.kf_evaluate(P["grids"], P["dims"], P["origins"], P["h"], 1e-3, P["scan"][:4],
                            P["poses"], P["kf"], n_nb=4)
     for i in range(40):
-        # FP32 squared distance, one rounding per operation (the kernel's precision).
-        dd = P["poses"][i, :3][None, :] - P["kf"][i, :, :3]
-        d2 = (dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]
-        assert d2.dtype == np.float32
-        ref = np.argsort(d2, kind="stable")[:4]
-        assert list(r["neighbors"][i]) == list(ref)
+        # Sec. III-C.1: nearest by translation distance; exact ties to the smaller index.
+        dd = P["poses"][i, :3].astype(np.float64)[None, :] - P["kf"][i, :, :3].astype(np.float64)
+        d2 = np.einsum("ka,ka->k", dd, dd)
+        order = np.argsort(d2, kind="stable")
+        assert list(r["neighbors"][i]) == list(order[:4])
+        # The margin is the smallest relative gap between consecutive ranks 0..4
+        # over pairs of distinct translations.
+        gaps = [(d2[order[s + 1]] - d2[order[s]]) / d2[order[s + 1]] for s in range(4)
+                if not np.array_equal(P["kf"][i, order[s], :3], P["kf"][i, order[s + 1], :3])]
+        assert r["nb_margin"][i] == pytest.approx(min(gaps), rel=1e-9, abs=1e-18)
+
+
+def test_neighbour_margin_flags_near_ties_and_forced_choice():
+    P = make_problem(4, K=6, N=3)
+    # Keyframe 5 is keyframe 1 moved by one FP32 ulp along x, away from the
+    # particle: its squared distance is larger by a relative gap of about 1e-7.
+    kx = P["kf"][0, 1, 0]
+    away = np.float32(np.inf) if kx > P["poses"][0, 0] else np.float32(-np.inf)
+    P["kf"][0, 5, :3] = P["kf"][0, 1, :3]
+    P["kf"][0, 5, 0] = np.nextafter(kx, away)
+    r = oracle.kf_evaluate(P["grids"], P["dims"], P["origins"], P["h"], 1e-3, P["scan"][:8],
+                           P["poses"], P["kf"], n_nb=6)
+    assert r["nb_margin"][0] < 1e-6
+    # A forced choice evaluates exactly those keyframes (order does not matter).
+    nb = r["neighbors"].copy()
+    f = oracle.kf_evaluate(P["grids"], P["dims"], P["origins"], P["h"], 1e-3, P["scan"][:8],
+                           P["poses"], P["kf"], n_nb=6, neighbors=nb[:, ::-1])
+    assert np.allclose(f["loglik"], r["loglik"], rtol=1e-13)
+    nb2 = np.tile(np.arange(6, dtype=np.int32), (3, 1))
+    f2 = oracle.kf_evaluate(P["grids"], P["dims"], P["origins"], P["h"], 1e-3, P["scan"][:8],
+                            P["poses"], P["kf"], n_nb=6, neighbors=nb2)
+    assert np.allclose(f2["loglik"], r["loglik"], rtol=1e-13)   # all six either way
+    one = oracle.kf_evaluate(P["grids"], P["dims"], P["origins"], P["h"], 1e-3, P["scan"][:8],
+                             P["poses"], P["kf"], n_nb=1, neighbors=np.full((3, 1), 3, np.int32))
+    Trel = np.linalg.inv(T_of(P["kf"][0, 3])) @ T_of(P["poses"][0])
+    ll, _ = oracle.evaluate_f64(P["grids"][3], P["dims"], P["origins"][3], P["h"], 1e-3,
+                                P["scan"][:8], pose_of(Trel)[None, :])
+    assert abs(one["loglik"][0] - ll[0]) < 1e-9 * abs(ll[0])
 
 
 def test_sum_over_neighbours_is_additive():
