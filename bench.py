@@ -27,15 +27,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particle×point lik+grad evals/s; ms/step @100k particles; p99 session ms"
-# The evaluation kernel is bound by VALU issue.  Its algorithmic work is
-# counted in VALU lane-operations (FP32 or FP64, an FMA counting once): the
-# compiled inner loop (gfx950) issues 233 VALU instructions per 4 evaluations
-# with FP32 cell records, 277 with FP16 and 309 with BF16 records.  Peak: 256 CU x 4 SIMD x 16
-# lanes x 2.4 GHz = 39.3e12 lane-ops/s without packed FP32 (disabled in this
-# build); the 157.3 TFLOP/s vector figure counts a packed FMA as 4 flops per
-# lane and cycle.
-VALU_OPS_PER_EVAL = {0: 58.25, 1: 69.25, 2: 77.25}
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic arithmetic of one (particle, point) evaluation, in FLOPs with an
+# FMA counted as two (the method's operations, independent of how the kernel
+# compiles them): transform u = A p + b, 9 FMA (18); cell index and fraction,
+# 3 floor + 3 subtract (6); trilinear value and gradient from the cell's 8
+# polynomial coefficients, 13 FMA + 3 multiplies (29); G + eps, ln, reciprocal
+# (3); gradient scale, 3 multiplies (3); accumulation of l, sum d and
+# sum v x d: 1 + 3 adds, cross product 3 multiplies + 3 FMA, 3 adds (16).
+FLOPS_PER_EVAL = 75
+# Published MI355X vector FP32 rate (256 CU x 2.4 GHz; an FMA = 2 FLOPs).
+FP32_PEAK_TFLOPS = 157.3
 BYTES_PER_EVAL = {0: 32, 1: 16, 2: 16}    # one cell record per evaluation
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_corridors_100k_counters.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2504_18056_amd", "csrc", "kernels.hip")
@@ -87,6 +88,33 @@ def device_copy_gbps(torch, mib=1024, reps=10):
     secs = a.elapsed_time(b) * 1e-3 / reps
     del src, dst
     return 2.0 * n * 4 / secs / 1e9
+
+
+def eval_vs_floor(abi, torch, ctx, sid, scan_dev, M, p, poses, logw, reps=10):
+    """Evaluation stage against its gather floor from one state: `reps` times
+    the likelihood passes of a step (no prediction, no resampling) and `reps`
+    times the gather-floor passes (same tiling, transformed coordinates and
+    record loads; a checksum instead of the arithmetic), each restarted from
+    the same poses.  Mean stage times from the library's HIP events."""
+    q = dict(p, resample=abi.RESAMPLE_NEVER, beta=0.0)
+    q.pop("delta_T", None)
+    out = {}
+    for name in ("eval", "floor"):
+        total, steps = 0.0, 0
+        for _ in range(reps):
+            abi.mcs_set_particles(ctx, sid, poses=poses, logw=logw)
+            abi.mcs_session_profile(ctx, sid, True)
+            if name == "eval":
+                abi.mcs_filter_step_dev(ctx, sid, scan_dev, M, q)
+            else:
+                abi.mcs_gather_floor_dev(ctx, sid, scan_dev, M, q)
+            pr = abi.mcs_session_profile_read(ctx, sid)
+            abi.mcs_session_profile(ctx, sid, False)
+            total += pr["eval_ms"]
+            steps += pr["steps"]
+        out[name + "_ms"] = round(total / max(1, steps), 4)
+    out["frac_of_floor_rate"] = round(out["floor_ms"] / out["eval_ms"], 4)
+    return out
 
 
 def run_cpu_baseline(c, frame, n_sample, threads=None):
@@ -419,6 +447,10 @@ def main():
                     help="1: also report the record-precision table, the keyframe-map and GICP "
                          "timings and the repeated-floors demo; 2: only the keyframe-map and GICP "
                          "timings (for profiling those kernels)")
+    ap.add_argument("--gather-floor", type=int, default=0,
+                    help="only time the evaluation stage against its gather floor, this many "
+                         "times each, from the cloud after the warm-up frames and from the "
+                         "initial spread (for profiling those kernels)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -496,6 +528,20 @@ def main():
         step(frames[k])
     torch.cuda.synchronize()
     log("warmup done (%d steps)" % args.warmup)
+    if args.gather_floor > 0:
+        st = abi.mcs_get_particles(ctx, sid, poses=True, logw=True, parents=False, loglik=False,
+                                   grad=False, stats=False)
+        f = frames[args.warmup - 1]
+        pf = dict(base, u=float(c["u"][f]))
+        res = {"workload": "corridors N=%d M=%d, %d passes" % (N, M, base["iters"]),
+               "converged": eval_vs_floor(abi, torch, ctx, sid, scans[f].data_ptr(), M, pf,
+                                          st["poses"], st["logw"], reps=args.gather_floor),
+               "initial_spread": eval_vs_floor(abi, torch, ctx, sid, scans[frames[0]].data_ptr(), M, pf,
+                                               c["poses"], np.full(N, -math.log(N)),
+                                               reps=args.gather_floor)}
+        abi.mcs_destroy(ctx)
+        print(json.dumps(res), flush=True)
+        return
     abi.mcs_session_profile(ctx, sid, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -525,6 +571,19 @@ def main():
     abi.mcs_session_sync(ctx, sid)
     host_ms = 1e3 * (time.perf_counter() - t0) / n_host
     log("host-buffer entry point: %.3f ms/step" % host_ms)
+    # The evaluation stage against its gather floor (same tiling, coordinates
+    # and record loads; the arithmetic cut to a checksum), from the converged
+    # cloud of the last timed frame and from the initial spread.
+    st = abi.mcs_get_particles(ctx, sid, poses=True, logw=True, parents=False, loglik=False,
+                               grad=False, stats=False)
+    pf = dict(base, u=float(c["u"][f_last]))
+    floors_conv = eval_vs_floor(abi, torch, ctx, sid, scans[f_last].data_ptr(), M, pf,
+                                st["poses"], st["logw"])
+    floors_conv["state"] = "the cloud after the timed frames, frame %d's scan" % f_last
+    floors_spread = eval_vs_floor(abi, torch, ctx, sid, scans[frames[0]].data_ptr(), M, pf,
+                                  c["poses"], np.full(N, -math.log(N)))
+    floors_spread["state"] = "the initial spread (0.5 m, 5 deg), frame %d's scan" % frames[0]
+    log("gather floor: converged %s; initial spread %s" % (floors_conv, floors_spread))
     abi.mcs_destroy(ctx)
     copy_gbps = device_copy_gbps(torch)
     log("device copy: %.0f GB/s (read + write)" % copy_gbps)
@@ -540,22 +599,27 @@ def main():
     # when the last round is small, the tail kernels beside it (HIP events on
     # the session stream around the stage).
     eval_s = prof["eval_ms"] * 1e-3 / max(1, prof["steps"])
-    ops = VALU_OPS_PER_EVAL[args.grid_dtype] * evals_per_step
-    achieved = ops / eval_s / 1e12
+    achieved = FLOPS_PER_EVAL * evals_per_step / eval_s / 1e12
     traffic = measured_traffic(args.grid_dtype)
-    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+    gbytes = BYTES_PER_EVAL[args.grid_dtype] * evals_per_step / 1e9
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": traffic,
                 "kernel": "k_eval (with its tail kernels)", "eval_launch_ms": round(eval_s * 1e3, 4),
-                "note": "VALU lane-operations per second (FP32/FP64, FMA counted once): %.2f per "
-                        "evaluation x %d evaluations per step's evaluation stage; peak = 256 CU x 64 "
-                        "lanes x 2.4 GHz (no packed FP32). traffic = HBM bytes per stage from "
-                        "FETCH_SIZE/WRITE_SIZE (%s); the algorithmic gather is %d B per evaluation = "
-                        "%.2f GB per stage, served almost entirely from the caches; VALU issue and the "
-                        "cache-resident gather co-limit the stage"
-                        % (VALU_OPS_PER_EVAL[args.grid_dtype], evals_per_step,
-                           os.path.relpath(PMC_SUMMARY, ROOT), BYTES_PER_EVAL[args.grid_dtype],
-                           BYTES_PER_EVAL[args.grid_dtype] * evals_per_step / 1e9)}
+                "flops_per_eval": FLOPS_PER_EVAL,
+                "gather_floor": floors_conv,
+                "gather_bytes_per_stage": round(gbytes * 1e9),
+                "gather_rate_TBps": round(gbytes / eval_s / 1e3, 3),
+                "note": "algorithmic FP32 arithmetic (%d FLOPs per evaluation, an FMA = 2) x %d "
+                        "evaluations per step's evaluation stage / the stage's time, against the "
+                        "published 157.3 TFLOP/s vector FP32 rate. gather_floor: the same passes "
+                        "with the arithmetic cut to a checksum of the gathered records (same tiling, "
+                        "coordinates and loads), timed from the same state; frac_of_floor_rate = "
+                        "floor time / evaluation time. traffic = HBM bytes per stage from "
+                        "FETCH_SIZE/WRITE_SIZE (%s); the algorithmic gather is %d B per evaluation, "
+                        "served almost entirely from the caches"
+                        % (FLOPS_PER_EVAL, evals_per_step, os.path.relpath(PMC_SUMMARY, ROOT),
+                           BYTES_PER_EVAL[args.grid_dtype])}
     stage_ms = {k: round(prof[k] / max(1, prof["steps"]), 4)
                 for k in ("predict_ms", "eval_ms", "weights_ms", "resample_ms")}
 
@@ -613,6 +677,7 @@ def main():
                    "particles": N, "points": M, "passes": passes,
                    "grid": list(c["dims"]), "grid_dtype": dtype_name},
         "stage_ms": stage_ms,
+        "gather_floor_initial_spread": floors_spread,
         "eval_ms_first_frame_initial_spread": round(first_eval_ms, 4),
         "eval_ms_initial_spread_second_time": round(spread_eval_ms, 4),
         "trilinear_samples_per_s": round(value, 1),
@@ -624,8 +689,8 @@ def main():
         "cpu_baseline": cpu,
         "cpu_baseline_one_thread": cpu1,
         "ms_per_step_100k": round(1e3 * wall / args.steps, 4) if N == 100000 else None,
-        "p99_session_ms": (min(serving["batched"]["p99_ms"], serving["concurrent"]["p99_ms"])
-                           if serving else None),
+        "p99_session_ms": serving["batched"]["p99_ms"] if serving else None,
+        "p99_session_ms_one_at_a_time": serving["one_at_a_time"]["p99_ms"] if serving else None,
         "serving": serving,
         "grid_record_precision": precision,
         "keyframes": keyframes,

@@ -12,6 +12,7 @@ arXiv 2504.18056).
 """
 
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -41,7 +42,9 @@ def _opt(kind):
 def lib():
     global _lib
     if _lib is None:
-        L = C.CDLL(ensure_built())
+        # MCS_ORACLE_LIB names another build of mcs_oracle.c (the mutation
+        # check loads deliberately broken copies to show that the pins fail).
+        L = C.CDLL(os.environ.get("MCS_ORACLE_LIB") or ensure_built())
         i32, f64 = C.c_int, C.c_double
         L.oracle_quat_to_rot.argtypes = [_dp, _dp]
         L.oracle_se3_exp.argtypes = [_dp, _dp]
