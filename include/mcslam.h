@@ -268,6 +268,37 @@ mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t session_id, const float *sc
 mcs_status mcs_gather_floor_dev(mcs_ctx *ctx, int32_t session_id, const float *scan_dev,
                                 int32_t M, const mcs_step_params *p, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one filter
+ * step, the same as mcs_filter_step_dev, of N particles on a single-grid map
+ * (from mcs_init_map), with the particle state and the outputs in the
+ * caller's device memory and every temporary of the step (packed scan,
+ * resampling copies, CDF and partial sums, statistics) in one static device
+ * area of 32 MiB per GPU, which the library holds from the first mcs_create
+ * on that GPU until the process ends.  The call allocates nothing.
+ *   pose_dev     [7][N] FP32, rows tx ty tz qw qx qy qz (in/out; quaternion
+ *                signs as the step leaves them)
+ *   logw_dev     [N] FP64 log-weights (in/out)
+ *   loglik_dev   [N], grad_dev [6][N] FP32: l and g of the last gradient pass
+ *   parents_dev  [N] int32 ancestors (identity when not resampled)
+ *   scan_dev     M*3 FP32; noise_dev N*6 FP32 or NULL, as for
+ *                mcs_filter_step_dev
+ *   stats_dev    one mcs_step_stats in device memory, or NULL
+ *   stream       hipStream_t to enqueue on (NULL: the null stream)
+ * Limits: 1 <= N <= MCS_NOALLOC_MAX_PARTICLES, 1 <= M <=
+ * MCS_NOALLOC_MAX_POINTS (MCS_EINVAL beyond them), single-grid maps only
+ * (MCS_EINVAL for keyframe or GICP maps).  Every call on one GPU uses that
+ * GPU's one area, which keeps the last call's contents: calls that overlap
+ * on one GPU (other streams, other threads) race and must be serialised by
+ * the caller.  The map must stay loaded until the enqueued work completes. */
+#define MCS_NOALLOC_MAX_PARTICLES 262144
+#define MCS_NOALLOC_MAX_POINTS    16384
+mcs_status mcs_filter_step_noalloc(mcs_ctx *ctx, int32_t map_id, int32_t N, float *pose_dev,
+                                   double *logw_dev, float *loglik_dev, float *grad_dev,
+                                   int32_t *parents_dev, const float *scan_dev, int32_t M,
+                                   const float *noise_dev, const mcs_step_params *p,
+                                   mcs_step_stats *stats_dev, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* GICP likelihood and Gauss-Newton correction (Sec. III-C, Eq. 2-7)          */
 /* ------------------------------------------------------------------------ */

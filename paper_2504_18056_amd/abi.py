@@ -127,6 +127,8 @@ def lib():
             "mcs_get_gicp_system": (i32, [vp, i32, vp, vp]),
             "mcs_session_info": (i32, [vp, i32, P(i32), P(i32), P(i32), P(i32)]),
             "mcs_gather_floor_dev": (i32, [vp, i32, vp, i32, P(StepParams), vp]),
+            "mcs_filter_step_noalloc": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, vp, i32, vp,
+                                              P(StepParams), vp, vp]),
             "mcs_session_trace": (i32, [vp, i32, i32]),
             "mcs_get_pass_trace": (i32, [vp, i32, i32, vp, vp, vp]),
         }
@@ -349,6 +351,19 @@ def mcs_filter_step_dev(ctx, sid, scan_dev_ptr, M, params, noise_dev_ptr=None, s
     _check(lib().mcs_filter_step_dev(ctx, int(sid), C.c_void_p(int(scan_dev_ptr)), int(M),
                                      None if noise_dev_ptr is None else C.c_void_p(int(noise_dev_ptr)),
                                      C.byref(p), None if stream is None else C.c_void_p(int(stream))))
+
+
+NOALLOC_MAX_PARTICLES, NOALLOC_MAX_POINTS = 262144, 16384
+
+
+def mcs_filter_step_noalloc(ctx, map_id, N, pose_dev, logw_dev, loglik_dev, grad_dev, parents_dev,
+                            scan_dev, M, params, noise_dev=None, stats_dev=None, stream=None):
+    """Allocation-free step on caller device memory (pointers as ints)."""
+    p = params if isinstance(params, StepParams) else step_params(params)
+    v = lambda x: None if x is None else C.c_void_p(int(x))  # noqa: E731
+    _check(lib().mcs_filter_step_noalloc(ctx, int(map_id), int(N), v(pose_dev), v(logw_dev),
+                                         v(loglik_dev), v(grad_dev), v(parents_dev), v(scan_dev),
+                                         int(M), v(noise_dev), C.byref(p), v(stats_dev), v(stream)))
 
 
 def mcs_gather_floor_dev(ctx, sid, scan_dev_ptr, M, params, stream=None):

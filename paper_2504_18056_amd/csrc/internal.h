@@ -151,4 +151,9 @@ struct BatchTables {
 // and out-of-grid rule.
 hipError_t launch_batch(const BatchTables &t, int dtype, int skip, hipStream_t st);
 
+// The allocation-free step's static device area: its size, and its address on
+// `device` (which must be current), looked up once per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+hipError_t scratch_init(int device, void **ptr);
+
 }  // namespace mcs

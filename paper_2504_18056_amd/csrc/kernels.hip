@@ -2497,4 +2497,31 @@ hipError_t launch_batch(const BatchTables &t, int dtype, int skip, hipStream_t s
     }
 }
 
+// ---------------------------------------------------------------------------
+// Static device area of the allocation-free step (mcs_filter_step_noalloc)
+// ---------------------------------------------------------------------------
+
+// One per GPU the library runs on, held until the process ends.  In host code
+// the array's name is not a device address: its address on a device comes
+// from hipGetSymbolAddress with that device current (scratch_init).
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t scratch_init(int device, void **ptr)
+{
+    static std::mutex mu;
+    static std::map<int, void *> by_device;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = by_device.find(device);
+    if (it != by_device.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    by_device[device] = p;
+    *ptr = p;
+    return hipSuccess;
+}
+
 }  // namespace mcs

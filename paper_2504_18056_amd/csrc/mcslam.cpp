@@ -7,6 +7,7 @@
 #include <array>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -446,9 +447,12 @@ mcs_status mcs_create(int32_t device, uint64_t hbm_budget_bytes, mcs_ctx **out)
     HIP_TRY(hipGetDeviceCount(&n), "hipGetDeviceCount");
     if (device < 0 || device >= n) return fail(MCS_EINVAL, "device %d not in [0, %d)", device, n);
     HIP_TRY(hipSetDevice(device), "hipSetDevice");
+    void *scr = nullptr;
+    HIP_TRY(scratch_init(device, &scr), "hipGetSymbolAddress(scratch)");
     mcs_ctx *c = new mcs_ctx;
     c->device = device;
     c->budget = hbm_budget_bytes;
+    c->scratch = scr;
     *out = c;
     return MCS_OK;
 }
@@ -1011,6 +1015,93 @@ mcs_status mcs_filter_step_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev,
                                const float *noise_dev, const mcs_step_params *p, void *stream)
 {
     return filter_step_dev(ctx, sid, scan_dev, nullptr, M, noise_dev, p, stream);
+}
+
+// The public statistics are the leading fields of the device-side record.
+static_assert(offsetof(StepStatsDev, lse) == offsetof(mcs_step_stats, lse) &&
+                  offsetof(StepStatsDev, ess) == offsetof(mcs_step_stats, ess) &&
+                  offsetof(StepStatsDev, resampled) == offsetof(mcs_step_stats, resampled) &&
+                  offsetof(StepStatsDev, best) == offsetof(mcs_step_stats, best) &&
+                  offsetof(StepStatsDev, best_pose) == offsetof(mcs_step_stats, best_pose) &&
+                  offsetof(StepStatsDev, degenerate) == offsetof(mcs_step_stats, degenerate) &&
+                  offsetof(StepStatsDev, pruned) == offsetof(mcs_step_stats, pruned),
+              "mcs_step_stats must be a prefix of StepStatsDev");
+
+mcs_status mcs_filter_step_noalloc(mcs_ctx *ctx, int32_t map_id, int32_t N, float *pose_dev,
+                                   double *logw_dev, float *loglik_dev, float *grad_dev,
+                                   int32_t *parents_dev, const float *scan_dev, int32_t M,
+                                   const float *noise_dev, const mcs_step_params *p,
+                                   mcs_step_stats *stats_dev, void *stream)
+{
+    if (!ctx || !pose_dev || !logw_dev || !loglik_dev || !grad_dev || !parents_dev || !scan_dev)
+        return fail(MCS_EINVAL, "NULL argument");
+    if (N < 1 || N > MCS_NOALLOC_MAX_PARTICLES)
+        return fail(MCS_EINVAL, "N=%d outside [1, %d] (the static area's limit)", N,
+                    MCS_NOALLOC_MAX_PARTICLES);
+    if (M < 1 || M > MCS_NOALLOC_MAX_POINTS)
+        return fail(MCS_EINVAL, "M=%d outside [1, %d] (the static area's limit)", M,
+                    MCS_NOALLOC_MAX_POINTS);
+    if (!ctx->scratch) return fail(MCS_EDEVICE, "no static area on device %d", ctx->device);
+    Map *m = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->maps.find(map_id);
+        if (it == ctx->maps.end()) return fail(MCS_ENOTFOUND, "no map %d", map_id);
+        m = it->second;
+    }
+    if (m->kind != kGridMap || m->K_cap > 0)
+        return fail(MCS_EINVAL, "the allocation-free step takes single-grid maps only");
+    // The step's temporaries, carved out of the static area.
+    const size_t n = (size_t)N, nb = (size_t)weight_blocks(N);
+    const size_t sizes[] = {7 * n * 4, n * 8, nb * kPartPerBlock * 8, n * 4, (size_t)M * 16,
+                            (size_t)M * 32, sizeof(StepStatsDev)};
+    size_t off[8], o = 0;
+    for (int k = 0; k < 7; ++k) {
+        off[k] = o;
+        o += align_up(sizes[k]);
+    }
+    off[7] = o;
+    if (o > kNoAllocScratchBytes) return fail(MCS_EINVAL, "step temporaries exceed the static area");
+    // A small last round of tiles is spread over one wave per sub-chunk when
+    // its partial sums fit the rest of the area (same results either way).
+    int tail = eval_tail_tiles(N, m->desc.dtype, false);
+    if (o + (size_t)tail * kTailBytesPerTile > kNoAllocScratchBytes) tail = 0;
+    char *b = (char *)ctx->scratch;
+    Session tmp;
+    tmp.map = m;
+    tmp.N = N;
+    tmp.M_max = M;
+    tmp.pose = pose_dev;
+    tmp.pose_tmp = (float *)(b + off[0]);
+    tmp.cdf_local = (double *)(b + off[1]);
+    tmp.part = (double *)(b + off[2]);
+    tmp.copies = (int32_t *)(b + off[3]);
+    tmp.scan4 = (float4 *)(b + off[4]);
+    tmp.scan8 = (double4 *)(b + off[5]);
+    tmp.stats = (StepStatsDev *)(b + off[6]);
+    tmp.loglik = loglik_dev;
+    tmp.grad = grad_dev;
+    tmp.logw = logw_dev;
+    tmp.parents = parents_dev;
+    if (tail > 0) {
+        tmp.tail_tiles = tail;
+        tmp.tail_l = (double *)(b + off[7]);
+        tmp.tail_g = (float *)(b + off[7] + (size_t)tail * kSubChunks * 64 * 8);
+    }
+    mcs_status st = validate_params(&tmp, p, M);
+    if (st != MCS_OK) return st;
+    if ((st = set_device(ctx)) != MCS_OK) return st;
+    const hipStream_t hs = (hipStream_t)stream;
+    const StepDesc d = make_desc(&tmp, scan_dev, M, p->predict ? noise_dev : nullptr, p);
+    if (!eval_supported(d)) return fail(MCS_EINVAL, "map not supported");
+    HIP_TRY(launch_pack_predict(d, hs), "pack/predict");
+    HIP_TRY(launch_eval(d, hs, nullptr), "eval");
+    HIP_TRY(launch_weights(d, hs), "weights");
+    HIP_TRY(launch_resample(d, hs), "resample");
+    if (stats_dev)
+        HIP_TRY(hipMemcpyAsync(stats_dev, d.stats, sizeof(mcs_step_stats), hipMemcpyDeviceToDevice, hs),
+                "stats");
+    return MCS_OK;
 }
 
 mcs_status mcs_gather_floor_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev, int32_t M,

@@ -97,6 +97,7 @@ struct mcs_ctx {
     std::map<int, mcs::Map *> maps;
     std::map<int, mcs::Session *> sessions;
     int next_id = 1;
+    void *scratch = nullptr;         // this device's static area (mcs_filter_step_noalloc)
 };
 
 namespace mcs {
