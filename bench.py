@@ -117,6 +117,48 @@ def eval_vs_floor(abi, torch, ctx, sid, scan_dev, M, p, poses, logw, reps=10):
     return out
 
 
+def run_trajectory(abi, torch, ctx, mid, c, base):
+    """The whole seeded trajectory from the initial spread, one step per frame
+    (the benchmark's step: prediction with odometry and per-particle noise, 3
+    passes, ESS resampling); per frame the representative's (max-weight
+    particle's) translation and rotation error against the true pose."""
+    from scipy.spatial.transform import Rotation
+    from synth import configs
+    N = c["poses"].shape[0]
+    M = c["scans"].shape[1]
+    n = c["scans"].shape[0]
+    dev = torch.device("cuda:0")
+    sid = abi.mcs_session_create(ctx, mid, c["poses"], M_max=M)
+    terr, rerr, ess, res = [], [], [], 0
+    try:
+        scans = torch.from_numpy(np.ascontiguousarray(c["scans"])).to(dev)
+        for f in range(1, n):
+            noise = torch.from_numpy(configs.prediction_noise(N, f, c["noise_sigma"], c["noise_seed"])).to(dev)
+            p = dict(base, u=float(c["u"][f]), delta_T=c["odometry"][f])
+            abi.mcs_filter_step_dev(ctx, sid, scans[f].data_ptr(), M, p, noise_dev_ptr=noise.data_ptr())
+            st = abi.mcs_get_particles(ctx, sid, poses=False, logw=False, parents=False, loglik=False,
+                                       grad=False)["stats"]
+            b = st["best_pose"].astype(np.float64)
+            terr.append(float(np.linalg.norm(b[:3] - c["t_traj"][f])))
+            qt = np.asarray(c["q_traj"][f], np.float64)
+            rel = Rotation.from_quat([qt[1], qt[2], qt[3], qt[0]]).inv() * \
+                Rotation.from_quat([b[4], b[5], b[6], b[3]])
+            rerr.append(float(np.degrees(rel.magnitude())))
+            ess.append(st["ess"])
+            res += int(st["resampled"])
+    finally:
+        abi.mcs_session_destroy(ctx, sid)
+    t, r = np.array(terr), np.array(rerr)
+    return {"frames": n - 1, "representative_translation_error_m":
+            {"mean": round(float(t.mean()), 4), "median": round(float(np.median(t)), 4),
+             "p95": round(float(np.percentile(t, 95)), 4), "max": round(float(t.max()), 4),
+             "final": round(float(t[-1]), 4)},
+            "representative_rotation_error_deg":
+            {"mean": round(float(r.mean()), 3), "median": round(float(np.median(r)), 3),
+             "max": round(float(r.max()), 3), "final": round(float(r[-1]), 3)},
+            "resampled_frames": res, "ess_median": round(float(np.median(ess)), 1)}
+
+
 def run_cpu_baseline(c, frame, n_sample, threads=None):
     """The FP64 oracle on one frame for n_sample particles (all host threads by default)."""
     import oracle
@@ -293,11 +335,63 @@ def run_gicp(abi, steps=5):
                     "3x3 inverse and 28-term accumulation"}
 
 
+FLOORS_NOISE_SIGMA = (0.03, 0.03, 0.005, 0.002, 0.002, 0.008)
+
+
+def floors_run(c, policy, beta=0.05, ctx=None):
+    """Kidnapped start over identical storeys, run through the library: each frame
+    prediction with odometry and device-drawn random-walk noise, gradient passes,
+    weighting and dead-particle pruning (or ESS resampling).  Returns the
+    per-frame share of the weight mass and of the particles on each storey, and
+    the representative's storey."""
+    from paper_2504_18056_amd import abi
+    own = ctx is None
+    ctx = abi.mcs_create(0) if own else ctx
+    N = c["poses"].shape[0]
+    M = c["scans"].shape[1]
+    mid = abi.mcs_init_map(ctx, abi.grid_desc(c["dims"], c["origin"], c["h"]), c["grid"])
+    sid = abi.mcs_session_create(ctx, mid, c["poses"], M_max=M)
+    z0 = c["t_traj"][0][2] - c["true_floor"] * c["storey"]
+    mass, share, best = [], [], []
+    try:
+        for f in range(c["scans"].shape[0]):
+            p = dict(c["params"], u=float(c["u"][f]), beta=beta, resample=policy, ess_frac=0.5,
+                     prune_post=1e-8, prune_lik=1e-16, noise_mode=abi.NOISE_DEVICE, rng_seed=77,
+                     rng_frame=f, noise_sigma=FLOORS_NOISE_SIGMA)
+            if f > 0:
+                p["delta_T"] = c["odometry"][f]
+            abi.mcs_filter_step(ctx, sid, c["scans"][f], p)
+            o = abi.mcs_get_particles(ctx, sid, N, parents=False, loglik=False, grad=False)
+            fl = np.clip(np.rint((o["poses"][:, 2] - z0) / c["storey"]), 0, c["floors"] - 1).astype(int)
+            w = np.exp(o["logw"])
+            mass.append(np.bincount(fl, weights=w, minlength=c["floors"]) / w.sum())
+            share.append(np.bincount(fl, minlength=c["floors"]) / N)
+            bz = o["stats"]["best_pose"][2]
+            best.append(int(np.clip(round((bz - z0) / c["storey"]), 0, c["floors"] - 1)))
+    finally:
+        abi.mcs_session_destroy(ctx, sid)
+        abi.mcs_release_map(ctx, mid)
+        if own:
+            abi.mcs_destroy(ctx)
+    return np.array(mass), np.array(share), np.array(best)
+
+
+def floors_summary(c, mass, share, best):
+    """Storey shares before the distinguishing feature is seen, and convergence after."""
+    t = c["true_floor"]
+    fs = c["first_seen"]
+    conv = [f for f in range(fs, len(mass)) if mass[f, t] > 0.9]
+    return {"first_seen_frame": int(fs),
+            "floors_with_5pct_particles_before": int(np.sum(share[fs - 1] >= 0.05)),
+            "mass_per_floor_before": [round(float(x), 3) for x in mass[fs - 1]],
+            "true_floor_mass_end": round(float(mass[-1, t]), 4),
+            "frames_to_90pct_after_first_seen": (conv[0] - fs) if conv else None,
+            "representative_on_true_floor_end": bool(best[-1] == t)}
+
+
 def run_floors(abi):
     """Kidnapped start over four identical storeys (N = 20,000, 80 frames): storey
     shares before the distinguishing feature is seen, and convergence after."""
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    import floors_demo
     from synth import configs
     c = configs.repeated_floors(N=20000)
     out = {"workload": "repeated floors: 4 identical storeys of a 51.2 m maze level, one box only on "
@@ -305,8 +399,8 @@ def run_floors(abi):
                        "device random-walk noise"}
     for policy, name in ((abi.RESAMPLE_PRUNE, "pruning"), (abi.RESAMPLE_ESS, "ess_resampling")):
         t0 = time.perf_counter()
-        mass, share, best = floors_demo.run(c, policy)
-        out[name] = dict(floors_demo.summary(c, mass, share, best),
+        mass, share, best = floors_run(c, policy)
+        out[name] = dict(floors_summary(c, mass, share, best),
                          ms_per_frame=round(1e3 * (time.perf_counter() - t0) / len(mass), 3))
     return out
 
@@ -584,6 +678,8 @@ def main():
                                   c["poses"], np.full(N, -math.log(N)))
     floors_spread["state"] = "the initial spread (0.5 m, 5 deg), frame %d's scan" % frames[0]
     log("gather floor: converged %s; initial spread %s" % (floors_conv, floors_spread))
+    trajectory = run_trajectory(abi, torch, ctx, mid, c, base)
+    log("trajectory: %s" % trajectory)
     abi.mcs_destroy(ctx)
     copy_gbps = device_copy_gbps(torch)
     log("device copy: %.0f GB/s (read + write)" % copy_gbps)
@@ -678,6 +774,7 @@ def main():
                    "grid": list(c["dims"]), "grid_dtype": dtype_name},
         "stage_ms": stage_ms,
         "gather_floor_initial_spread": floors_spread,
+        "trajectory_200_frames": trajectory,
         "eval_ms_first_frame_initial_spread": round(first_eval_ms, 4),
         "eval_ms_initial_spread_second_time": round(spread_eval_ms, 4),
         "trilinear_samples_per_s": round(value, 1),

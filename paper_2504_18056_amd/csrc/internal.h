@@ -91,9 +91,21 @@ struct StepDesc {
     // and the record loads and replace the arithmetic by a checksum of the
     // gathered words (l = checksum, g = 0, so the poses stay put).
     int32_t floor_only;
+    // Evaluation order (null: slot s takes particle s): the particles grouped
+    // by a coarse cell of their pose, recomputed each step after the
+    // prediction.  order [N] (slot -> particle), ocell and orank [N], ocount
+    // [kOrderCells] (counts, then offsets), obounds [weight_blocks(N)][2 * 6].
+    int32_t *order, *ocell, *orank, *ocount;
+    float *obounds;
 };
 
 constexpr int kTraceRows = 14;
+constexpr int kOrderDims = 6;
+constexpr int kOrderBits = 3;                                  // per coordinate
+constexpr int kOrderDrop = 2;                                  // low Morton bits dropped
+constexpr int kOrderCells = 1 << (kOrderDims * kOrderBits - kOrderDrop);   // 65536
+// Sessions of at least this many particles evaluate in the grouped order.
+constexpr int kOrderMinParticles = 4096;
 
 constexpr int kWeightBlock = 256;
 constexpr int kPartPerBlock = 6;   // doubles of per-block partials
@@ -122,6 +134,8 @@ struct TailAux {
     hipEvent_t fork, join;
 };
 hipError_t launch_eval(const StepDesc &d, hipStream_t st, const TailAux *aux = nullptr);
+// Evaluation order of the step (nothing when d.order is null).
+hipError_t launch_order(const StepDesc &d, hipStream_t st);
 hipError_t launch_weights(const StepDesc &d, hipStream_t st);
 hipError_t launch_resample(const StepDesc &d, hipStream_t st);
 // Whether the eval kernels accept this map (record buffer under 4 GiB).

@@ -671,6 +671,12 @@ __device__ __forceinline__ void body_gradient(const float q[4], const float s[6]
     gr[5] = R[2] * s[3] + R[5] * s[4] + R[8] * s[5];
 }
 
+// The particle a slot of the evaluation takes (N for the slots past the last).
+__device__ __forceinline__ int slot_particle(const StepDesc &d, int slot)
+{
+    return d.order ? (slot < d.N ? d.order[slot] : d.N) : slot;
+}
+
 // Load the tile's poses into LDS as stored: the first pass evaluates the
 // pose itself (its quaternion normalised in FP64 by the grid map); the FP32
 // normalisation happens before the first step.
@@ -765,7 +771,7 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int i = tile * 64 + lane;
+    const int i = slot_particle(d, tile * 64 + lane);
     if (wave == 0) load_tile_pose(d, i, lane, s_pose);
 
     GridK g;
@@ -831,7 +837,7 @@ __device__ __forceinline__ void tail_chunk(const StepDesc &d, int tile0, int pas
 {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x & 63;
-    const int i = (tile0 + rel) * 64 + lane;
+    const int i = slot_particle(d, (tile0 + rel) * 64 + lane);
     GridK g;
     const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
     g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
@@ -867,7 +873,7 @@ __device__ __forceinline__ void tail_step(const StepDesc &d, int tile0, int pass
     __shared__ float s_g[6][W][64];
     __shared__ float s_pose[7][64];
     const int lane = threadIdx.x & 63;
-    const int i = (tile0 + rel) * 64 + lane;
+    const int i = slot_particle(d, (tile0 + rel) * 64 + lane);
     float t[3], q[4];
     tail_pose(d, i, pass, t, q);
     s_pose[0][lane] = t[0]; s_pose[1][lane] = t[1]; s_pose[2][lane] = t[2];
@@ -2098,6 +2104,155 @@ __device__ __forceinline__ void fill_blk(const StepDesc &d, int b)
 }
 
 // ---------------------------------------------------------------------------
+// Evaluation order: particles grouped by a coarse cell of their pose
+// ---------------------------------------------------------------------------
+
+// Where a particle's transformed points land is set by its translation and
+// rotation, so the evaluation takes the particles grouped by a coarse cell of
+// six pose coordinates (translation, and the vector part of the quaternion
+// taken with w >= 0): each coordinate is cut into 2^kOrderBits equal parts of
+// the cloud's range, the parts are ranked along a Morton curve, and cells are
+// runs of 2^kOrderDrop consecutive Morton codes.  A wave's
+// 64 lanes then hold particles of nearby poses, whose record loads touch
+// fewer cache lines.  The order inside a cell is whatever the atomic ranks
+// give: every particle's arithmetic, and so its result, is the same in any
+// slot.
+__device__ __forceinline__ void order_coords(const StepDesc &d, int i, float c[kOrderDims])
+{
+    const int N = d.N;
+    const float w = d.pose[3 * N + i];
+    const float sg = w < 0.0f ? -1.0f : 1.0f;
+    c[0] = d.pose[i];
+    c[1] = d.pose[N + i];
+    c[2] = d.pose[2 * N + i];
+    c[3] = sg * d.pose[4 * N + i];
+    c[4] = sg * d.pose[5 * N + i];
+    c[5] = sg * d.pose[6 * N + i];
+}
+
+// Per block: the low and high ends of each coordinate over its particles
+// (non-finite values are left out); the blocks also clear the cell counts.
+__device__ __forceinline__ void order_bounds_blk(const StepDesc &d, int b)
+{
+    constexpr int B = kWeightBlock;
+    __shared__ float lo[B], hi[B];
+    const int tid = threadIdx.x;
+    const int i = b * B + tid;
+    float c[kOrderDims];
+    const bool ok = i < d.N;
+    if (ok) order_coords(d, i, c);
+    for (int k = 0; k < kOrderDims; ++k) {
+        const bool fin = ok && fabsf(c[k]) <= 1e30f;
+        lo[tid] = fin ? c[k] : INFINITY;
+        hi[tid] = fin ? c[k] : -INFINITY;
+        __syncthreads();
+        for (int st = B / 2; st > 0; st >>= 1) {
+            if (tid < st) {
+                lo[tid] = fminf(lo[tid], lo[tid + st]);
+                hi[tid] = fmaxf(hi[tid], hi[tid + st]);
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            d.obounds[(size_t)b * 2 * kOrderDims + 2 * k] = lo[0];
+            d.obounds[(size_t)b * 2 * kOrderDims + 2 * k + 1] = hi[0];
+        }
+        __syncthreads();
+    }
+    const int stride = weight_blocks(d.N) * B;
+    for (int k = b * B + tid; k < kOrderCells; k += stride) d.ocount[k] = 0;
+}
+
+// Per particle: its cell (the cloud's range from all blocks' bounds) and its
+// rank among the particles of that cell.
+__device__ __forceinline__ void order_cell_blk(const StepDesc &d, int b)
+{
+    constexpr int B = kWeightBlock;
+    __shared__ float lo[kOrderDims][B], hi[kOrderDims][B];
+    __shared__ float base[kOrderDims], scale[kOrderDims];
+    const int tid = threadIdx.x;
+    const int nb = weight_blocks(d.N);
+    for (int k = 0; k < kOrderDims; ++k) {
+        float l = INFINITY, h = -INFINITY;
+        for (int q = tid; q < nb; q += B) {
+            l = fminf(l, d.obounds[(size_t)q * 2 * kOrderDims + 2 * k]);
+            h = fmaxf(h, d.obounds[(size_t)q * 2 * kOrderDims + 2 * k + 1]);
+        }
+        lo[k][tid] = l;
+        hi[k][tid] = h;
+    }
+    __syncthreads();
+    for (int st = B / 2; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int k = 0; k < kOrderDims; ++k) {
+                lo[k][tid] = fminf(lo[k][tid], lo[k][tid + st]);
+                hi[k][tid] = fmaxf(hi[k][tid], hi[k][tid + st]);
+            }
+        __syncthreads();
+    }
+    if (tid < kOrderDims) {
+        const float l = lo[tid][0], h = hi[tid][0];
+        const float span = h - l;
+        base[tid] = l;
+        scale[tid] = (span > 0.0f && span <= 1e30f) ? (float)(1 << kOrderBits) / span : 0.0f;
+    }
+    __syncthreads();
+    const int i = b * B + tid;
+    if (i >= d.N) return;
+    float c[kOrderDims];
+    order_coords(d, i, c);
+    int q[kOrderDims];
+    for (int k = 0; k < kOrderDims; ++k) {
+        const float v = (c[k] - base[k]) * scale[k];
+        q[k] = (v >= 0.0f) ? min((int)v, (1 << kOrderBits) - 1) : 0;   // NaN and below: cell 0
+    }
+    int code = 0;
+    for (int bit = kOrderBits - 1; bit >= 0; --bit)
+        for (int k = 0; k < kOrderDims; ++k) code = (code << 1) | ((q[k] >> bit) & 1);
+    const int cell = code >> kOrderDrop;
+    d.ocell[i] = cell;
+    d.orank[i] = __hip_atomic_fetch_add(d.ocount + cell, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One block of kOrderPrefixBlock threads: exclusive prefix of the cell
+// counts, in place.
+constexpr int kOrderPrefixBlock = 1024;
+__device__ __forceinline__ void order_prefix_blk(const StepDesc &d)
+{
+    constexpr int B = kOrderPrefixBlock;
+    constexpr int per = kOrderCells / B;
+    __shared__ int sh[2][B];
+    const int tid = threadIdx.x;
+    int v[per], sum = 0;
+    for (int k = 0; k < per; ++k) {
+        v[k] = d.ocount[tid * per + k];
+        sum += v[k];
+    }
+    int cur = 0;
+    sh[cur][tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < B; off <<= 1) {
+        const int x = sh[cur][tid] + (tid >= off ? sh[cur][tid - off] : 0);
+        sh[cur ^ 1][tid] = x;
+        cur ^= 1;
+        __syncthreads();
+    }
+    int run = sh[cur][tid] - sum;              // exclusive prefix of this thread's cells
+    for (int k = 0; k < per; ++k) {
+        d.ocount[tid * per + k] = run;
+        run += v[k];
+    }
+}
+
+// Per particle: its slot in the evaluation order.
+__device__ __forceinline__ void order_scatter_blk(const StepDesc &d, int b)
+{
+    const int i = b * kWeightBlock + threadIdx.x;
+    if (i >= d.N) return;
+    d.order[d.ocount[d.ocell[i]] + d.orank[i]] = i;
+}
+
+// ---------------------------------------------------------------------------
 // Kernels: one session per launch (grid = that session's blocks)
 // ---------------------------------------------------------------------------
 
@@ -2179,6 +2334,10 @@ __global__ __launch_bounds__(kWeightBlock) void k_prefix(StepDesc d) { prefix_bl
 __global__ __launch_bounds__(kWeightBlock) void k_search(StepDesc d) { search_blk(d, blockIdx.x); }
 __global__ __launch_bounds__(kWeightBlock) void k_commit(StepDesc d) { commit_blk(d, blockIdx.x); }
 __global__ __launch_bounds__(kWeightBlock) void k_fill(StepDesc d) { fill_blk(d, blockIdx.x); }
+__global__ __launch_bounds__(kWeightBlock) void k_order_bounds(StepDesc d) { order_bounds_blk(d, blockIdx.x); }
+__global__ __launch_bounds__(kWeightBlock) void k_order_cell(StepDesc d) { order_cell_blk(d, blockIdx.x); }
+__global__ __launch_bounds__(kOrderPrefixBlock) void k_order_prefix(StepDesc d) { order_prefix_blk(d); }
+__global__ __launch_bounds__(kWeightBlock) void k_order_scatter(StepDesc d) { order_scatter_blk(d, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
 // Kernels: persistent, batched over many sessions
@@ -2436,6 +2595,17 @@ hipError_t launch_eval(const StepDesc &d, hipStream_t st, const TailAux *aux)
     case 2: return skip ? launch_eval_dt<2, true>(d, st, aux) : launch_eval_dt<2, false>(d, st, aux);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_order(const StepDesc &d, hipStream_t st)
+{
+    if (!d.order) return hipSuccess;
+    const dim3 nb((unsigned)weight_blocks(d.N));
+    hipLaunchKernelGGL(k_order_bounds, nb, dim3(kWeightBlock), 0, st, d);
+    hipLaunchKernelGGL(k_order_cell, nb, dim3(kWeightBlock), 0, st, d);
+    hipLaunchKernelGGL(k_order_prefix, dim3(1), dim3(kOrderPrefixBlock), 0, st, d);
+    hipLaunchKernelGGL(k_order_scatter, nb, dim3(kWeightBlock), 0, st, d);
+    return hipGetLastError();
 }
 
 hipError_t launch_weights(const StepDesc &d, hipStream_t st)

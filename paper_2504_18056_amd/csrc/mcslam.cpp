@@ -41,7 +41,7 @@ mcs_status hip_fail(hipError_t e, const char *what)
 }
 
 struct Layout {
-    size_t off[21];
+    size_t off[24];
     size_t total;
 };
 
@@ -81,6 +81,9 @@ Layout session_layout(int N, int M_max, int K, bool gicp, size_t tail_size)
         (gicp ? (size_t)M_max * 6 * 4 : 0),                // 18 cov6
         (gicp ? 21 * n * 4 : 0),                           // 19 hess
         tail_size,                                         // 20 tail sub-chunk sums
+        (K == 0 && !gicp ? 3 * n * 4 : 0),                 // 21 evaluation order: order, ocell, orank
+        (K == 0 && !gicp ? (size_t)kOrderCells * 4 : 0),   // 22 ocount
+        (K == 0 && !gicp ? nb * 2 * kOrderDims * 4 : 0),   // 23 obounds
     };
     Layout L{};
     size_t o = 0;
@@ -355,6 +358,13 @@ StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float 
     d.u = p->u;
     for (int c = 0; c < 7; ++c) d.dT[c] = p->delta_T[c];
     d.trace = s->trace;
+    if (s->order && s->N >= kOrderMinParticles) {
+        d.order = s->order;
+        d.ocell = s->ocell;
+        d.orank = s->orank;
+        d.ocount = s->ocount;
+        d.obounds = s->obounds;
+    }
     return d;
 }
 
@@ -394,6 +404,7 @@ mcs_status enqueue_step(Session *s, const float *scan3_dev, int M, const float *
                              (s->K > 0 ? p->n_neighbors : 1);
     PROF_MARK(0);
     HIP_TRY(launch_pack_predict(d, st), "pack/predict");
+    HIP_TRY(launch_order(d, st), "order");
     PROF_MARK(1);
     const TailAux aux{s->tail_stream, s->tail_fork, s->tail_join};
     HIP_TRY(launch_eval(d, st, s->tail_stream ? &aux : nullptr), "eval");
@@ -822,6 +833,13 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
     ss->stats = (StepStatsDev *)(b + L.off[14]);
     ss->scan8 = (double4 *)(b + L.off[15]);
     ss->copies = (int32_t *)(b + L.off[16]);
+    if (m->K_cap == 0 && m->kind == kGridMap) {
+        ss->order = (int32_t *)(b + L.off[21]);
+        ss->ocell = ss->order + N;
+        ss->orank = ss->ocell + N;
+        ss->ocount = (int32_t *)(b + L.off[22]);
+        ss->obounds = (float *)(b + L.off[23]);
+    }
     if (m->kind == kVoxelMap) {
         ss->scan_g = (float4 *)(b + L.off[17]);
         ss->cov6 = (float *)(b + L.off[18]);
@@ -1054,13 +1072,15 @@ mcs_status mcs_filter_step_noalloc(mcs_ctx *ctx, int32_t map_id, int32_t N, floa
     // The step's temporaries, carved out of the static area.
     const size_t n = (size_t)N, nb = (size_t)weight_blocks(N);
     const size_t sizes[] = {7 * n * 4, n * 8, nb * kPartPerBlock * 8, n * 4, (size_t)M * 16,
-                            (size_t)M * 32, sizeof(StepStatsDev)};
-    size_t off[8], o = 0;
-    for (int k = 0; k < 7; ++k) {
+                            (size_t)M * 32, sizeof(StepStatsDev), 3 * n * 4, (size_t)kOrderCells * 4,
+                            nb * 2 * kOrderDims * 4};
+    constexpr int kParts = sizeof sizes / sizeof sizes[0];
+    size_t off[kParts + 1], o = 0;
+    for (int k = 0; k < kParts; ++k) {
         off[k] = o;
         o += align_up(sizes[k]);
     }
-    off[7] = o;
+    off[kParts] = o;
     if (o > kNoAllocScratchBytes) return fail(MCS_EINVAL, "step temporaries exceed the static area");
     // A small last round of tiles is spread over one wave per sub-chunk when
     // its partial sums fit the rest of the area (same results either way).
@@ -1079,14 +1099,19 @@ mcs_status mcs_filter_step_noalloc(mcs_ctx *ctx, int32_t map_id, int32_t N, floa
     tmp.scan4 = (float4 *)(b + off[4]);
     tmp.scan8 = (double4 *)(b + off[5]);
     tmp.stats = (StepStatsDev *)(b + off[6]);
+    tmp.order = (int32_t *)(b + off[7]);
+    tmp.ocell = tmp.order + N;
+    tmp.orank = tmp.ocell + N;
+    tmp.ocount = (int32_t *)(b + off[8]);
+    tmp.obounds = (float *)(b + off[9]);
     tmp.loglik = loglik_dev;
     tmp.grad = grad_dev;
     tmp.logw = logw_dev;
     tmp.parents = parents_dev;
     if (tail > 0) {
         tmp.tail_tiles = tail;
-        tmp.tail_l = (double *)(b + off[7]);
-        tmp.tail_g = (float *)(b + off[7] + (size_t)tail * kSubChunks * 64 * 8);
+        tmp.tail_l = (double *)(b + off[kParts]);
+        tmp.tail_g = (float *)(b + off[kParts] + (size_t)tail * kSubChunks * 64 * 8);
     }
     mcs_status st = validate_params(&tmp, p, M);
     if (st != MCS_OK) return st;
@@ -1095,6 +1120,7 @@ mcs_status mcs_filter_step_noalloc(mcs_ctx *ctx, int32_t map_id, int32_t N, floa
     const StepDesc d = make_desc(&tmp, scan_dev, M, p->predict ? noise_dev : nullptr, p);
     if (!eval_supported(d)) return fail(MCS_EINVAL, "map not supported");
     HIP_TRY(launch_pack_predict(d, hs), "pack/predict");
+    HIP_TRY(launch_order(d, hs), "order");
     HIP_TRY(launch_eval(d, hs, nullptr), "eval");
     HIP_TRY(launch_weights(d, hs), "weights");
     HIP_TRY(launch_resample(d, hs), "resample");
@@ -1133,6 +1159,7 @@ mcs_status mcs_gather_floor_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev
     } while (0)
     FLOOR_MARK(0);
     HIP_TRY(launch_pack_predict(d, hs), "pack");
+    HIP_TRY(launch_order(d, hs), "order");
     FLOOR_MARK(1);
     const TailAux aux{s->tail_stream, s->tail_fork, s->tail_join};
     HIP_TRY(launch_eval(d, hs, s->tail_stream ? &aux : nullptr), "gather floor");

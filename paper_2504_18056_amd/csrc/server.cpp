@@ -199,7 +199,8 @@ bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b, T
             run.push_back(r.id);   // validated at submission; a destroyed session is skipped
             continue;
         }
-        const StepDesc d = make_desc(ss, r.scan, r.M, r.noise, &r.p);
+        StepDesc d = make_desc(ss, r.scan, r.M, r.noise, &r.p);
+        d.order = nullptr;   // the batched stages evaluate in slot order
         const int nb = weight_blocks(d.N), nt = particle_tiles(d.N), ns = scan_blocks(d.M);
         const std::array<int, kNumKinds> need = {ns, d.predict ? nb : 0, nt, nb, 1, nb, 1, nb, nb,
                                                  d.policy == MCS_RESAMPLE_PRUNE ? nb : 0};

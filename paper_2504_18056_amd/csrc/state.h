@@ -72,6 +72,8 @@ struct Session {
     float *pinned = nullptr;         // host staging for host-pointer steps
     size_t pinned_floats = 0;
     int last_nb = 0;                 // neighbours per particle in the last keyframe step
+    int32_t *order = nullptr, *ocell = nullptr, *orank = nullptr, *ocount = nullptr;
+    float *obounds = nullptr;        // single-grid sessions: evaluation order buffers
     float *trace = nullptr;          // pass trace [trace_passes][kTraceRows][N] (null: off)
     int trace_passes = 0;
     size_t trace_bytes = 0;

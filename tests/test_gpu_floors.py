@@ -10,15 +10,15 @@ import pytest
 from paper_2504_18056_amd import abi
 from synth import configs
 
-import floors_demo
+import bench
 
 pytestmark = pytest.mark.gpu
 
 
 def test_pruning_keeps_storeys_until_evidence_then_converges():
     c = configs.repeated_floors(N=20000)
-    mass, share, best = floors_demo.run(c, abi.RESAMPLE_PRUNE)
-    s = floors_demo.summary(c, mass, share, best)
+    mass, share, best = bench.floors_run(c, abi.RESAMPLE_PRUNE)
+    s = bench.floors_summary(c, mass, share, best)
     print("repeated floors (pruning):", s)
     fs = c["first_seen"]
     # Identical storeys: every storey keeps particles before the evidence.

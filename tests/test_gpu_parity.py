@@ -275,3 +275,17 @@ def test_grid_slab_beyond_24_bits(ctx, dtype, oob):
     full_check(c, out, p, dtype=dtype, report=rep)
     assert np.all(out["loglik"] > c["scan"].shape[0] * math.log(0.1))   # points inside the slab
     print("wide slab dtype %d: %s" % (dtype, rep))
+
+
+def test_evaluation_order_does_not_change_results(ctx):
+    """Sessions of >= 4096 particles evaluate them grouped by pose cell; each
+    particle's l, g and stepped pose are the same as in sessions too small to
+    be reordered (bit for bit), and the grouped session still matches the oracle."""
+    c = configs.box_room(N=5000, seed=93)
+    p = dict(c["params"], iters=2, u=0.5, beta=0.0, resample=abi.RESAMPLE_NEVER)
+    whole = one_step(ctx, c, p)
+    parts = [one_step(ctx, c, p, poses=c["poses"][a:b]) for a, b in ((0, 4000), (4000, 5000))]
+    for k in ("loglik", "grad", "poses"):
+        assert np.array_equal(whole[k], np.concatenate([q[k] for q in parts])), k
+    p1 = dict(p, iters=1, resample=abi.RESAMPLE_ALWAYS, u=0.37, beta=0.01)
+    full_check(c, one_step(ctx, c, p1), p1)
