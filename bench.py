@@ -198,8 +198,11 @@ def prepare_serving(args):
     return out
 
 
-def run_serving(args, abi, torch, prepared):
-    """Many concurrent sessions with Poisson frame arrivals: batched server vs one at a time."""
+def run_serving(args, abi, torch, prepared, load=None, seconds=None, admission=True):
+    """Many concurrent sessions with Poisson frame arrivals: batched server vs one at a time.
+    load multiplies the 10 Hz per-session arrival rate; seconds is the schedule's length."""
+    load = args.serving_load if load is None else load
+    seconds = args.serving_seconds if seconds is None else seconds
     from synth import configs
     dev = torch.device("cuda:0")
     ctx = abi.mcs_create(0)
@@ -226,7 +229,7 @@ def run_serving(args, abi, torch, prepared):
     rng = np.random.default_rng(4242)
     arrivals = []
     for k, s in enumerate(sessions):
-        for t in configs.poisson_arrivals(10.0 * args.serving_load, args.serving_seconds, rng):
+        for t in configs.poisson_arrivals(10.0 * load, seconds, rng):
             arrivals.append((t, k))
     arrivals.sort()
     results = {}
@@ -269,6 +272,10 @@ def run_serving(args, abi, torch, prepared):
                          "evals_per_s": round(st["evals"] / span, 1)}
         log("serving %s: %s" % (name, results[name]))
     abi.mcs_destroy(ctx)
+    if not admission:
+        return {"sessions": len(sessions), "seconds": seconds, "arrival_hz_per_session": 10.0 * load,
+                "offered_frames_per_s": round(len(arrivals) / seconds, 1),
+                "resident_gb": round(mem / 1e9, 2), **results}
     # Admission under an HBM budget of half the footprint: sessions are admitted
     # in order until the next one would exceed the budget.
     budget = mem // 2
@@ -293,8 +300,9 @@ def run_serving(args, abi, torch, prepared):
             refused += 1
     in_use = abi.mcs_memory_in_use(actx)
     abi.mcs_destroy(actx)
-    return {"sessions": len(sessions), "seconds": args.serving_seconds,
-            "arrival_hz_per_session": 10.0 * args.serving_load,
+    return {"sessions": len(sessions), "seconds": seconds,
+            "arrival_hz_per_session": 10.0 * load,
+            "offered_frames_per_s": round(len(arrivals) / seconds, 1),
             "resident_gb": round(mem / 1e9, 2), **results,
             "admission_at_half_budget": {"budget_gb": round(budget / 1e9, 2), "admitted": admitted,
                                          "refused": refused, "in_use_gb": round(in_use / 1e9, 2)}}
@@ -752,6 +760,10 @@ def main():
     serving = None
     if args.serving_seconds > 0:
         serving = run_serving(args, abi, torch, prepared)
+        # Three times the arrival rate, past what one-at-a-time execution
+        # sustains: aggregate evaluations per second of each mode.
+        serving["saturated"] = run_serving(args, abi, torch, prepared, load=3.0 * args.serving_load,
+                                           seconds=max(1.0, args.serving_seconds / 2), admission=False)
         del prepared
 
     dtype_name = {0: "fp32", 1: "fp32 (fp16 grid)", 2: "fp32 (bf16 grid)"}[args.grid_dtype]

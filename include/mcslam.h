@@ -423,13 +423,20 @@ mcs_status mcs_session_profile_read(mcs_ctx *ctx, int32_t session_id, mcs_profil
 
 /* Each particle, and so each session, updates independently (Sec. III-A), so
  * the steps of many sessions can share the device.  A server owns a worker
- * thread that takes submitted frame requests in arrival order and, in
- * MCS_SERVE_BATCHED mode, runs them in ticks: every tick takes at most one
- * pending frame per session (up to max_batch sessions), writes a table of
- * per-session step descriptors and work items, and replays one captured HIP
- * graph of persistent kernels that process all sessions' work items
- * together; up to two ticks are in flight, so frames arriving while a tick
- * runs join the next one.  A session's frames always run in submission order.
+ * thread that takes submitted frame requests and, in MCS_SERVE_BATCHED mode,
+ * runs them in two lanes side by side.  Frames of sessions large enough to
+ * fill the device on their own (a round of evaluation tiles: 512 x 64
+ * particles on MI355X) are launched as they arrive with the per-session
+ * launches on the session's own stream, so they overlap each other and the
+ * ticks (at most 256 in flight).  Frames of smaller sessions run
+ * in ticks: a tick takes the oldest pending frame, then the smallest pending
+ * frames of other sessions (at most one per session, up to max_batch) while
+ * its evaluations stay under a cap of one round's worth at 2,048 points and 3
+ * passes; it writes a table of per-session step descriptors and work items
+ * and replays one captured HIP graph of persistent kernels that process all
+ * sessions' work items together; up to two ticks are in flight, so frames
+ * arriving while a tick runs join a later one.  A session's frames always run
+ * in submission order.
  * Results are identical to mcs_filter_step_dev on the same inputs (the
  * kernels and their reduction order do not depend on the batch).
  * MCS_SERVE_CONCURRENT launches each request as soon as it arrives, with the

@@ -25,9 +25,11 @@ struct StepStatsDev {
 };
 
 // One session's filter step as every kernel sees it.  The grid is stored
-// cell-major: cell (i, j, k), i < nx-1, j < ny-1, k < nz-1, is record
-// i + (nx-1)*(j + (ny-1)*k) and holds the corner samples (i+a, j+b, k+c) at
-// slot a + 2b + 4c, as 8 FP32 (32 B) or 8 FP16/BF16 (16 B).
+// cell-major with a zero layer around the cells: cell (i, j, k), i < nx-1,
+// j < ny-1, k < nz-1, is record (i+1) + (nx+1)*((j+1) + (ny+1)*(k+1)) and holds
+// either the 8 coefficients of its trilinear polynomial (FP32, 32 B) or its
+// corner samples (i+a, j+b, k+c) at slot a + 2b + 4c (FP16/BF16, 16 B);
+// records with an index 0 or n on some axis are zero.
 struct StepDesc {
     // Map.  Keyframe maps (K > 0) hold K grids of equal dims, grid_stride
     // bytes apart, each with its own origin (origins[3k..3k+2]).
@@ -75,8 +77,6 @@ struct StepDesc {
     const float *cov6;       // [M][6] scan point covariances (xx xy xz yy yz zz)
     float4 *scan_g;          // [3M] packed points: (mu, 0), (xx xy xz yy), (yz zz 0 0)
     float *hess;             // [21][N] H of the last pass (upper triangle, row-major)
-    const void *zero_rec;    // keyframe grid maps: one zero record (read by outside points
-                             // when the grids exceed one buffer's range)
     // Tail tiles (eval_tail_tiles).  Single grid: per (tile, sub-chunk,
     // particle) partial sums, [tail][kSubChunks][64] log sums and
     // [tail][kSubChunks][6][64].  Keyframe maps: tail_l is the base of the
@@ -94,7 +94,8 @@ struct StepDesc {
     // Evaluation order (null: slot s takes particle s): the particles grouped
     // by a coarse cell of their pose, recomputed each step after the
     // prediction.  order [N] (slot -> particle), ocell and orank [N], ocount
-    // [kOrderCells] (counts, then offsets), obounds [weight_blocks(N)][2 * 6].
+    // [kOrderCells] (counts, then offsets), obounds [weight_blocks(N)][2 * 6]
+    // (per-block ranges of the six coordinates).
     int32_t *order, *ocell, *orank, *ocount;
     float *obounds;
 };
@@ -102,8 +103,8 @@ struct StepDesc {
 constexpr int kTraceRows = 14;
 constexpr int kOrderDims = 6;
 constexpr int kOrderBits = 3;                                  // per coordinate
-constexpr int kOrderDrop = 2;                                  // low Morton bits dropped
-constexpr int kOrderCells = 1 << (kOrderDims * kOrderBits - kOrderDrop);   // 65536
+constexpr int kOrderDrop = 3;                                  // low Morton bits dropped
+constexpr int kOrderCells = 1 << (kOrderDims * kOrderBits - kOrderDrop);   // 32768
 // Sessions of at least this many particles evaluate in the grouped order.
 constexpr int kOrderMinParticles = 4096;
 
@@ -116,6 +117,15 @@ constexpr int kSubChunks = 32;
 constexpr size_t kTailBytesPerTile = (size_t)kSubChunks * 64 * (8 + 6 * 4);
 constexpr size_t kKfTailBytesPerTile =
     (size_t)(kKfMaxNb + 1) * 64 * 4 + (size_t)kSubChunks * kKfMaxNb * 64 * (8 + 6 * 4);
+
+// Cell records of a grid of nx x ny x nz samples: the (nx - 1)(ny - 1)(nz - 1)
+// cells and a zero layer around them, (nx + 1)(ny + 1)(nz + 1) in all.
+__host__ __device__ inline uint64_t grid_records(int nx, int ny, int nz)
+{
+    return (uint64_t)(nx + 1) * (uint64_t)(ny + 1) * (uint64_t)(nz + 1);
+}
+// Largest byte range of one buffer of records (32-bit offsets).
+constexpr uint32_t kMaxRecordBytes = 0xFFFFFFE0u;
 
 __host__ __device__ inline int weight_blocks(int N) { return (N + kWeightBlock - 1) / kWeightBlock; }
 __host__ __device__ inline int particle_tiles(int N) { return (N + kParticleTile - 1) / kParticleTile; }
@@ -143,6 +153,8 @@ bool eval_supported(const StepDesc &d);
 // Tiles of a single-grid session of N particles that the evaluation spreads
 // over one wave per sub-chunk (the last, partly filled round of tiles), or 0.
 int eval_tail_tiles(int N, int dtype, bool keyframes);
+// Single-grid evaluation tiles resident on the device at once (0 if unknown).
+int eval_round_tiles(int dtype);
 bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe);
 
 // Batched steps of many sessions (the serving path).  Work lists in device

@@ -330,24 +330,32 @@ __host__ __device__ __forceinline__ int sub_chunk_len(int M)
     return 4 * ((M + 4 * kSubChunks - 1) / (4 * kSubChunks));
 }
 
-// Grid constants of one evaluation loop.
+// Grid constants of one evaluation loop.  Records are laid out with a zero
+// layer around the cells (grid_records): record (I, J, K), 0 <= I <= nx and so
+// on, x fastest; the cell (i, j, k) of the samples is record (i + 1, j + 1,
+// k + 1), and records with an index 0 or n on some axis are zero.
 struct GridK {
     __amdgpu_buffer_rsrc_t rs;
     const char *gbase;       // 64-bit addressing: the grid's records
-    const char *zero;        // 64-bit addressing: a zero record, read by outside points
-    uint32_t nxm, nym, nzm;  // cells per axis (n - 1): valid cell indices are [0, n - 1)
-    uint32_t cx, cxy;        // record strides: cells per row and per slab
+    int32_t ixm, iym, izm;   // largest record index per axis (n)
+    uint32_t nxm, nym, nzm;  // cells per axis (n - 1): inside records have indices 1 .. n - 1
+    uint32_t cx, cxy;        // record strides: records per row and per slab
     float eps;
 };
 
-// Offset of a point outside the grid: beyond the buffer's range, so its
-// record loads return zeros (G = 0, dG = 0).  Record bytes are < 2^32 - 32.
-constexpr uint32_t kOutside = 0xFFFFFFE0u;
+__device__ __forceinline__ void grid_layout(const StepDesc &d, GridK &g)
+{
+    g.ixm = d.nx; g.iym = d.ny; g.izm = d.nz;
+    g.nxm = (uint32_t)(d.nx - 1); g.nym = (uint32_t)(d.ny - 1); g.nzm = (uint32_t)(d.nz - 1);
+    g.cx = (uint32_t)(d.nx + 1);
+    g.cxy = (uint32_t)(d.nx + 1) * (uint32_t)(d.ny + 1);
+    g.eps = d.eps;
+}
 
 // Cell fractions and record offset of a transformed point.
 struct Pt {
     float fx, fy, fz;      // position inside the cell
-    uint32_t off;          // byte offset of the cell record, kOutside when outside
+    uint32_t off;          // byte offset of the cell's record (a zero record when outside)
     bool inside;
 };
 
@@ -480,18 +488,27 @@ __device__ __forceinline__ void grid_map64(const float *t, const float *q, doubl
     rot_of_quat_d(w, x, y, z, R);
     const double ih = 1.0 / h;
     for (int e = 0; e < 9; ++e) m.A[e] = R[e] * ih;
-    m.b[0] = ((double)t[0] - ox) * ih - 0.5;
-    m.b[1] = ((double)t[1] - oy) * ih - 0.5;
-    m.b[2] = ((double)t[2] - oz) * ih - 0.5;
+    // u + 1 = (x - o)/h - 1/2 + 1: the record index of the zero-layer layout.
+    m.b[0] = ((double)t[0] - ox) * ih + 0.5;
+    m.b[1] = ((double)t[1] - oy) * ih + 0.5;
+    m.b[2] = ((double)t[2] - oz) * ih + 0.5;
     m.base = 0;
 }
 
 // floor(x) as int32 in one instruction (saturating for out-of-range x).
-__device__ __forceinline__ int cvt_floor_d(double x)
+// Conversion toward zero, saturating (NaN gives 0).
+__device__ __forceinline__ int cvt_trunc_d(double x)
 {
     int r;
-    const double f = floor(x);
-    asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(f));
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// v clamped to [0, hi] in one instruction (hi is wave-uniform).
+__device__ __forceinline__ int clamp_index(int v, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(v), "s"(hi));
     return r;
 }
 
@@ -502,19 +519,24 @@ __device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, 
 #pragma clang fp contract(off)
     Pt p;
     const double *A = gm.A;
+    // u + 1 per axis (the map's b carries the +1): for u + 1 >= 0 the
+    // truncation is the floor, so a point inside the grid (0 <= u < n - 1)
+    // takes record index floor(u) + 1 in [1, n - 1]; every other point, NaN
+    // included, lands in the zero layer (index 0 or n) after the clamp.
     const double ux = fma(A[0], px, fma(A[1], py, fma(A[2], pz, gm.b[0])));
     const double uy = fma(A[3], px, fma(A[4], py, fma(A[5], pz, gm.b[1])));
     const double uz = fma(A[6], px, fma(A[7], py, fma(A[8], pz, gm.b[2])));
-    const int ix = cvt_floor_d(ux), iy = cvt_floor_d(uy), iz = cvt_floor_d(uz);
+    const int ix = clamp_index(cvt_trunc_d(ux), g.ixm);
+    const int iy = clamp_index(cvt_trunc_d(uy), g.iym);
+    const int iz = clamp_index(cvt_trunc_d(uz), g.izm);
     p.fx = (float)__builtin_amdgcn_fract(ux);
     p.fy = (float)__builtin_amdgcn_fract(uy);
     p.fz = (float)__builtin_amdgcn_fract(uz);
-    p.inside = ((uint32_t)ix < g.nxm) & ((uint32_t)iy < g.nym) & ((uint32_t)iz < g.nzm);
+    p.inside = ((uint32_t)(ix - 1) < g.nxm) & ((uint32_t)(iy - 1) < g.nym) & ((uint32_t)(iz - 1) < g.nzm);
     const uint32_t rec = BIG ? (uint32_t)ix + g.cx * (uint32_t)iy + g.cxy * (uint32_t)iz
                              : (uint32_t)ix + __umul24(g.cx, (uint32_t)iy) +
                                    __umul24(g.cxy, (uint32_t)iz);
-    p.off = p.inside ? (KF ? gm.base + (rec << record_shift<DT>()) : (rec << record_shift<DT>()))
-                     : kOutside;
+    p.off = KF ? gm.base + (rec << record_shift<DT>()) : (rec << record_shift<DT>());
     return p;
 }
 
@@ -565,14 +587,13 @@ template <> __device__ __forceinline__ uint32_t cell_xor<2>(const Cell<2> &c)
     return c.a.x ^ c.a.y ^ c.a.z ^ c.a.w;
 }
 
-// Record of a prepared point: from the buffer (an outside point's offset lies
-// beyond its range and reads zeros) or, with GLB, through a 64-bit address
-// (an outside point reads the zero record).
+// Record of a prepared point: from the buffer or, with GLB, through a 64-bit
+// address (an outside point reads a record of the zero layer either way).
 template <int DT, bool GLB>
 __device__ __forceinline__ void fetch(const GridK &g, const Pt &p, Cell<DT> &c)
 {
     if (GLB)
-        load_cell_g<DT>(p.inside ? (uint64_t)(g.gbase + p.off) : (uint64_t)g.zero, c);
+        load_cell_g<DT>((uint64_t)(g.gbase + p.off), c);
     else
         load_cell<DT>(g.rs, p.off, c);
 }
@@ -775,14 +796,10 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
     if (wave == 0) load_tile_pose(d, i, lane, s_pose);
 
     GridK g;
-    const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
-    g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
-                                             (int)((cxn * cyn * czn) << record_shift<DT>()),
-                                             kRsrcWord3);
-    g.nxm = cxn; g.nym = cyn; g.nzm = czn;
-    g.cx = cxn;
-    g.cxy = cxn * cyn;
-    g.eps = d.eps;
+    grid_layout(d, g);
+    g.rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(d.cells), (short)0,
+        (int)((uint32_t)grid_records(d.nx, d.ny, d.nz) << record_shift<DT>()), kRsrcWord3);
     const int M = d.M;
     const int Q = sub_chunk_len(M);
     constexpr int S = kSubChunks / W;      // sub-chunks per wave
@@ -839,14 +856,10 @@ __device__ __forceinline__ void tail_chunk(const StepDesc &d, int tile0, int pas
     const int lane = threadIdx.x & 63;
     const int i = slot_particle(d, (tile0 + rel) * 64 + lane);
     GridK g;
-    const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
-    g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
-                                             (int)((cxn * cyn * czn) << record_shift<DT>()),
-                                             kRsrcWord3);
-    g.nxm = cxn; g.nym = cyn; g.nzm = czn;
-    g.cx = cxn;
-    g.cxy = cxn * cyn;
-    g.eps = d.eps;
+    grid_layout(d, g);
+    g.rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(d.cells), (short)0,
+        (int)((uint32_t)grid_records(d.nx, d.ny, d.nz) << record_shift<DT>()), kRsrcWord3);
     const int M = d.M, Q = sub_chunk_len(M);
     float t[3], q[4];
     tail_pose(d, i, pass, t, q);
@@ -1333,7 +1346,7 @@ __device__ __forceinline__ void kf_grid_map(const StepDesc &d, int k, int ic, co
             gm.A[3 * row + col] =
                 (Rk[row] * Rp[col] + Rk[3 + row] * Rp[3 + col] + Rk[6 + row] * Rp[6 + col]) * ih;
         const double tr = Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2];
-        gm.b[row] = (tr - (double)d.origins[3 * k + row]) * ih - 0.5;
+        gm.b[row] = (tr - (double)d.origins[3 * k + row]) * ih + 0.5;   // u + 1
     }
 }
 
@@ -1379,16 +1392,11 @@ __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
     const int i = tile * 64 + lane;
     const int ic = i < N ? i : N - 1;
     GridK g;
-    const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
+    grid_layout(d, g);
     g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
                                              GLB ? 0 : (int)((uint32_t)d.grid_stride * (uint32_t)d.K),
                                              kRsrcWord3);
     g.gbase = static_cast<const char *>(d.cells);
-    g.zero = static_cast<const char *>(d.zero_rec);
-    g.nxm = cxn; g.nym = cyn; g.nzm = czn;
-    g.cx = cxn;
-    g.cxy = cxn * cyn;
-    g.eps = d.eps;
     const double ih = 1.0 / (double)d.h;
 
     if (wave == 0) kf_select(d, i, lane, s_pose, s_nb, s_loop);
@@ -1484,16 +1492,11 @@ __device__ __forceinline__ void kf_tail_chunk(const StepDesc &d, int tile0, int 
     const int i = (tile0 + rel) * 64 + lane;
     const int ic = i < N ? i : N - 1;
     GridK g;
-    const uint32_t cxn = (uint32_t)(d.nx - 1), cyn = (uint32_t)(d.ny - 1), czn = (uint32_t)(d.nz - 1);
+    grid_layout(d, g);
     g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
                                              GLB ? 0 : (int)((uint32_t)d.grid_stride * (uint32_t)d.K),
                                              kRsrcWord3);
     g.gbase = static_cast<const char *>(d.cells);
-    g.zero = static_cast<const char *>(d.zero_rec);
-    g.nxm = cxn; g.nym = cyn; g.nzm = czn;
-    g.cx = cxn;
-    g.cxy = cxn * cyn;
-    g.eps = d.eps;
     const double ih = 1.0 / (double)d.h;
     const int M = d.M, Q = sub_chunk_len(M);
     float tf[3], qf[4];
@@ -1703,13 +1706,25 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
 __global__ void k_build_cells(const float *__restrict__ grid, void *__restrict__ cells, int nx,
                               int ny, int nz, int dtype)
 {
-    const int cxn = nx - 1, cyn = ny - 1, czn = nz - 1;
-    const size_t n_cells = (size_t)cxn * cyn * czn;
+    const size_t px = (size_t)nx + 1, py = (size_t)ny + 1;
+    const size_t n_rec = grid_records(nx, ny, nz);
     const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_cells) return;
-    const int i = (int)(r % cxn);
-    const int j = (int)((r / cxn) % cyn);
-    const int k = (int)(r / ((size_t)cxn * cyn));
+    if (r >= n_rec) return;
+    const int I = (int)(r % px);
+    const int J = (int)((r / px) % py);
+    const int Kz = (int)(r / (px * py));
+    if (I == 0 || I == nx || J == 0 || J == ny || Kz == 0 || Kz == nz) {
+        // The zero layer: what a point outside the grid reads.
+        if (dtype == 0) {
+            float4 *o = reinterpret_cast<float4 *>(cells) + 2 * r;
+            o[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            o[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        } else {
+            reinterpret_cast<uint4 *>(cells)[r] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        return;
+    }
+    const int i = I - 1, j = J - 1, k = Kz - 1;
     float c[8];
     for (int s = 0; s < 8; ++s) {
         const int a = s & 1, b = (s >> 1) & 1, cc = s >> 2;
@@ -2131,7 +2146,8 @@ __device__ __forceinline__ void order_coords(const StepDesc &d, int i, float c[k
 }
 
 // Per block: the low and high ends of each coordinate over its particles
-// (non-finite values are left out); the blocks also clear the cell counts.
+// (non-finite values are left out), written as the block's partial range;
+// the blocks also clear the cell counts.
 __device__ __forceinline__ void order_bounds_blk(const StepDesc &d, int b)
 {
     constexpr int B = kWeightBlock;
@@ -2163,8 +2179,9 @@ __device__ __forceinline__ void order_bounds_blk(const StepDesc &d, int b)
     for (int k = b * B + tid; k < kOrderCells; k += stride) d.ocount[k] = 0;
 }
 
-// Per particle: its cell (the cloud's range from all blocks' bounds) and its
-// rank among the particles of that cell.
+// Per particle: its cell (over the cloud's range, from all blocks' partial
+// ranges) and its rank among the particles of that cell.  The lanes of a
+// wave that share a cell take their ranks from one atomic add.
 __device__ __forceinline__ void order_cell_blk(const StepDesc &d, int b)
 {
     constexpr int B = kWeightBlock;
@@ -2198,36 +2215,64 @@ __device__ __forceinline__ void order_cell_blk(const StepDesc &d, int b)
     }
     __syncthreads();
     const int i = b * B + tid;
-    if (i >= d.N) return;
-    float c[kOrderDims];
-    order_coords(d, i, c);
-    int q[kOrderDims];
-    for (int k = 0; k < kOrderDims; ++k) {
-        const float v = (c[k] - base[k]) * scale[k];
-        q[k] = (v >= 0.0f) ? min((int)v, (1 << kOrderBits) - 1) : 0;   // NaN and below: cell 0
+    const bool valid = i < d.N;
+    int cell = -1;
+    if (valid) {
+        float c[kOrderDims];
+        order_coords(d, i, c);
+        int q[kOrderDims];
+        for (int k = 0; k < kOrderDims; ++k) {
+            const float v = (c[k] - base[k]) * scale[k];
+            q[k] = (v >= 0.0f) ? min((int)v, (1 << kOrderBits) - 1) : 0;   // NaN and below: part 0
+        }
+        int code = 0;
+        for (int bit = kOrderBits - 1; bit >= 0; --bit)
+            for (int k = 0; k < kOrderDims; ++k) code = (code << 1) | ((q[k] >> bit) & 1);
+        cell = code >> kOrderDrop;
     }
-    int code = 0;
-    for (int bit = kOrderBits - 1; bit >= 0; --bit)
-        for (int k = 0; k < kOrderDims; ++k) code = (code << 1) | ((q[k] >> bit) & 1);
-    const int cell = code >> kOrderDrop;
-    d.ocell[i] = cell;
-    d.orank[i] = __hip_atomic_fetch_add(d.ocount + cell, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // One atomic add per distinct cell of the wave; every lane of that cell
+    // takes its rank from the lanes below it.
+    const int lane = __lane_id();
+    uint64_t todo = __ballot(valid);
+    int rank = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int c = __shfl(cell, leader);
+        const uint64_t same = __ballot(cell == c);
+        int first = 0;
+        if (lane == leader)
+            first = __hip_atomic_fetch_add(d.ocount + c, (int)__popcll(same), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+        first = __shfl(first, leader);
+        if (cell == c) rank = first + (int)__popcll(same & ((1ull << lane) - 1ull));
+        todo &= ~same;
+    }
+    if (valid) {
+        d.ocell[i] = cell;
+        d.orank[i] = rank;
+    }
 }
 
 // One block of kOrderPrefixBlock threads: exclusive prefix of the cell
-// counts, in place.
+// counts, in place, through LDS (coalesced loads and stores; each thread
+// scans a contiguous run of cells, the run totals are scanned across the
+// block).
 constexpr int kOrderPrefixBlock = 1024;
 __device__ __forceinline__ void order_prefix_blk(const StepDesc &d)
 {
     constexpr int B = kOrderPrefixBlock;
     constexpr int per = kOrderCells / B;
+    constexpr int pad = per + 1;                 // LDS row stride (bank spread)
+    __shared__ int cnt[B * pad];
     __shared__ int sh[2][B];
     const int tid = threadIdx.x;
-    int v[per], sum = 0;
     for (int k = 0; k < per; ++k) {
-        v[k] = d.ocount[tid * per + k];
-        sum += v[k];
+        const int e = k * B + tid;               // coalesced in global memory
+        cnt[(e / per) * pad + e % per] = d.ocount[e];
     }
+    __syncthreads();
+    int sum = 0;
+    for (int k = 0; k < per; ++k) sum += cnt[tid * pad + k];
     int cur = 0;
     sh[cur][tid] = sum;
     __syncthreads();
@@ -2237,10 +2282,16 @@ __device__ __forceinline__ void order_prefix_blk(const StepDesc &d)
         cur ^= 1;
         __syncthreads();
     }
-    int run = sh[cur][tid] - sum;              // exclusive prefix of this thread's cells
+    int run = sh[cur][tid] - sum;                // exclusive prefix of this thread's cells
     for (int k = 0; k < per; ++k) {
-        d.ocount[tid * per + k] = run;
-        run += v[k];
+        const int v = cnt[tid * pad + k];
+        cnt[tid * pad + k] = run;
+        run += v;
+    }
+    __syncthreads();
+    for (int k = 0; k < per; ++k) {
+        const int e = k * B + tid;
+        d.ocount[e] = cnt[(e / per) * pad + e % per];
     }
 }
 
@@ -2388,7 +2439,7 @@ constexpr int kGicpW = 8;
 hipError_t launch_build_cells(const float *grid, void *cells, int nx, int ny, int nz, int dtype,
                               hipStream_t st)
 {
-    const size_t n = (size_t)(nx - 1) * (ny - 1) * (nz - 1);
+    const size_t n = grid_records(nx, ny, nz);
     const size_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_build_cells, dim3((unsigned)blocks), dim3(256), 0, st, grid, cells, nx,
                        ny, nz, dtype);
@@ -2404,16 +2455,16 @@ hipError_t launch_pack_predict(const StepDesc &d, hipStream_t st)
 
 static bool big_slab(const StepDesc &d)
 {
-    return (uint64_t)(d.nx - 1) >= (1u << 24) || (uint64_t)(d.nx - 1) * (d.ny - 1) >= (1u << 24);
+    return (uint64_t)(d.nx + 1) >= (1u << 24) || (uint64_t)(d.nx + 1) * (d.ny + 1) >= (1u << 24);
 }
 
-// One grid's records must fit a 32-bit byte offset (below the outside
-// sentinel); keyframe grids also take the 24-bit index products.
+// One grid's records must fit a 32-bit byte range (kMaxRecordBytes); keyframe
+// grids also take the 24-bit index products.
 bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe)
 {
-    const uint64_t n_rec = (uint64_t)(nx - 1) * (ny - 1) * (nz - 1);
-    const bool slab = (uint64_t)(nx - 1) >= (1u << 24) || (uint64_t)(nx - 1) * (ny - 1) >= (1u << 24);
-    return (n_rec << (dtype == 0 ? 5 : 4)) <= (uint64_t)kOutside && !(keyframe && slab);
+    const uint64_t n_rec = grid_records(nx, ny, nz);
+    const bool slab = (uint64_t)(nx + 1) >= (1u << 24) || (uint64_t)(nx + 1) * (ny + 1) >= (1u << 24);
+    return (n_rec << (dtype == 0 ? 5 : 4)) <= (uint64_t)kMaxRecordBytes && !(keyframe && slab);
 }
 
 // Tiles of the evaluation kernel (single grid, or keyframe map) resident on
@@ -2456,6 +2507,13 @@ static void eval_round(int dtype, bool kf, int &round, int &cus)
     cache[{dev, key}] = {round, cus};
 }
 
+int eval_round_tiles(int dtype)
+{
+    int round = 0, cus = 0;
+    eval_round(dtype, false, round, cus);
+    return round;
+}
+
 // A launch of at least one full round leaves its tiles unevenly spread over
 // the compute units when the count is not a multiple of their number: the
 // remainder is split when it is at most a quarter of the units.  A single-grid
@@ -2490,7 +2548,7 @@ static hipError_t launch_eval_dt(const StepDesc &d, hipStream_t st, const TailAu
         // One buffer can address all keyframe grids when they fit its 32-bit
         // range; larger maps are read through 64-bit addresses.  As for single
         // grids, a small last round of tiles runs as one wave per sub-chunk.
-        const bool one_buffer = (uint64_t)d.grid_stride * (uint64_t)d.K <= (uint64_t)kOutside;
+        const bool one_buffer = (uint64_t)d.grid_stride * (uint64_t)d.K <= (uint64_t)kMaxRecordBytes;
         const int tail = d.tail_l ? min(d.tail_tiles, particle_tiles(d.N)) : 0;
         const unsigned main_tiles = blocks - (unsigned)tail;
         const bool fork = tail > 0 && main_tiles > 0 && aux != nullptr;

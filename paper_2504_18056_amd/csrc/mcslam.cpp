@@ -121,7 +121,7 @@ mcs_status validate_desc(const mcs_grid_desc *d)
         if (!std::isfinite(d->origin[a])) return fail(MCS_EINVAL, "grid origin not finite");
     if (d->dtype < MCS_GRID_FP32 || d->dtype > MCS_GRID_BF16)
         return fail(MCS_EINVAL, "unknown grid dtype %d", d->dtype);
-    const double cells = (double)(d->nx - 1) * (d->ny - 1) * (d->nz - 1);
+    const double cells = (double)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
     if (cells >= 2147483647.0) return fail(MCS_EINVAL, "grid has too many cells (%.0f)", cells);
     if (d->nx > (1 << 24) || d->ny > (1 << 24) || d->nz > (1 << 24))
         return fail(MCS_EINVAL, "grid axis too long");
@@ -147,10 +147,10 @@ mcs_status build_map(mcs_ctx *ctx, int K, const mcs_grid_desc *descs, const floa
         const mcs_status s = check_samples(values[k], samples, k);
         if (s != MCS_OK) return s;
     }
-    const int64_t recs = (int64_t)(d0.nx - 1) * (d0.ny - 1) * (d0.nz - 1);
+    const int64_t recs = (int64_t)grid_records(d0.nx, d0.ny, d0.nz);
     const size_t grid_bytes = (size_t)recs * record_bytes(d0.dtype);
     const int G = K > 0 ? K : 1;
-    const size_t total = align_up(grid_bytes) * G + align_up((size_t)G * 3 * sizeof(float)) + kZeroBytes;
+    const size_t total = align_up(grid_bytes) * G + align_up((size_t)G * 3 * sizeof(float));
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (!budget_allows(ctx, total))
@@ -176,9 +176,6 @@ mcs_status build_map(mcs_ctx *ctx, int K, const mcs_grid_desc *descs, const floa
     hipError_t e = hipMalloc(&m->cells, total);
     if (e != hipSuccess) { m->cells = nullptr; return undo(hip_fail(e, "hipMalloc(map)")); }
     m->origins_dev = reinterpret_cast<float *>((char *)m->cells + align_up(grid_bytes) * G);
-    m->zero_rec = (char *)m->origins_dev + align_up((size_t)G * 3 * sizeof(float));
-    e = hipMemset(m->zero_rec, 0, kZeroBytes);
-    if (e != hipSuccess) return undo(hip_fail(e, "hipMemset(zero record)"));
     float *tmp = nullptr;
     e = hipMalloc(&tmp, samples * sizeof(float));
     if (e != hipSuccess) return undo(hip_fail(e, "hipMalloc(grid staging)"));
@@ -317,7 +314,6 @@ StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float 
     d.scan_g = s->scan_g;
     d.hess = s->hess;
     d.origins = m->origins_dev;
-    d.zero_rec = m->zero_rec;
     d.tail_l = s->tail_l;
     d.tail_g = s->tail_g;
     d.tail_tiles = s->tail_tiles;
@@ -608,10 +604,10 @@ mcs_status mcs_create_keyframe_map(mcs_ctx *ctx, int32_t K_cap, const mcs_grid_d
     if (!grid_supported(desc->nx, desc->ny, desc->nz, desc->dtype, true))
         return fail(MCS_EINVAL, "keyframe grid too large (32-bit record offsets, 24-bit row and slab products)");
     if ((s = set_device(ctx)) != MCS_OK) return s;
-    const int64_t recs = (int64_t)(desc->nx - 1) * (desc->ny - 1) * (desc->nz - 1);
+    const int64_t recs = (int64_t)grid_records(desc->nx, desc->ny, desc->nz);
     const size_t grid_bytes = (size_t)recs * record_bytes(desc->dtype);
     const size_t total =
-        align_up(grid_bytes) * K_cap + align_up((size_t)K_cap * 3 * sizeof(float)) + kZeroBytes;
+        align_up(grid_bytes) * K_cap + align_up((size_t)K_cap * 3 * sizeof(float));
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (!budget_allows(ctx, total))
@@ -635,15 +631,6 @@ mcs_status mcs_create_keyframe_map(mcs_ctx *ctx, int32_t K_cap, const mcs_grid_d
         return hip_fail(e, "hipMalloc(map)");
     }
     m->origins_dev = reinterpret_cast<float *>((char *)m->cells + align_up(grid_bytes) * K_cap);
-    m->zero_rec = (char *)m->origins_dev + align_up((size_t)K_cap * 3 * sizeof(float));
-    e = hipMemset(m->zero_rec, 0, kZeroBytes);
-    if (e != hipSuccess) {
-        (void)hipFree(m->cells);
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->in_use -= total;
-        delete m;
-        return hip_fail(e, "hipMemset(zero record)");
-    }
     std::lock_guard<std::mutex> lk(ctx->mu);
     m->id = ctx->next_id++;
     ctx->maps[m->id] = m;

@@ -1,11 +1,15 @@
 // Serving: a request loop that runs the frames of many concurrent sessions.
 //
-// BATCHED mode forms ticks of at most one pending frame per session, writes
-// one compact table of step descriptors and per-stage work items into pinned
-// host memory, copies it to the device in one transfer and replays a HIP
-// graph of persistent kernels captured once per table buffer.  Two table
-// buffers alternate so a tick can be prepared and queued while the previous
-// one runs.  CONCURRENT mode launches every request as soon as it arrives on
+// BATCHED mode serves two lanes side by side.  Frames of sessions large
+// enough to fill the device on their own (a round of evaluation tiles) are
+// launched as they arrive with the per-session launches on the session's own
+// stream, so they overlap each other and the ticks.  Frames of smaller sessions form ticks: the oldest pending
+// frame, then the smallest frames of other sessions (at most one per session)
+// while the tick's work stays under a cap; a tick writes one compact table of
+// step descriptors and per-stage work items into pinned host memory, copies
+// it to the device in one transfer and replays a HIP graph of persistent
+// kernels captured once per table buffer.  Two table buffers alternate so a
+// tick can be prepared and queued while the previous one runs.  CONCURRENT mode launches every request as soon as it arrives on
 // its session's own stream, so frames of different sessions overlap on the
 // device without a tick boundary.  SERIAL mode runs one request at a time
 // with the per-session launches and waits for it.
@@ -14,8 +18,10 @@
 // the work in flight and retires requests as soon as their work is done.
 #include "state.h"
 
+#include <algorithm>
 #include <array>
 #include <chrono>
+#include <climits>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -43,6 +49,7 @@ struct Request {
     mcs_step_params p;
     mcs_request_times t;
     int64_t evals;
+    bool big;                         // BATCHED mode: runs in the large-session lane
 };
 
 // One table buffer of BATCHED mode.  Device and pinned host images share one
@@ -82,6 +89,12 @@ struct mcs_server {
     hipStream_t stream = nullptr;     // SERIAL mode
     TableBuf buf[2];
     int next_buf = 0;
+    // BATCHED mode, large-session lane: sessions of at least big_tiles
+    // evaluation tiles; each frame launched on its session's stream as soon
+    // as it arrives (tracked with the in-flight events).
+    int big_tiles = 0;
+    int64_t tick_cap = 0;             // evaluations per tick (its first frame always fits)
+    std::deque<int64_t> pending_big;
     std::deque<InFlight> inflight;    // CONCURRENT mode, launch order
     std::vector<hipEvent_t> ev_free;
     std::vector<hipEvent_t> ev_all;
@@ -168,17 +181,36 @@ void retire(mcs_server *s, int64_t id, int64_t t, bool ok)
 // entry; released while touching the device).  Returns false if nothing ran.
 bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b, TableBuf &other)
 {
-    // Pick at most one pending frame per session, oldest first.
-    std::vector<int64_t> take;
-    std::unordered_set<int32_t> seen;
-    for (auto it = s->pending.begin(); it != s->pending.end() && (int)take.size() < s->max_batch;) {
-        const Request &r = s->reqs[*it];
-        if (seen.count(r.session_id)) { ++it; continue; }
-        seen.insert(r.session_id);
-        take.push_back(*it);
-        it = s->pending.erase(it);
+    // The oldest pending frame, then the smallest frames of other sessions
+    // (each session's oldest) while the tick's evaluations stay under the cap.
+    std::vector<int64_t> heads;
+    {
+        std::unordered_set<int32_t> seen;
+        for (int64_t id : s->pending) {
+            const Request &r = s->reqs[id];
+            if (seen.insert(r.session_id).second) heads.push_back(id);
+        }
     }
-    if (take.empty()) return false;
+    if (heads.empty()) return false;
+    std::vector<int64_t> take = {heads[0]};
+    int64_t work = s->reqs[heads[0]].evals;
+    std::vector<int64_t> rest(heads.begin() + 1, heads.end());
+    std::stable_sort(rest.begin(), rest.end(),
+                     [&](int64_t a, int64_t b) { return s->reqs[a].evals < s->reqs[b].evals; });
+    for (int64_t id : rest) {
+        if ((int)take.size() >= s->max_batch) break;
+        const int64_t w = s->reqs[id].evals;
+        if (work + w > s->tick_cap) break;
+        take.push_back(id);
+        work += w;
+    }
+    {
+        std::unordered_set<int64_t> taken(take.begin(), take.end());
+        std::deque<int64_t> keep;
+        for (int64_t id : s->pending)
+            if (!taken.count(id)) keep.push_back(id);
+        s->pending.swap(keep);
+    }
     std::vector<Request> rq;
     for (int64_t id : take) rq.push_back(s->reqs[id]);
     // A session still running in the other buffer's tick orders this tick
@@ -267,11 +299,12 @@ bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b, T
     return true;
 }
 
-// CONCURRENT mode: launch the oldest pending request on its session's stream.
-void launch_concurrent(mcs_server *s, std::unique_lock<std::mutex> &lk)
+// CONCURRENT mode (and BATCHED mode's large-session lane): launch the oldest
+// request of `queue` on its session's stream.
+void launch_concurrent(mcs_server *s, std::unique_lock<std::mutex> &lk, std::deque<int64_t> &queue)
 {
-    const int64_t id = s->pending.front();
-    s->pending.pop_front();
+    const int64_t id = queue.front();
+    queue.pop_front();
     const Request r = s->reqs[id];
     hipEvent_t ev = s->ev_free.back();
     s->ev_free.pop_back();
@@ -331,8 +364,10 @@ void run_serial(mcs_server *s, std::unique_lock<std::mutex> &lk)
 
 bool can_launch(const mcs_server *s)
 {
+    if (s->mode == MCS_SERVE_BATCHED)
+        return (!s->pending.empty() && !s->buf[s->next_buf].busy) ||
+               (!s->pending_big.empty() && !s->ev_free.empty());
     if (s->pending.empty()) return false;
-    if (s->mode == MCS_SERVE_BATCHED) return !s->buf[s->next_buf].busy;
     if (s->mode == MCS_SERVE_CONCURRENT) return !s->ev_free.empty();
     return true;
 }
@@ -343,14 +378,16 @@ void worker_main(mcs_server *s)
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         if (!can_launch(s)) {
-            if (s->stop && s->pending.empty()) break;
+            if (s->stop && s->pending.empty() && s->pending_big.empty()) break;
             s->cv_work.wait(lk);
             continue;
         }
         if (s->mode == MCS_SERVE_SERIAL) {
             run_serial(s, lk);
         } else if (s->mode == MCS_SERVE_CONCURRENT) {
-            launch_concurrent(s, lk);
+            launch_concurrent(s, lk, s->pending);
+        } else if (!s->pending_big.empty() && !s->ev_free.empty()) {
+            launch_concurrent(s, lk, s->pending_big);
         } else {
             TableBuf &nb = s->buf[s->next_buf];
             if (launch_tick(s, lk, nb, s->buf[s->next_buf ^ 1])) s->next_buf ^= 1;
@@ -375,6 +412,7 @@ void completer_main(mcs_server *s)
         std::vector<std::pair<int, hipEvent_t>> q;
         for (int k = 0; k < 2; ++k)
             if (s->buf[k].busy) q.emplace_back(k, s->buf[k].done);
+
         for (size_t k = 0; k < s->inflight.size(); ++k) q.emplace_back(-1 - (int)k, s->inflight[k].ev);
         lk.unlock();
         std::vector<std::pair<int, hipError_t>> ready;
@@ -462,13 +500,19 @@ mcs_status mcs_server_create(mcs_ctx *ctx, int32_t mode, int32_t dtype, int32_t 
         return hip_fail(e, "hipStreamCreate");
     }
     if (mode == MCS_SERVE_BATCHED) {
+        // One round of evaluation tiles (0 if the device cannot be queried:
+        // then every session goes through the ticks).  A tick holds at most a
+        // round's worth of work at 2,048 points and 3 passes.
+        s->big_tiles = eval_round_tiles(dtype);
+        s->tick_cap = s->big_tiles > 0 ? (int64_t)s->big_tiles * kParticleTile * 2048 * 3 : INT64_MAX;
         for (auto &b : s->buf) {
             if ((st = alloc_tables(s, b)) != MCS_OK) {
                 destroy_server(s);
                 return st;
             }
         }
-    } else if (mode == MCS_SERVE_CONCURRENT) {
+    }
+    if (mode == MCS_SERVE_CONCURRENT || mode == MCS_SERVE_BATCHED) {
         for (int k = 0; k < kMaxInFlight; ++k) {
             hipEvent_t ev;
             if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
@@ -531,8 +575,10 @@ mcs_status mcs_server_submit(mcs_server *s, int32_t sid, const float *scan_dev, 
         return fail(MCS_EINVAL, "out-of-grid rule differs from the server's");
     StepDesc probe = make_desc(ss, scan_dev, M, noise_dev, p);
     if (!eval_supported(probe)) return fail(MCS_EINVAL, "map not supported");
-    if (particle_tiles(ss->N) > s->max_items || weight_blocks(ss->N) > s->max_items ||
-        scan_blocks(M) > s->max_items)
+    const bool big = s->mode == MCS_SERVE_BATCHED && s->big_tiles > 0 &&
+                     particle_tiles(ss->N) >= s->big_tiles;
+    if (!big && (particle_tiles(ss->N) > s->max_items || weight_blocks(ss->N) > s->max_items ||
+                 scan_blocks(M) > s->max_items))
         return fail(MCS_EINVAL, "session work exceeds the server's per-tick work lists");
     Request r{};
     r.session_id = sid;
@@ -544,11 +590,12 @@ mcs_status mcs_server_submit(mcs_server *s, int32_t sid, const float *scan_dev, 
     r.t.submit_ns = now_ns();
     r.t.tick = -1;
     r.evals = (int64_t)ss->N * M * (p->iters + (p->post_eval ? 1 : 0));
+    r.big = big;
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return fail(MCS_EBUSY, "server is stopping");
     r.id = s->next_id++;
     s->reqs[r.id] = r;
-    s->pending.push_back(r.id);
+    (big ? s->pending_big : s->pending).push_back(r.id);
     s->submitted++;
     *request_id = r.id;
     s->cv_work.notify_one();

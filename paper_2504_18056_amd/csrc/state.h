@@ -26,7 +26,6 @@ constexpr int kMaxNeighbors = 8;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 inline size_t record_bytes(int dtype) { return dtype == MCS_GRID_FP32 ? 32 : 16; }
-constexpr size_t kZeroBytes = 256;
 
 enum MapKind { kGridMap = 0, kVoxelMap = 1 };
 constexpr size_t kVoxelRecordBytes = 48;   // mean (3), count, covariance (6), 2 unused
@@ -42,7 +41,6 @@ struct Map {
     size_t bytes = 0;
     int64_t records = 0;             // per grid (cells or voxels)
     float *origins_dev = nullptr;
-    void *zero_rec = nullptr;        // grid maps: one zero record (kZeroBytes) after the origins
     int users = 0;
 };
 
