@@ -686,6 +686,17 @@ def main():
                                   c["poses"], np.full(N, -math.log(N)))
     floors_spread["state"] = "the initial spread (0.5 m, 5 deg), frame %d's scan" % frames[0]
     log("gather floor: converged %s; initial spread %s" % (floors_conv, floors_spread))
+    # The same scan visited ring by ring instead of in firing order: the
+    # evaluation follows the given point order, whose locality reaches the caches.
+    rings = 32
+    ring_major = np.arange(M).reshape(M // rings, rings).T.reshape(-1)
+    scan_rm = torch.from_numpy(np.ascontiguousarray(c["scans"][f_last][ring_major])).to(dev)
+    rm = eval_vs_floor(abi, torch, ctx, sid, scan_rm.data_ptr(), M, pf, st["poses"], st["logw"])
+    scan_order = {"firing_order_eval_ms": floors_conv["eval_ms"], "ring_major_eval_ms": rm["eval_ms"],
+                  "note": "the converged cloud's evaluation stage with frame %d's points in the "
+                          "sensor's firing order (every ring at one azimuth, then the next) and "
+                          "ring by ring" % f_last}
+    log("scan order: %s" % scan_order)
     trajectory = run_trajectory(abi, torch, ctx, mid, c, base)
     log("trajectory: %s" % trajectory)
     abi.mcs_destroy(ctx)
@@ -787,6 +798,7 @@ def main():
         "stage_ms": stage_ms,
         "gather_floor_initial_spread": floors_spread,
         "trajectory_200_frames": trajectory,
+        "scan_order": scan_order,
         "eval_ms_first_frame_initial_spread": round(first_eval_ms, 4),
         "eval_ms_initial_spread_second_time": round(spread_eval_ms, 4),
         "trilinear_samples_per_s": round(value, 1),

@@ -21,7 +21,8 @@ the FP64 oracle finishes in seconds):
 * ``serving``    -- many concurrent sessions with their own maps, particle
   counts and scan sizes.
 
-Scans are ordered ring by azimuth.  Particles start from a Gaussian around the
+Scans come in a spinning LiDAR's firing order (all rings at one azimuth, then
+the next azimuth).  Particles start from a Gaussian around the
 true pose: translation N(0, 0.5^2 I) m per axis and a body-frame rotation
 vector N(0, (5 deg)^2 I).
 """
@@ -49,9 +50,12 @@ def f32(x):
     return float(np.float32(x))
 
 
-def lidar_scan(scene, t, q, elevations_deg, n_az, rmax, noise_sigma, rng, el_range=None):
-    """Ray-cast a ring-by-azimuth scan from pose (t, q); returns (M, 3) FP32, sensor frame.
+def lidar_scan(scene, t, q, elevations_deg, n_az, rmax, noise_sigma, rng, el_range=None,
+               column_major=True):
+    """Ray-cast a scan of rings x azimuths from pose (t, q); returns (M, 3) FP32, sensor frame.
 
+    Points come in the firing order of a spinning LiDAR: every ring at one
+    azimuth, then the next azimuth (column_major=False: ring by ring).
     Rays that miss (nothing within ``rmax`` inside the volume) are re-drawn in
     place from a seeded stream of directions with uniform azimuth and uniform
     elevation in ``el_range``, so the scan always has exactly
@@ -61,6 +65,8 @@ def lidar_scan(scene, t, q, elevations_deg, n_az, rmax, noise_sigma, rng, el_ran
     els = np.radians(np.asarray(elevations_deg, dtype=np.float64))
     az = 2.0 * np.pi * np.arange(n_az) / n_az
     E, A = np.meshgrid(els, az, indexing="ij")
+    if column_major:
+        E, A = E.T, A.T
     E, A = E.reshape(-1), A.reshape(-1)
     if el_range is None:
         el_range = (els.min(), els.max())

@@ -42,6 +42,15 @@ def ctx():
     abi.mcs_destroy(c)
 
 
+def assert_few_ambiguous(rep, M):
+    """Points within DELTA of a cell face (where the two sides' cell choices may
+    differ; the oracle's allowance covers them) must stay as rare as the FP64
+    transforms' agreement makes them: a window of 2e-9 index units per axis
+    holds about 6e-9 of the points.  A mismatch of the transforms themselves
+    (an input or pose difference) puts thousands of points there."""
+    assert rep["n_amb"] <= 2 + 1e-6 * rep["n"] * M, rep
+
+
 def passes_of(p):
     return int(p["iters"]) + int(bool(p.get("post_eval", False)))
 
@@ -149,7 +158,7 @@ def test_every_pass_of_a_fused_step(ctx, case):
     res = check_output(out, tr, p, idx, np.full(N, -math.log(N)), p["beta"], p["u"], p["resample"])
     print("%s: per pass %s; ess %.2f ties %d" % (case, reports, res["ess"], res["ties"]))
     for r in reports:
-        assert r["n_amb"] == 0
+        assert_few_ambiguous(r, M=scan.shape[0])
 
 
 def test_corridors_benchmark_configuration_every_pass(ctx):
@@ -187,7 +196,7 @@ def test_corridors_benchmark_configuration_every_pass(ctx):
             print("corridors frame %d: per pass %s; ess %.1f resampled %s ties %d" % (
                 f, reports, res["ess"], out["stats"]["resampled"], res["ties"]), flush=True)
             for r in reports:
-                assert r["n_amb"] == 0
+                assert_few_ambiguous(r, M=M)
     finally:
         abi.mcs_session_destroy(ctx, sid)
         abi.mcs_release_map(ctx, mid)
@@ -224,7 +233,7 @@ def test_keyframe_map_every_pass(ctx):
         rep = {}
         check_eval(tr[k]["loglik"], tr[k]["grad"], ref, report=rep)
         print("keyframes pass %d: %s" % (k, rep))
-        assert rep["n_amb"] == 0
+        assert_few_ambiguous(rep, M=c["scan"].shape[0] * p["n_neighbors"])
         if k < 2:
             check_step(tr[k]["poses"], tr[k]["grad"], tr[k + 1]["poses"], p)
     check_output(out, tr, p, idx, c["logw"], 0.01, p["u"], abi.RESAMPLE_ALWAYS)
