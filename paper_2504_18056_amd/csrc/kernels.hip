@@ -2317,10 +2317,23 @@ __global__ __launch_bounds__(kWeightBlock) void k_pack_predict(StepDesc d)
         predict_blk(d, blockIdx.x - ns);
 }
 
+// The dispatcher hands workgroups to the eight XCDs in turn (workgroup b to
+// XCD b % 8), and each XCD has its own L2.  This maps workgroup b of a grid of
+// n to a tile so that each XCD works through one contiguous run of tiles:
+// particles that are neighbours in the evaluation order (similar poses, so
+// overlapping cells) then share an L2 instead of being spread over all eight.
+// A bijection on [0, n) for any n; only the cache behaviour depends on the
+// dispatch order.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 template <int DT, bool BIG, bool SKIP, int W, bool FLOOR = false>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_eval(StepDesc d)
 {
-    eval_tile<DT, BIG, SKIP, W, FLOOR>(d, blockIdx.x);
+    eval_tile<DT, BIG, SKIP, W, FLOOR>(d, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Eight waves per block, one sub-chunk each: block b covers tail tile
@@ -2346,7 +2359,7 @@ __global__ __launch_bounds__(64) void k_eval_tail_step(StepDesc d, int tile0, in
 template <int DT, bool SKIP, int W, bool GLB>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_kf_eval(StepDesc d)
 {
-    kf_tile_buf<DT, SKIP, W, GLB>(d, blockIdx.x);
+    kf_tile_buf<DT, SKIP, W, GLB>(d, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 __global__ __launch_bounds__(64) void k_kf_tail_select(StepDesc d, int tile0)
@@ -2375,7 +2388,7 @@ __global__ __launch_bounds__(64 * W) void k_kf_tail_step(StepDesc d, int tile0, 
 template <int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_gicp_eval(StepDesc d)
 {
-    gicp_tile<W>(d, blockIdx.x);
+    gicp_tile<W>(d, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 __global__ __launch_bounds__(kWeightBlock) void k_weights(StepDesc d) { weights_blk(d, blockIdx.x); }
