@@ -736,8 +736,11 @@ __device__ __forceinline__ void tile_epilogue(const StepDesc &d, int i, int lane
     const int N = d.N;
     const bool stepping = pass < d.iters;
     if (i < N) {
-        d.loglik[i] = (float)(l * kLn2);
-        if (stepping)
+        // Only the last pass's log-likelihood and the last step's gradient are
+        // outputs; earlier passes' would be overwritten (and, with the
+        // evaluation order, scattered writes cost a partial line each).
+        if (pass == d.iters + d.post_eval - 1) d.loglik[i] = (float)(l * kLn2);
+        if (pass == d.iters - 1)
             for (int c = 0; c < 6; ++c) d.grad[c * N + i] = gr[c];
         if (d.trace) {
             float *tr = d.trace + (size_t)pass * kTraceRows * N + i;
@@ -1112,26 +1115,41 @@ __device__ __forceinline__ bool gn_solve(const float h[21], const float b[6], fl
 typedef const __attribute__((address_space(4))) f4v *gscan_ptr;
 
 // One (particle, point, keyframe) term of Eq. 3-6 in the scan's frame:
-// x = R' mu + t' (FP64) selects the voxel; e = mu_v - x; with R'^T the
+// x = R' mu + t' (FP64) selects the voxel, taken in voxel units as
+// y = (R'/vs) mu + ((t' - o)/vs + 1) and x = y vs + (o - vs); e = mu_v - x; with R'^T the
 // rotation back, e_s = R'^T e, Omega_s = (R'^T S_v R' + Sigma)^-1 (FP64
 // inverse), w = Omega_s e_s; l -= e_s^T w; b += J_s^T w and
 // H += J_s^T Omega_s J_s with J_s = [-I, [mu]x].
 typedef const __attribute__((address_space(1))) f4v *gf4_ptr;
 
-__device__ __forceinline__ void gicp_point(const double R[9], const float Rf[9], const double t[3],
-                                           const double o[3], double inv_vs, int nx, int ny, int nz,
+// 1/x for a positive normal x: the hardware's reciprocal estimate refined by
+// two Newton steps, each of which roughly doubles its correct bits (to about
+// one ulp; IEEE division's scaling and fix-up steps are not needed here).
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ void gicp_point(const double Rs[9], const float Rf[9], const double ts[3],
+                                           const double ob[3], double vs, int nx, int ny, int nz,
                                            uint64_t vbase, const f4v p4, const f4v c4a, const f4v c4b,
                                            double &l, float acc[27])
 {
-    const double x0 = fma(R[0], (double)p4.x, fma(R[1], (double)p4.y, fma(R[2], (double)p4.z, t[0])));
-    const double x1 = fma(R[3], (double)p4.x, fma(R[4], (double)p4.y, fma(R[5], (double)p4.z, t[1])));
-    const double x2 = fma(R[6], (double)p4.x, fma(R[7], (double)p4.y, fma(R[8], (double)p4.z, t[2])));
-    const double u0 = floor((x0 - o[0]) * inv_vs), u1 = floor((x1 - o[1]) * inv_vs),
-                 u2 = floor((x2 - o[2]) * inv_vs);
-    if (!(u0 >= 0.0 && u0 < (double)nx && u1 >= 0.0 && u1 < (double)ny && u2 >= 0.0 && u2 < (double)nz))
-        return;
+    const double y0 = fma(Rs[0], (double)p4.x, fma(Rs[1], (double)p4.y, fma(Rs[2], (double)p4.z, ts[0])));
+    const double y1 = fma(Rs[3], (double)p4.x, fma(Rs[4], (double)p4.y, fma(Rs[5], (double)p4.z, ts[1])));
+    const double y2 = fma(Rs[6], (double)p4.x, fma(Rs[7], (double)p4.y, fma(Rs[8], (double)p4.z, ts[2])));
+    // y = (x - o) / vs + 1: truncation gives floor + 1 for y >= 0, and 0 or
+    // less (outside, as are NaN and the saturated out-of-range results) below.
+    const uint32_t i0 = (uint32_t)cvt_trunc_d(y0) - 1u, i1 = (uint32_t)cvt_trunc_d(y1) - 1u,
+                   i2 = (uint32_t)cvt_trunc_d(y2) - 1u;
+    if (!(i0 < (uint32_t)nx && i1 < (uint32_t)ny && i2 < (uint32_t)nz)) return;
+    const double x0 = fma(y0, vs, ob[0]), x1 = fma(y1, vs, ob[1]), x2 = fma(y2, vs, ob[2]);
     // Fewer than 2^31 voxels per map (checked at load).
-    const uint32_t rec = (uint32_t)u0 + (uint32_t)nx * ((uint32_t)u1 + (uint32_t)ny * (uint32_t)u2);
+    const uint32_t rec = i0 + (uint32_t)nx * (i1 + (uint32_t)ny * i2);
     const gf4_ptr vr = reinterpret_cast<gf4_ptr>(vbase + (uint64_t)rec * 48u);
     // All three parts of the record are requested at once (one memory round
     // trip), before the occupancy test.
@@ -1144,7 +1162,8 @@ __device__ __forceinline__ void gicp_point(const double R[9], const float Rf[9],
     const float es0 = Rf[0] * e0 + Rf[3] * e1 + Rf[6] * e2;
     const float es1 = Rf[1] * e0 + Rf[4] * e1 + Rf[7] * e2;
     const float es2 = Rf[2] * e0 + Rf[5] * e1 + Rf[8] * e2;
-    // S_v (xx xy xz yy yz zz) = (vb.x vb.y vb.z vb.w vc.x vc.y); T = S_v R', Ss = R'^T T.
+    // S_v (xx xy xz yy yz zz) = (vb.x vb.y vb.z vb.w vc.x vc.y); T = S_v R', Ss = R'^T T;
+    // C = Ss + Sigma in FP32, then inverted in FP64.
     const float S00 = vb.x, S01 = vb.y, S02 = vb.z, S11 = vb.w, S12 = vc.x, S22 = vc.y;
     float T[9];
     for (int c = 0; c < 3; ++c) {
@@ -1152,17 +1171,17 @@ __device__ __forceinline__ void gicp_point(const double R[9], const float Rf[9],
         T[3 + c] = S01 * Rf[c] + S11 * Rf[3 + c] + S12 * Rf[6 + c];
         T[6 + c] = S02 * Rf[c] + S12 * Rf[3 + c] + S22 * Rf[6 + c];
     }
-    const double C00 = (double)(Rf[0] * T[0] + Rf[3] * T[3] + Rf[6] * T[6]) + (double)c4a.x;
-    const double C01 = (double)(Rf[0] * T[1] + Rf[3] * T[4] + Rf[6] * T[7]) + (double)c4a.y;
-    const double C02 = (double)(Rf[0] * T[2] + Rf[3] * T[5] + Rf[6] * T[8]) + (double)c4a.z;
-    const double C11 = (double)(Rf[1] * T[1] + Rf[4] * T[4] + Rf[7] * T[7]) + (double)c4a.w;
-    const double C12 = (double)(Rf[1] * T[2] + Rf[4] * T[5] + Rf[7] * T[8]) + (double)c4b.x;
-    const double C22 = (double)(Rf[2] * T[2] + Rf[5] * T[5] + Rf[8] * T[8]) + (double)c4b.y;
+    const double C00 = (double)(Rf[0] * T[0] + Rf[3] * T[3] + Rf[6] * T[6] + c4a.x);
+    const double C01 = (double)(Rf[0] * T[1] + Rf[3] * T[4] + Rf[6] * T[7] + c4a.y);
+    const double C02 = (double)(Rf[0] * T[2] + Rf[3] * T[5] + Rf[6] * T[8] + c4a.z);
+    const double C11 = (double)(Rf[1] * T[1] + Rf[4] * T[4] + Rf[7] * T[7] + c4a.w);
+    const double C12 = (double)(Rf[1] * T[2] + Rf[4] * T[5] + Rf[7] * T[8] + c4b.x);
+    const double C22 = (double)(Rf[2] * T[2] + Rf[5] * T[5] + Rf[8] * T[8] + c4b.y);
     // Inverse of the symmetric C by its adjugate.
     const double a00 = C11 * C22 - C12 * C12, a01 = C02 * C12 - C01 * C22, a02 = C01 * C12 - C02 * C11;
     const double det = C00 * a00 + C01 * a01 + C02 * a02;
     if (!(det > 0.0)) return;
-    const double id = 1.0 / det;
+    const double id = rcp_nr(det);
     const double O00 = a00 * id, O01 = a01 * id, O02 = a02 * id;
     const double O11 = (C00 * C22 - C02 * C02) * id, O12 = (C01 * C02 - C00 * C12) * id,
                  O22 = (C00 * C11 - C01 * C01) * id;
@@ -1217,7 +1236,7 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
     const int i = tile * 64 + lane;
     const int ic = i < N ? i : N - 1;
     const gscan_ptr scan = (gscan_ptr)d.scan_g;
-    const double inv_vs = 1.0 / (double)d.h;
+    const double vs = (double)d.h, inv_vs = 1.0 / vs;
 
     if (wave == 0) kf_select(d, i, lane, s_pose, s_nb, s_loop);
     const int chunk = (d.M + W - 1) / W;
@@ -1236,13 +1255,14 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
         float acc[27];
         for (int c = 0; c < 27; ++c) acc[c] = 0.0f;
         for (int s = 0; s < n_nb; ++s) {
-            // Relative pose T_k^-1 T (Eq. 4) in FP64: R' = R_k^T R, t' = R_k^T (t - t_k).
+            // Relative pose T_k^-1 T (Eq. 4) in FP64: R' = R_k^T R, t' = R_k^T (t - t_k);
+            // kept as R'/vs and (t' - o)/vs + 1 for the voxel index, o - vs for x.
             const int k = s_nb[s][lane];
             const size_t r = (size_t)k * 7 * N + ic;
             const float ktf[3] = {d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]};
             const float kqf[4] = {d.kf_pose[r + 3 * N], d.kf_pose[r + 4 * N], d.kf_pose[r + 5 * N],
                                   d.kf_pose[r + 6 * N]};
-            double kt[3], kq[4], Rk[9], R[9], t[3], o[3];
+            double kt[3], kq[4], Rk[9], R[9], t[3], ob[3];
             load_pose_d(ktf, kqf, kt, kq);
             rot_of_quat_d(kq[0], kq[1], kq[2], kq[3], Rk);
             const double dt[3] = {tp[0] - kt[0], tp[1] - kt[1], tp[2] - kt[2]};
@@ -1252,12 +1272,14 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
                     R[3 * row + col] = Rk[row] * Rp[col] + Rk[3 + row] * Rp[3 + col] + Rk[6 + row] * Rp[6 + col];
                     Rf[3 * row + col] = (float)R[3 * row + col];
                 }
-                t[row] = Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2];
-                o[row] = (double)d.origins[3 * k + row];
+                const double o = (double)d.origins[3 * k + row];
+                t[row] = ((Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2]) - o) * inv_vs + 1.0;
+                for (int col = 0; col < 3; ++col) R[3 * row + col] *= inv_vs;
+                ob[row] = o - vs;
             }
             const uint64_t vbase = (uint64_t)d.cells + (uint64_t)k * (uint64_t)d.grid_stride;
             for (int j = j0; j < j1; ++j)
-                gicp_point(R, Rf, t, o, inv_vs, d.nx, d.ny, d.nz, vbase, scan[3 * j], scan[3 * j + 1],
+                gicp_point(R, Rf, t, ob, vs, d.nx, d.ny, d.nz, vbase, scan[3 * j], scan[3 * j + 1],
                            scan[3 * j + 2], l, acc);
         }
         s_l[wave][lane] = l;
