@@ -661,7 +661,7 @@ def main():
     log("timed %d steps: %.3f ms/step; eval %.3f ms/step; representative error %.3f m" % (
         args.steps, 1e3 * wall / args.steps, prof["eval_ms"] / max(1, prof["steps"]), err))
     # Host-buffer entry point (scan and noise copied over PCIe each step), for reference.
-    n_host = 10
+    n_host = min(10, len(frames))
     scans_host = [np.ascontiguousarray(c["scans"][f]) for f in frames[:n_host]]
     noise_host_f = [noise_host[slot[f]] for f in frames[:n_host]]
     abi.mcs_session_sync(ctx, sid)

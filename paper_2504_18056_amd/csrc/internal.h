@@ -36,6 +36,10 @@ struct StepDesc {
     const void *cells;
     int64_t grid_stride;
     const float *origins;
+    // GICP voxel maps: one byte per voxel, nonzero where the voxel holds
+    // points (its count is positive), occ_stride bytes per map.
+    const uint8_t *vox_occ;
+    int64_t occ_stride;
     int32_t nx, ny, nz, dtype;
     float ox, oy, oz;
     float h, inv_h;

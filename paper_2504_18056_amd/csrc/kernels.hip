@@ -1134,28 +1134,41 @@ __device__ __forceinline__ double rcp_nr(double x)
     return fma(r, e, r);
 }
 
-__device__ __forceinline__ void gicp_point(const double Rs[9], const float Rf[9], const double ts[3],
-                                           const double ob[3], double vs, int nx, int ny, int nz,
-                                           uint64_t vbase, const f4v p4, const f4v c4a, const f4v c4b,
-                                           double &l, float acc[27])
+// Voxel coordinates of point p in a neighbour's map: y = (x - o)/vs + 1 (FP64),
+// truncated to floor + 1 for y >= 0 and to 0 or less (outside, as are NaN and
+// the saturated out-of-range results) below; returns the record index, or
+// 0xFFFFFFFF outside the map.  The index products take 24-bit multiplies
+// (nx and nx * ny below 2^24, voxels below 2^31: checked at load), formed for
+// every lane and then selected, so that no branch is taken.
+__device__ __forceinline__ uint32_t gicp_voxel(const double Rs[9], const double ts[3], uint32_t nx,
+                                               uint32_t ny, uint32_t nz, uint32_t nxy, double px,
+                                               double py, double pz, double y[3])
 {
-    const double y0 = fma(Rs[0], (double)p4.x, fma(Rs[1], (double)p4.y, fma(Rs[2], (double)p4.z, ts[0])));
-    const double y1 = fma(Rs[3], (double)p4.x, fma(Rs[4], (double)p4.y, fma(Rs[5], (double)p4.z, ts[1])));
-    const double y2 = fma(Rs[6], (double)p4.x, fma(Rs[7], (double)p4.y, fma(Rs[8], (double)p4.z, ts[2])));
-    // y = (x - o) / vs + 1: truncation gives floor + 1 for y >= 0, and 0 or
-    // less (outside, as are NaN and the saturated out-of-range results) below.
-    const uint32_t i0 = (uint32_t)cvt_trunc_d(y0) - 1u, i1 = (uint32_t)cvt_trunc_d(y1) - 1u,
-                   i2 = (uint32_t)cvt_trunc_d(y2) - 1u;
-    if (!(i0 < (uint32_t)nx && i1 < (uint32_t)ny && i2 < (uint32_t)nz)) return;
-    const double x0 = fma(y0, vs, ob[0]), x1 = fma(y1, vs, ob[1]), x2 = fma(y2, vs, ob[2]);
-    // Fewer than 2^31 voxels per map (checked at load).
-    const uint32_t rec = i0 + (uint32_t)nx * (i1 + (uint32_t)ny * i2);
-    const gf4_ptr vr = reinterpret_cast<gf4_ptr>(vbase + (uint64_t)rec * 48u);
-    // All three parts of the record are requested at once (one memory round
-    // trip), before the occupancy test.
-    const f4v va = vr[0], vb = vr[1], vc = vr[2];
-    asm volatile("" ::"v"(vb), "v"(vc));
-    if (!(va.w > 0.0f)) return;
+    y[0] = fma(Rs[0], px, fma(Rs[1], py, fma(Rs[2], pz, ts[0])));
+    y[1] = fma(Rs[3], px, fma(Rs[4], py, fma(Rs[5], pz, ts[1])));
+    y[2] = fma(Rs[6], px, fma(Rs[7], py, fma(Rs[8], pz, ts[2])));
+    const uint32_t i0 = (uint32_t)cvt_trunc_d(y[0]) - 1u, i1 = (uint32_t)cvt_trunc_d(y[1]) - 1u,
+                   i2 = (uint32_t)cvt_trunc_d(y[2]) - 1u;
+    const bool in = (i0 < nx) & (i1 < ny) & (i2 < nz);
+    const uint32_t rec = i0 + __umul24(nx, i1) + __umul24(nxy, i2);
+    return in ? rec : 0xFFFFFFFFu;
+}
+
+// Points whose occupancy is probed together.
+constexpr int kGicpProbe = 4;
+
+struct GicpFetch {
+    f4v va, vb, vc;
+    double x0, x1, x2;
+};
+
+__device__ __forceinline__ void gicp_point(const GicpFetch &f, const float Rf[9], const f4v p4,
+                                           const f4v c4a, const f4v c4b, double &l, float acc[27])
+{
+    // Called only for a lane whose voxel is occupied (its occupancy byte is
+    // set exactly when the record's count is positive).
+    const f4v va = f.va, vb = f.vb, vc = f.vc;
+    const double x0 = f.x0, x1 = f.x1, x2 = f.x2;
     // Residual in the keyframe frame (FP64 difference, then FP32) and in the scan frame.
     const float e0 = (float)((double)va.x - x0), e1 = (float)((double)va.y - x1),
                 e2 = (float)((double)va.z - x2);
@@ -1222,8 +1235,14 @@ __device__ __forceinline__ void gicp_point(const double Rs[9], const float Rf[9]
 template <int W>
 __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
 {
+    // The relative poses of a pass (s_rel, written before the point loops) and
+    // the per-wave partial sums (s_h, written after them) share one area.
+    constexpr size_t kRelBytes = (size_t)kKfMaxNb * 12 * 64 * sizeof(double);
+    constexpr size_t kSumBytes = (size_t)27 * W * 64 * sizeof(float);
+    __shared__ __attribute__((aligned(16))) unsigned char s_area[kRelBytes > kSumBytes ? kRelBytes : kSumBytes];
+    double(*s_rel)[12][64] = reinterpret_cast<double(*)[12][64]>(s_area);   // [neighbour][Rs 9, ts 3][lane]
+    float(*s_h)[W][64] = reinterpret_cast<float(*)[W][64]>(s_area);         // H (21) and b (6) per wave
     __shared__ double s_l[W][64];
-    __shared__ float s_h[27][W][64];            // H (21) and b (6) partial sums per wave
     __shared__ float s_pose[7][64];
     __shared__ int s_nb[kKfMaxNb][64];
     __shared__ int s_loop[64];
@@ -1235,8 +1254,13 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
     const int N = d.N, n_nb = d.n_nb;
     const int i = tile * 64 + lane;
     const int ic = i < N ? i : N - 1;
-    const gscan_ptr scan = (gscan_ptr)d.scan_g;
+    const gscan_ptr scan = (gscan_ptr)d.scan_g;           // [3M]: (mu, 0), covariance
+    const scan64_ptr scan8 = (scan64_ptr)d.scan8;         // [M] FP64 means
     const double vs = (double)d.h, inv_vs = 1.0 / vs;
+    const uint32_t nx = (uint32_t)d.nx, ny = (uint32_t)d.ny, nz = (uint32_t)d.nz, nxy = nx * ny;
+    // Occupancy bytes of all K maps (below 4 GiB, checked at load).
+    const __amdgpu_buffer_rsrc_t occ_rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(d.vox_occ), (short)0, (int)(uint32_t)(d.K * d.occ_stride), kRsrcWord3);
 
     if (wave == 0) kf_select(d, i, lane, s_pose, s_nb, s_loop);
     const int chunk = (d.M + W - 1) / W;
@@ -1246,42 +1270,104 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
     __syncthreads();
 
     for (int pass = 0; pass < passes; ++pass) {
-        const float tf[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
-        const float qf[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
-        double tp[3], qp[4], Rp[9];
-        load_pose_d(tf, qf, tp, qp);
-        rot_of_quat_d(qp[0], qp[1], qp[2], qp[3], Rp);
-        double l = 0.0;
-        float acc[27];
-        for (int c = 0; c < 27; ++c) acc[c] = 0.0f;
-        for (int s = 0; s < n_nb; ++s) {
-            // Relative pose T_k^-1 T (Eq. 4) in FP64: R' = R_k^T R, t' = R_k^T (t - t_k);
-            // kept as R'/vs and (t' - o)/vs + 1 for the voxel index, o - vs for x.
+        // Relative pose T_k^-1 T (Eq. 4) of each neighbour in FP64, one
+        // neighbour per wave: R' = R_k^T R, t' = R_k^T (t - t_k), kept as
+        // R'/vs and (t' - o)/vs + 1 for the voxel index.
+        for (int s = wave; s < n_nb; s += W) {
+            const float tf[3] = {s_pose[0][lane], s_pose[1][lane], s_pose[2][lane]};
+            const float qf[4] = {s_pose[3][lane], s_pose[4][lane], s_pose[5][lane], s_pose[6][lane]};
+            double tp[3], qp[4], Rp[9];
+            load_pose_d(tf, qf, tp, qp);
+            rot_of_quat_d(qp[0], qp[1], qp[2], qp[3], Rp);
             const int k = s_nb[s][lane];
             const size_t r = (size_t)k * 7 * N + ic;
             const float ktf[3] = {d.kf_pose[r], d.kf_pose[r + N], d.kf_pose[r + 2 * N]};
             const float kqf[4] = {d.kf_pose[r + 3 * N], d.kf_pose[r + 4 * N], d.kf_pose[r + 5 * N],
                                   d.kf_pose[r + 6 * N]};
-            double kt[3], kq[4], Rk[9], R[9], t[3], ob[3];
+            double kt[3], kq[4], Rk[9];
             load_pose_d(ktf, kqf, kt, kq);
             rot_of_quat_d(kq[0], kq[1], kq[2], kq[3], Rk);
             const double dt[3] = {tp[0] - kt[0], tp[1] - kt[1], tp[2] - kt[2]};
-            float Rf[9];
             for (int row = 0; row < 3; ++row) {
-                for (int col = 0; col < 3; ++col) {
-                    R[3 * row + col] = Rk[row] * Rp[col] + Rk[3 + row] * Rp[3 + col] + Rk[6 + row] * Rp[6 + col];
-                    Rf[3 * row + col] = (float)R[3 * row + col];
-                }
+                for (int col = 0; col < 3; ++col)
+                    s_rel[s][3 * row + col][lane] =
+                        (Rk[row] * Rp[col] + Rk[3 + row] * Rp[3 + col] + Rk[6 + row] * Rp[6 + col]) * inv_vs;
                 const double o = (double)d.origins[3 * k + row];
-                t[row] = ((Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2]) - o) * inv_vs + 1.0;
-                for (int col = 0; col < 3; ++col) R[3 * row + col] *= inv_vs;
-                ob[row] = o - vs;
+                s_rel[s][9 + row][lane] =
+                    ((Rk[row] * dt[0] + Rk[3 + row] * dt[1] + Rk[6 + row] * dt[2]) - o) * inv_vs + 1.0;
+            }
+        }
+        __syncthreads();
+        double l = 0.0;
+        float acc[27];
+        for (int c = 0; c < 27; ++c) acc[c] = 0.0f;
+        for (int s = 0; s < n_nb; ++s) {
+            const int k = s_nb[s][lane];
+            double Rs[9], ts[3], ob[3];
+            float Rf[9];
+            for (int c = 0; c < 9; ++c) {
+                Rs[c] = s_rel[s][c][lane];
+                Rf[c] = (float)(Rs[c] * vs);
+            }
+            for (int c = 0; c < 3; ++c) {
+                ts[c] = s_rel[s][9 + c][lane];
+                ob[c] = (double)d.origins[3 * k + c] - vs;
             }
             const uint64_t vbase = (uint64_t)d.cells + (uint64_t)k * (uint64_t)d.grid_stride;
-            for (int j = j0; j < j1; ++j)
-                gicp_point(R, Rf, t, ob, vs, d.nx, d.ny, d.nz, vbase, scan[3 * j], scan[3 * j + 1],
-                           scan[3 * j + 2], l, acc);
+            // Most (point, neighbour) pairs fall outside the map or in an empty
+            // voxel, for every lane at once.  So kGicpProbe points (their FP64
+            // means in one 128 B scalar load) have their occupancy bytes
+            // requested together, and only a point that some lane finds
+            // occupied has its whole record read and its terms formed.
+            const gf4_ptr vrec = reinterpret_cast<gf4_ptr>(vbase);
+            const uint32_t occ_base = (uint32_t)k * (uint32_t)d.occ_stride;
+            const auto point = [&](int j, double px, double py, double pz) {
+                double y[3];
+                const uint32_t rec = gicp_voxel(Rs, ts, nx, ny, nz, nxy, px, py, pz, y);
+                GicpFetch f;
+                const gf4_ptr vr = vrec + 3 * (size_t)rec;
+                f.va = vr[0];
+                f.vb = vr[1];
+                f.vc = vr[2];
+                // The record's three parts are requested together (one round trip).
+                asm volatile("" ::"v"(f.va), "v"(f.vb), "v"(f.vc));
+                f.x0 = fma(y[0], vs, ob[0]);
+                f.x1 = fma(y[1], vs, ob[1]);
+                f.x2 = fma(y[2], vs, ob[2]);
+                const f4v p4 = {(float)px, (float)py, (float)pz, 0.0f};
+                gicp_point(f, Rf, p4, scan[3 * j + 1], scan[3 * j + 2], l, acc);
+            };
+            int jb = j0;
+            for (; jb + kGicpProbe <= j1; jb += kGicpProbe) {
+                const d16v sq = *(const __attribute__((address_space(4))) d16v *)(scan8 + jb);
+                uint32_t occ[kGicpProbe];
+#pragma unroll
+                for (int b = 0; b < kGicpProbe; ++b) {
+                    double y[3];
+                    const uint32_t rec =
+                        gicp_voxel(Rs, ts, nx, ny, nz, nxy, sq[4 * b], sq[4 * b + 1], sq[4 * b + 2], y);
+                    // A lane outside the map reads past the buffer's end,
+                    // which returns 0 (empty): no branch, all issued before the first wait.
+                    occ[b] = __builtin_amdgcn_raw_buffer_load_b8(
+                        occ_rs, rec != 0xFFFFFFFFu ? occ_base + rec : 0xFFFFFFFFu, 0, 0);
+                }
+#pragma unroll
+                for (int b = 0; b < kGicpProbe; ++b) {
+                    if (__builtin_amdgcn_ballot_w64(occ[b] != 0u) == 0) continue;
+                    if (occ[b] != 0u) point(jb + b, sq[4 * b], sq[4 * b + 1], sq[4 * b + 2]);
+                }
+            }
+            for (; jb < j1; ++jb) {
+                const d4v p = scan8[jb];
+                double y[3];
+                const uint32_t rec = gicp_voxel(Rs, ts, nx, ny, nz, nxy, p.x, p.y, p.z, y);
+                const uint32_t o = __builtin_amdgcn_raw_buffer_load_b8(
+                    occ_rs, rec != 0xFFFFFFFFu ? occ_base + rec : 0xFFFFFFFFu, 0, 0);
+                if (__builtin_amdgcn_ballot_w64(o != 0u) == 0) continue;
+                if (o != 0u) point(jb, p.x, p.y, p.z);
+            }
         }
+        __syncthreads();   // every wave is done with s_rel before s_h reuses it
         s_l[wave][lane] = l;
         for (int c = 0; c < 27; ++c) s_h[c][wave][lane] = acc[c];
         __syncthreads();
@@ -1626,6 +1712,7 @@ __device__ __forceinline__ void pack_blk(const StepDesc &d, int b)
         o[0] = ok ? make_float4(x, y, z, 0.0f) : make_float4(1e30f, 1e30f, 1e30f, 0.0f);
         o[1] = ok ? make_float4(c[0], c[1], c[2], c[3]) : make_float4(1.0f, 0.0f, 0.0f, 1.0f);
         o[2] = ok ? make_float4(c[4], c[5], 0.0f, 0.0f) : make_float4(0.0f, 1.0f, 0.0f, 0.0f);
+        d.scan8[j] = ok ? make_double4(x, y, z, 0.0) : make_double4(1e30, 1e30, 1e30, 0.0);
         return;
     }
     const float x = d.scan3[3 * j], y = d.scan3[3 * j + 1], z = d.scan3[3 * j + 2];

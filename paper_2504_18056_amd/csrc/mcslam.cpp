@@ -314,6 +314,8 @@ StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float 
     d.scan_g = s->scan_g;
     d.hess = s->hess;
     d.origins = m->origins_dev;
+    d.vox_occ = m->occ_dev;
+    d.occ_stride = (int64_t)align_up((size_t)m->records);
     d.tail_l = s->tail_l;
     d.tail_g = s->tail_g;
     d.tail_tiles = s->tail_tiles;
@@ -543,10 +545,15 @@ mcs_status mcs_load_gicp_keyframes(mcs_ctx *ctx, int32_t K, const mcs_voxel_desc
     }
     const int64_t recs = (int64_t)d0.nx * d0.ny * d0.nz;
     if (recs >= (int64_t)1 << 31) return fail(MCS_EINVAL, "voxel map has 2^31 or more voxels");
+    if ((int64_t)d0.nx * d0.ny >= (int64_t)1 << 24)
+        return fail(MCS_EINVAL, "voxel map rows times columns must stay below 2^24");
     mcs_status s = set_device(ctx);
     if (s != MCS_OK) return s;
     const size_t map_bytes = (size_t)recs * kVoxelRecordBytes;
-    const size_t total = align_up(map_bytes) * K + align_up((size_t)K * 3 * sizeof(float));
+    const size_t occ_stride = align_up((size_t)recs);
+    if (occ_stride * (size_t)K >= ((size_t)1 << 32) - 1)
+        return fail(MCS_EINVAL, "voxel maps hold 2^32 or more voxels in total");
+    const size_t total = align_up(map_bytes) * K + align_up((size_t)K * 3 * sizeof(float)) + occ_stride * K;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (!budget_allows(ctx, total))
@@ -569,9 +576,16 @@ mcs_status mcs_load_gicp_keyframes(mcs_ctx *ctx, int32_t K, const mcs_voxel_desc
     hipError_t e = hipMalloc(&m->cells, total);
     if (e == hipSuccess) {
         m->origins_dev = reinterpret_cast<float *>((char *)m->cells + align_up(map_bytes) * K);
-        for (int k = 0; k < K && e == hipSuccess; ++k)
+        m->occ_dev = reinterpret_cast<uint8_t *>((char *)m->origins_dev + align_up((size_t)K * 3 * sizeof(float)));
+        std::vector<uint8_t> occ(occ_stride, 0);
+        for (int k = 0; k < K && e == hipSuccess; ++k) {
             e = hipMemcpy((char *)m->cells + align_up(map_bytes) * k, voxels[k], map_bytes,
                           hipMemcpyHostToDevice);
+            // Occupied: a positive point count (the test the kernel makes on the record).
+            for (int64_t v = 0; v < recs; ++v) occ[v] = voxels[k][(size_t)v * 12 + 3] > 0.0f ? 1 : 0;
+            if (e == hipSuccess)
+                e = hipMemcpy(m->occ_dev + occ_stride * k, occ.data(), occ_stride, hipMemcpyHostToDevice);
+        }
         if (e == hipSuccess)
             e = hipMemcpy(m->origins_dev, m->origins.data(), (size_t)K * 3 * sizeof(float),
                           hipMemcpyHostToDevice);

@@ -41,6 +41,7 @@ struct Map {
     size_t bytes = 0;
     int64_t records = 0;             // per grid (cells or voxels)
     float *origins_dev = nullptr;
+    uint8_t *occ_dev = nullptr;      // voxel maps: occupancy bytes, align_up(records) per map
     int users = 0;
 };
 
