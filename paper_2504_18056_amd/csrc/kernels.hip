@@ -2339,26 +2339,40 @@ __device__ __forceinline__ void order_cell_blk(const StepDesc &d, int b)
             for (int k = 0; k < kOrderDims; ++k) code = (code << 1) | ((q[k] >> bit) & 1);
         cell = code >> kOrderDrop;
     }
-    // One atomic add per distinct cell of the wave; every lane of that cell
-    // takes its rank from the lanes below it.
+    // Ranks within the cells: the wave's (cell, lane) keys are sorted across
+    // the lanes (bitonic; unused lanes last), each run of equal cells takes its
+    // base from one atomic add by its first lane (all runs in one instruction),
+    // and every lane of a run adds its place in the run.  The sorted lane
+    // writes the cell and rank of the particle its key came from.
     const int lane = __lane_id();
-    uint64_t todo = __ballot(valid);
-    int rank = 0;
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int c = __shfl(cell, leader);
-        const uint64_t same = __ballot(cell == c);
-        int first = 0;
-        if (lane == leader)
-            first = __hip_atomic_fetch_add(d.ocount + c, (int)__popcll(same), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-        first = __shfl(first, leader);
-        if (cell == c) rank = first + (int)__popcll(same & ((1ull << lane) - 1ull));
-        todo &= ~same;
+    uint32_t key = valid ? ((uint32_t)cell << 6) | (uint32_t)lane : 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t other = (uint32_t)__shfl_xor((int)key, j);
+            const bool ascending = (lane & k) == 0, lower = (lane & j) == 0;
+            key = (lower == ascending) ? min(key, other) : max(key, other);
+        }
     }
-    if (valid) {
-        d.ocell[i] = cell;
-        d.orank[i] = rank;
+    const bool used = key != 0xFFFFFFFFu;
+    const uint32_t c = key >> 6;
+    const uint32_t c_prev = (uint32_t)__shfl_up((int)c, 1);
+    const bool head = used && (lane == 0 || c != c_prev);
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int start = 63 - __clzll((long long)(heads & upto));   // this lane's run starts here
+    const uint64_t later = heads & ~upto;                           // heads after this lane
+    const int n_used = (int)__popcll(__ballot(used));
+    const int next = later ? __ffsll((long long)later) - 1 : n_used;
+    int first = 0;
+    if (head)
+        first = __hip_atomic_fetch_add(d.ocount + c, next - lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    first = __shfl(first, start);
+    if (used) {
+        const int i_src = b * B + (tid & ~63) + (int)(key & 63u);
+        d.ocell[i_src] = (int)c;
+        d.orank[i_src] = first + (lane - start);
     }
 }
 
