@@ -167,8 +167,12 @@ bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe);
 // serves any batch composition.
 enum BatchKind {
     kPack = 0, kPredict, kEval, kWeights, kWCombine, kNormScan, kPrefix, kSearch, kCommit, kFill,
+    kChunk,    // sessions split whole: (descriptor, tile * 4 + group of 8 sub-chunks)
+    kTStep,    // their per-pass reduce and epilogue: (descriptor, tile)
     kNumKinds
 };
+// Passes that a tick runs on split sessions (requests with more take kEval).
+constexpr int kBatchSplitPasses = 4;
 
 struct BatchTables {
     const StepDesc *descs;

@@ -2562,6 +2562,24 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) voi
     MCS_BATCH_LOOP(kEval, (eval_tile<DT, false, SKIP, W>(d, w.y)))
 }
 
+// Sessions split whole in a tick (fewer tiles than fill the device): pass
+// PASS of every tile as one wave per sub-chunk, then the tile's reduce and
+// epilogue, as the per-session tail path does (same sums, same order).
+template <int DT, bool SKIP, int PASS>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void kb_tail_chunk(BatchTables t)
+{
+    constexpr int G = kSubChunks / 8;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    MCS_BATCH_LOOP(kChunk, if (PASS < d.iters + d.post_eval)
+                               (tail_chunk<DT, false, SKIP>(d, 0, PASS, w.y / G, (w.y % G) * 8 + wave)))
+}
+
+template <int W, int PASS>
+__global__ __launch_bounds__(64) void kb_tail_step(BatchTables t)
+{
+    MCS_BATCH_LOOP(kTStep, if (PASS < d.iters + d.post_eval) (tail_step<W>(d, 0, PASS, w.y)))
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2838,6 +2856,15 @@ static hipError_t launch_batch_dt(const BatchTables &t, hipStream_t st)
     hipLaunchKernelGGL(kb_pack, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_predict, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL((kb_eval<DT, SKIP, kEvalW>), dim3(kBatchGridEval), dim3(64 * kEvalW), 0, st, t);
+    static_assert(kBatchSplitPasses == 4, "one chunk and one step launch per split pass");
+    hipLaunchKernelGGL((kb_tail_chunk<DT, SKIP, 0>), dim3(kBatchGridEval), dim3(512), 0, st, t);
+    hipLaunchKernelGGL((kb_tail_step<kEvalW, 0>), dim3(kBatchGridSmall), dim3(64), 0, st, t);
+    hipLaunchKernelGGL((kb_tail_chunk<DT, SKIP, 1>), dim3(kBatchGridEval), dim3(512), 0, st, t);
+    hipLaunchKernelGGL((kb_tail_step<kEvalW, 1>), dim3(kBatchGridSmall), dim3(64), 0, st, t);
+    hipLaunchKernelGGL((kb_tail_chunk<DT, SKIP, 2>), dim3(kBatchGridEval), dim3(512), 0, st, t);
+    hipLaunchKernelGGL((kb_tail_step<kEvalW, 2>), dim3(kBatchGridSmall), dim3(64), 0, st, t);
+    hipLaunchKernelGGL((kb_tail_chunk<DT, SKIP, 3>), dim3(kBatchGridEval), dim3(512), 0, st, t);
+    hipLaunchKernelGGL((kb_tail_step<kEvalW, 3>), dim3(kBatchGridSmall), dim3(64), 0, st, t);
     hipLaunchKernelGGL(kb_weights, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_wcombine, dim3(kBatchGridOne), dim3(kWeightBlock), 0, st, t);
     hipLaunchKernelGGL(kb_normscan, dim3(kBatchGridSmall), dim3(kWeightBlock), 0, st, t);

@@ -234,8 +234,12 @@ bool launch_tick(mcs_server *s, std::unique_lock<std::mutex> &lk, TableBuf &b, T
         StepDesc d = make_desc(ss, r.scan, r.M, r.noise, &r.p);
         d.order = nullptr;   // the batched stages evaluate in slot order
         const int nb = weight_blocks(d.N), nt = particle_tiles(d.N), ns = scan_blocks(d.M);
-        const std::array<int, kNumKinds> need = {ns, d.predict ? nb : 0, nt, nb, 1, nb, 1, nb, nb,
-                                                 d.policy == MCS_RESAMPLE_PRUNE ? nb : 0};
+        // A session whose tail buffer holds all its tiles (one small enough not
+        // to fill the device) is split whole, as on its own stream.
+        const bool split = d.tail_tiles >= nt && d.iters + d.post_eval <= kBatchSplitPasses;
+        const std::array<int, kNumKinds> need = {ns, d.predict ? nb : 0, split ? 0 : nt, nb, 1, nb, 1, nb, nb,
+                                                 d.policy == MCS_RESAMPLE_PRUNE ? nb : 0,
+                                                 split ? nt * (kSubChunks / 8) : 0, split ? nt : 0};
         bool fits = true;
         for (int k = 0; k < kNumKinds; ++k) fits = fits && counts[k] + need[k] <= s->max_items;
         if (!fits) {
