@@ -46,11 +46,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(grid_dtype):
-    """HBM bytes per launch of the evaluation kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings), or
-    None when the summary is missing, is for another grid dtype, or was taken
-    on a different kernel source."""
+def counter_summary(grid_dtype):
+    """The committed counter summary of the evaluation stage as a dict of its
+    "key: value" lines, or None when it is missing, is for another grid dtype,
+    or was taken on a different kernel source."""
     import hashlib
     try:
         with open(PMC_SUMMARY) as f:
@@ -61,7 +60,49 @@ def measured_traffic(grid_dtype):
         return None
     if kv.get("kernel_source_sha256", "").strip() != sha or int(kv.get("grid_dtype", -1)) != grid_dtype:
         return None
-    return float(kv["hbm_bytes_per_launch"])
+    return kv
+
+
+def measured_traffic(grid_dtype):
+    """HBM bytes per launch of the evaluation kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings), or
+    None (see counter_summary)."""
+    kv = counter_summary(grid_dtype)
+    return None if kv is None else float(kv["hbm_bytes_per_launch"])
+
+
+def issue_ceilings(rates, evals_per_s, grid_dtype):
+    """VALU issue ceiling of the evaluation stage from the measured per-class
+    issue rates (mcs_measure_issue_rates) and the stage's instruction mix per
+    evaluation (SQ_INSTS_VALU_* counters of the committed summary): every
+    instruction issued at its own class's measured rate, one after another,
+    1 / sum_c (n_c / rate_c) evaluations per second."""
+    kv = counter_summary(grid_dtype)
+    if kv is None or rates is None:
+        return None
+    per = lambda k: float(kv[k].split()[0])
+    total = per("valu_lane_ops_per_eval")
+    mix = {"fp32": per("sq_insts_valu_fma_f32_per_eval") + per("sq_insts_valu_mul_f32_per_eval") +
+                   per("sq_insts_valu_add_f32_per_eval"),
+           "fp64": per("sq_insts_valu_fma_f64_per_eval") + per("sq_insts_valu_add_f64_per_eval"),
+           "cvt": per("sq_insts_valu_cvt_per_eval"),
+           "int32": per("sq_insts_valu_int32_per_eval"),
+           "trans": per("sq_insts_valu_trans_f32_per_eval")}
+    mix["other"] = max(0.0, total - sum(mix.values()))
+    rate_of = {"fp32": rates["fp32_fma"], "fp64": rates["fp64_fma"], "cvt": rates["fp64_unary"],
+               "int32": rates["int24"], "trans": rates["trans"], "other": rates["int24"]}
+    by_class = 1.0 / sum(mix[k] / rate_of[k] for k in mix)
+    return {"rates_T_lane_ops_per_s": {k: round(v / 1e12, 2) for k, v in rates.items()},
+            "valu_per_eval": round(total, 2), "mix_per_eval": {k: round(v, 2) for k, v in mix.items()},
+            "ceiling_evals_per_s": round(by_class, 1),
+            "evals_per_s": round(evals_per_s, 1),
+            "frac": round(evals_per_s / by_class, 4),
+            "note": "rates: eight independent chains per lane of one instruction class over the "
+                    "whole device (fp32: v_fmac_f32; fp64: v_fmac_f64; fp64_unary: v_fract_f64, "
+                    "the class of floor and FP64 conversions; int24: v_mad_u32_u24; trans: "
+                    "v_rcp_f32; fp32_fp64: v_fmac_f32 and v_fmac_f64 alternating); mix: the evaluation stage's VALU instructions per evaluation "
+                    "by class from %s (other: the rest, at the int24 rate)"
+                    % os.path.relpath(PMC_SUMMARY, ROOT)}
 
 
 def cpu_cores():
@@ -699,6 +740,8 @@ def main():
     log("scan order: %s" % scan_order)
     trajectory = run_trajectory(abi, torch, ctx, mid, c, base)
     log("trajectory: %s" % trajectory)
+    rates = abi.mcs_measure_issue_rates(ctx)
+    log("VALU issue rates (T lane-ops/s): %s" % {k: round(v / 1e12, 2) for k, v in rates.items()})
     abi.mcs_destroy(ctx)
     copy_gbps = device_copy_gbps(torch)
     log("device copy: %.0f GB/s (read + write)" % copy_gbps)
@@ -723,6 +766,7 @@ def main():
                 "kernel": "k_eval (with its tail kernels)", "eval_launch_ms": round(eval_s * 1e3, 4),
                 "flops_per_eval": FLOPS_PER_EVAL,
                 "gather_floor": floors_conv,
+                "issue_ceiling": issue_ceilings(rates, evals_per_step / eval_s, args.grid_dtype),
                 "gather_bytes_per_stage": round(gbytes * 1e9),
                 "gather_rate_TBps": round(gbytes / eval_s / 1e3, 3),
                 "note": "algorithmic FP32 arithmetic (%d FLOPs per evaluation, an FMA = 2) x %d "

@@ -417,6 +417,26 @@ mcs_status mcs_session_profile(mcs_ctx *ctx, int32_t session_id, int32_t enable)
 /* Wait for the session's profiled steps and return the accumulated times. */
 mcs_status mcs_session_profile_read(mcs_ctx *ctx, int32_t session_id, mcs_profile *out);
 
+/* VALU issue rates of the device by instruction class: a measurement aid for
+ * the roofline of the evaluation kernels, not part of the filter.  Each class
+ * runs eight independent dependency chains per lane over a grid that fills
+ * the device several times; rates[c] is lane-operations per second (an FMA
+ * counts once) for class c, timed with HIP events on the null stream. */
+typedef enum {
+    MCS_RATE_FP32_FMA = 0,     /* v_fmac_f32 */
+    MCS_RATE_FP64_FMA = 1,     /* v_fmac_f64 */
+    MCS_RATE_FP64_UNARY = 2,   /* v_fract_f64 (the class of v_floor_f64 and v_cvt_*_f64) */
+    MCS_RATE_INT24 = 3,        /* v_mad_u32_u24 */
+    MCS_RATE_TRANS = 4,        /* v_rcp_f32 (the class of v_log_f32) */
+    MCS_RATE_FP32_FP64 = 5,    /* v_fmac_f32 and v_fmac_f64 alternating */
+    MCS_RATE_COUNT = 6
+} mcs_rate_class;
+
+/* rates: caller's host array of n >= MCS_RATE_COUNT doubles.  Takes about a
+ * second; runs on the context's device.  Errors: MCS_EINVAL (NULL, n too
+ * small), MCS_EDEVICE. */
+mcs_status mcs_measure_issue_rates(mcs_ctx *ctx, double *rates, int32_t n);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: a request loop over many concurrent sessions                     */
 /* ------------------------------------------------------------------------ */

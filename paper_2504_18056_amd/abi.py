@@ -127,6 +127,7 @@ def lib():
             "mcs_get_gicp_system": (i32, [vp, i32, vp, vp]),
             "mcs_session_info": (i32, [vp, i32, P(i32), P(i32), P(i32), P(i32)]),
             "mcs_gather_floor_dev": (i32, [vp, i32, vp, i32, P(StepParams), vp]),
+            "mcs_measure_issue_rates": (i32, [vp, P(C.c_double), i32]),
             "mcs_filter_step_noalloc": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, vp, i32, vp,
                                               P(StepParams), vp, vp]),
             "mcs_session_trace": (i32, [vp, i32, i32]),
@@ -371,6 +372,16 @@ def mcs_gather_floor_dev(ctx, sid, scan_dev_ptr, M, params, stream=None):
     p = params if isinstance(params, StepParams) else step_params(params)
     _check(lib().mcs_gather_floor_dev(ctx, int(sid), C.c_void_p(int(scan_dev_ptr)), int(M), C.byref(p),
                                       None if stream is None else C.c_void_p(int(stream))))
+
+
+RATE_CLASSES = ("fp32_fma", "fp64_fma", "fp64_unary", "int24", "trans", "fp32_fp64")
+
+
+def mcs_measure_issue_rates(ctx):
+    """VALU lane-operations per second by instruction class (measurement aid)."""
+    r = (C.c_double * len(RATE_CLASSES))()
+    _check(lib().mcs_measure_issue_rates(ctx, r, len(RATE_CLASSES)))
+    return {k: float(r[i]) for i, k in enumerate(RATE_CLASSES)}
 
 
 def mcs_session_info(ctx, sid):

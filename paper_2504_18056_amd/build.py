@@ -35,13 +35,14 @@ def _run(cmd, verbose):
 
 
 def build(verbose=False, save_temps=False):
-    """Compile kernels.hip and mcslam.cpp and link libmcslam.so (always rebuilds)."""
+    """Compile kernels.hip, mcslam.cpp, server.cpp and rates.hip and link libmcslam.so (always rebuilds)."""
     hipcc = _hipcc()
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
     k_obj = os.path.join(obj_dir, "kernels.o")
     h_obj = os.path.join(obj_dir, "mcslam.o")
     s_obj = os.path.join(obj_dir, "server.o")
+    r_obj = os.path.join(obj_dir, "rates.o")
     extra = ["-save-temps=obj"] if save_temps else []
     _run([hipcc, "-x", "hip", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS + extra +
          ["-c", os.path.join(CSRC, "kernels.hip"), "-o", k_obj], verbose)
@@ -49,9 +50,11 @@ def build(verbose=False, save_temps=False):
          ["-c", os.path.join(CSRC, "mcslam.cpp"), "-o", h_obj], verbose)
     _run([hipcc, "-x", "hip", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS +
          ["-c", os.path.join(CSRC, "server.cpp"), "-o", s_obj], verbose)
+    _run([hipcc, "-x", "hip", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS +
+         ["-c", os.path.join(CSRC, "rates.hip"), "-o", r_obj], verbose)
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp, k_obj, h_obj,
-          s_obj], verbose)
+          s_obj, r_obj], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -190,4 +190,8 @@ hipError_t launch_batch(const BatchTables &t, int dtype, int skip, hipStream_t s
 constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
 hipError_t scratch_init(int device, void **ptr);
 
+// VALU lane-operations per second by instruction class (mcs_rate_class
+// order, MCS_RATE_COUNT entries), on the current device.
+hipError_t measure_issue_rates(double *rates);
+
 }  // namespace mcs

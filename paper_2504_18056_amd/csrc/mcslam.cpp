@@ -1171,6 +1171,16 @@ mcs_status mcs_gather_floor_dev(mcs_ctx *ctx, int32_t sid, const float *scan_dev
     return MCS_OK;
 }
 
+mcs_status mcs_measure_issue_rates(mcs_ctx *ctx, double *rates, int32_t n)
+{
+    if (!ctx || !rates) return fail(MCS_EINVAL, "NULL argument");
+    if (n < MCS_RATE_COUNT) return fail(MCS_EINVAL, "rates holds %d entries, %d needed", n, (int)MCS_RATE_COUNT);
+    mcs_status st = set_device(ctx);
+    if (st != MCS_OK) return st;
+    HIP_TRY(measure_issue_rates(rates), "issue-rate kernels");
+    return MCS_OK;
+}
+
 mcs_status mcs_filter_step_gicp(mcs_ctx *ctx, int32_t sid, const float *mu, const float *cov,
                                 int32_t M, const float *noise, const mcs_step_params *p)
 {

@@ -62,3 +62,17 @@ def test_gather_floor_keeps_poses_and_is_tiling_independent():
         abi.mcs_release_map(ctx, kmid)
     finally:
         abi.mcs_destroy(ctx)
+
+
+def test_issue_rates_are_measured():
+    """The per-class VALU issue rates behind the bench's issue ceilings: every
+    class measured, positive and below the device's lane count x clock x 2."""
+    ctx = abi.mcs_create(0)
+    try:
+        r = abi.mcs_measure_issue_rates(ctx)
+    finally:
+        abi.mcs_destroy(ctx)
+    assert set(r) == set(abi.RATE_CLASSES)
+    bound = 256 * 4 * 64 * 3.0e9     # far above any class on this device
+    for k, v in r.items():
+        assert 1e11 < v < bound, (k, v)
