@@ -85,6 +85,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise McsError(MCS_EDEVICE, "HIP library %s is not built; run "
                            "`python -m paper_2504_18056_amd.build`" % LIB_PATH)
+        # One HIP runtime per process: PyTorch ships its own copy of the ROCm
+        # runtime libraries, and when this library is loaded first (binding the
+        # system's copy) a later `import torch` finds no GPU.  So torch, when
+        # installed, is imported before the library, and both use its runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         try:
             L = C.CDLL(LIB_PATH)
         except OSError as e:

@@ -1,13 +1,15 @@
-"""The gather-floor measurement entry point (mcs_gather_floor_dev).
+"""The measurement entry points: the gather floor (mcs_gather_floor_dev) and
+the VALU issue rates (mcs_measure_issue_rates), and torch in the same process.
 
-It runs the evaluation passes with the arithmetic cut to a checksum of the
-gathered record words.  Checked here: the poses stay put (translations
-bit-exact), the checksum of a particle does not depend on the tiling of the
-session it sits in (whole rounds, a split tail, a small session), repeated
-runs agree, and keyframe maps are refused.
+The gather floor runs the evaluation passes with the arithmetic cut to a
+checksum of the gathered record words.  Checked here: the poses stay put
+(translations bit-exact), the checksum of a particle does not depend on the
+tiling of the session it sits in (whole rounds, a split tail, a small
+session), repeated runs agree, and keyframe maps are refused.
 """
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -17,6 +19,8 @@ from paper_2504_18056_amd import abi
 from synth import configs
 
 pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 DEV = torch.device("cuda:0")
 
@@ -76,3 +80,21 @@ def test_issue_rates_are_measured():
     bound = 256 * 4 * 64 * 3.0e9     # far above any class on this device
     for k, v in r.items():
         assert 1e11 < v < bound, (k, v)
+
+
+def test_torch_works_after_the_library_initialised_the_gpu():
+    """A process that creates a context first and uses torch afterwards (the
+    binding imports torch before loading the library, so both share its HIP
+    runtime)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2504_18056_amd import abi\n"
+            "ctx = abi.mcs_create(0)\n"
+            "import torch\n"
+            "x = torch.ones(8, device='cuda:0'); torch.cuda.synchronize()\n"
+            "assert float(x.sum()) == 8.0\n"
+            "abi.mcs_destroy(ctx)\n"
+            "print('ok')\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stderr[-2000:]
