@@ -712,6 +712,13 @@ __device__ __forceinline__ void load_tile_pose(const StepDesc &d, int i, int lan
 // With s_upd (keyframe maps, loop-gated correction) only lanes with s_loop >= 0
 // step, and each of them leaves psi (rows 0-5) and its translation before the
 // step (rows 6-8) in s_upd for the keyframe propagation.
+// Sub-chunk sc (in summation order) of wave w of a tile: the waves take the
+// sub-chunks in turn, so that at any time the 8 waves of a tile, and the tiles
+// running beside it, evaluate neighbouring parts of the scan (whose points
+// land in overlapping cells).
+template <int W>
+__device__ __forceinline__ constexpr int wave_sub_chunk(int w, int sc) { return sc * W + w; }
+
 template <int W>
 __device__ __forceinline__ void tile_epilogue(const StepDesc &d, int i, int lane, int pass,
                                               const double (*s_l)[64], const float (*s_g)[W][64],
@@ -817,7 +824,7 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
             GridMap64 gm;
             grid_map64(t, q, d.ox, d.oy, d.oz, d.h, gm);
             for (int sc = 0; sc < S; ++sc) {
-                const int c = wave * S + sc;
+                const int c = wave_sub_chunk<W>(wave, sc);
                 Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
                 eval_range64<DT, BIG, SKIP, false, false, FLOOR>(g, (scan64_ptr)d.scan8, (scan32_ptr)d.scan4,
                                                                  min(M, c * Q), min(M, (c + 1) * Q), gm, part);
@@ -898,7 +905,7 @@ __device__ __forceinline__ void tail_step(const StepDesc &d, int tile0, int pass
     for (int w = 0; w < W; ++w) {
         Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         for (int sc = 0; sc < S; ++sc) {
-            const size_t r = (size_t)rel * kSubChunks + w * S + sc;
+            const size_t r = (size_t)rel * kSubChunks + wave_sub_chunk<W>(w, sc);
             const float *tg = d.tail_g + r * 6 * 64 + lane;
             const Acc part = {d.tail_l[r * 64 + lane], tg[0], tg[64], tg[128], tg[192], tg[256], tg[320]};
             add_acc(acc, part);
