@@ -1270,9 +1270,6 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
         const_cast<uint8_t *>(d.vox_occ), (short)0, (int)(uint32_t)(d.K * d.occ_stride), kRsrcWord3);
 
     if (wave == 0) kf_select(d, i, lane, s_pose, s_nb, s_loop);
-    const int chunk = (d.M + W - 1) / W;
-    const int j0 = min(d.M, wave * chunk);
-    const int j1 = min(d.M, j0 + chunk);
     const int passes = d.iters + d.post_eval;
     __syncthreads();
 
@@ -1344,8 +1341,12 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
                 const f4v p4 = {(float)px, (float)py, (float)pz, 0.0f};
                 gicp_point(f, Rf, p4, scan[3 * j + 1], scan[3 * j + 2], l, acc);
             };
-            int jb = j0;
-            for (; jb + kGicpProbe <= j1; jb += kGicpProbe) {
+            // Batches of kGicpProbe points are dealt to the waves in turn (at any
+            // time the waves of a tile probe neighbouring points); the last
+            // M mod kGicpProbe points go to the last wave.
+            const int n_batch = d.M / kGicpProbe;
+            for (int bt = wave; bt < n_batch; bt += W) {
+                const int jb = bt * kGicpProbe;
                 const d16v sq = *(const __attribute__((address_space(4))) d16v *)(scan8 + jb);
                 uint32_t occ[kGicpProbe];
 #pragma unroll
@@ -1364,7 +1365,7 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
                     if (occ[b] != 0u) point(jb + b, sq[4 * b], sq[4 * b + 1], sq[4 * b + 2]);
                 }
             }
-            for (; jb < j1; ++jb) {
+            for (int jb = wave == W - 1 ? n_batch * kGicpProbe : d.M; jb < d.M; ++jb) {
                 const d4v p = scan8[jb];
                 double y[3];
                 const uint32_t rec = gicp_voxel(Rs, ts, nx, ny, nz, nxy, p.x, p.y, p.z, y);
