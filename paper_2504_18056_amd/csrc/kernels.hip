@@ -1536,7 +1536,7 @@ __device__ __forceinline__ void kf_tile_buf(const StepDesc &d, int tile)
             if (GLB) g.gbase = static_cast<const char *>(d.cells) + (uint64_t)k * (uint64_t)d.grid_stride;
             Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             for (int sc = 0; sc < S; ++sc) {
-                const int c = wave * S + sc;
+                const int c = wave_sub_chunk<W>(wave, sc);
                 Acc part = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
                 eval_range64<DT, false, SKIP, !GLB, GLB>(g, (scan64_ptr)d.scan8, (scan32_ptr)d.scan4, min(M, c * Q),
                                                          min(M, (c + 1) * Q), gm, part);
@@ -1674,7 +1674,7 @@ __device__ __forceinline__ void kf_tail_step(const StepDesc &d, int tile0, int p
         kf_grid_map(d, k, ic, tf, qf, ih, gm);
         Acc acc = {0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         for (int sc = 0; sc < S; ++sc) {
-            const size_t r = ((size_t)rel * kSubChunks + wave * S + sc) * kKfMaxNb + s;
+            const size_t r = ((size_t)rel * kSubChunks + wave_sub_chunk<W>(wave, sc)) * kKfMaxNb + s;
             const float *tg = t.g + r * 6 * 64 + lane;
             const Acc part = {t.l[r * 64 + lane], tg[0], tg[64], tg[128], tg[192], tg[256], tg[320]};
             add_acc(acc, part);
