@@ -295,7 +295,8 @@ def gicp_evaluate(vox, dims, origins, vs, mu, cov, poses, kf_poses, n_nb=4, delt
     correspondences, and the Gauss-Newton system of Eq. 6: H (N, 21) upper
     triangle row-major, b (N, 6).  vox (K, nz, ny, nx, 12) voxel Gaussians in
     each keyframe's frame, origins (K, 3), voxel edge vs; scan means mu (M, 3)
-    and covariances cov (M, 6: xx xy xz yy yz zz)."""
+    and covariances cov (M, 6: xx xy xz yy yz zz).  habs, babs: per entry, the
+    sum of the magnitudes of the products it is made of (the rounding scale)."""
     nx, ny, nz = (int(v) for v in dims)
     v = _f32(vox).reshape(-1)
     K = v.size // (nx * ny * nz * 12)

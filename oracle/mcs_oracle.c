@@ -1091,16 +1091,37 @@ static void gicp_terms(const voxmap_t *m, const double R[9], const double t[3], 
                 for (int k = 0; k < 3; ++k) acc += Om[3 * r + k] * J[k][c];
                 OJ[r][c] = acc;
             }
+        /* Scales for the checks: each entry of b and H is a sum of products
+         * (J^T Omega e, J^T Omega J); its rounding in any evaluation order is
+         * bounded in proportion to the sum of those products' magnitudes,
+         * |J|^T |Omega| |e| and |J|^T |Omega| |J|, which can be far larger
+         * than the entry itself when the products cancel. */
+        double aw[3], aOJ[3][6];
+        for (int r = 0; r < 3; ++r) {
+            aw[r] = 0.0;
+            for (int k = 0; k < 3; ++k) aw[r] += fabs(Om[3 * r + k]) * fabs(es[k]);
+            for (int c = 0; c < 6; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += fabs(Om[3 * r + k]) * fabs(J[k][c]);
+                aOJ[r][c] = acc;
+            }
+        }
         for (int r = 0; r < 6; ++r) {
-            double bb = 0.0;
-            for (int k = 0; k < 3; ++k) bb += J[k][r] * w[k];
+            double bb = 0.0, ba = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                bb += J[k][r] * w[k];
+                ba += fabs(J[k][r]) * aw[k];
+            }
             o->b[r] += bb;
-            o->babs[r] += fabs(bb);
+            o->babs[r] += ba;
             for (int c = r; c < 6; ++c) {
-                double hh = 0.0;
-                for (int k = 0; k < 3; ++k) hh += J[k][r] * OJ[k][c];
+                double hh = 0.0, ha = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    hh += J[k][r] * OJ[k][c];
+                    ha += fabs(J[k][r]) * aOJ[k][c];
+                }
                 o->H[tri(r, c)] += hh;
-                o->habs[tri(r, c)] += fabs(hh);
+                o->habs[tri(r, c)] += ha;
             }
         }
     }
@@ -1112,6 +1133,9 @@ static void gicp_terms(const voxmap_t *m, const double R[9], const double t[3], 
  * K voxel maps back to back (each nx*ny*nz*12 floats), origins (K, 3) in each
  * keyframe's frame; scan means (M, 3) and covariances (M, 6).  n_corr counts
  * the points with a correspondence, n_amb those within delta of a voxel face.
+ * habs (21) and babs (6) per particle: the sums of the magnitudes of the
+ * products that make up each entry (|J|^T |Omega| |J|, |J|^T |Omega| |e|),
+ * the scale of their rounding (test infrastructure).
  * nb_force (N, n_nb) or NULL, nb_margin (N) or NULL as for oracle_kf_eval. */
 int oracle_gicp_eval(const float *vox, int K, int nx, int ny, int nz, const double *origins,
                      double vs, const float *mu, const float *cov, int M, const float *poses,
