@@ -1259,7 +1259,7 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int N = d.N, n_nb = d.n_nb;
-    const int i = tile * 64 + lane;
+    const int i = slot_particle(d, tile * 64 + lane);
     const int ic = i < N ? i : N - 1;
     const gscan_ptr scan = (gscan_ptr)d.scan_g;           // [3M]: (mu, 0), covariance
     const scan64_ptr scan8 = (scan64_ptr)d.scan8;         // [M] FP64 means

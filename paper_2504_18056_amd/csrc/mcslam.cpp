@@ -81,9 +81,9 @@ Layout session_layout(int N, int M_max, int K, bool gicp, size_t tail_size)
         (gicp ? (size_t)M_max * 6 * 4 : 0),                // 18 cov6
         (gicp ? 21 * n * 4 : 0),                           // 19 hess
         tail_size,                                         // 20 tail sub-chunk sums
-        (K == 0 && !gicp ? 3 * n * 4 : 0),                 // 21 evaluation order: order, ocell, orank
-        (K == 0 && !gicp ? (size_t)kOrderCells * 4 : 0),   // 22 ocount
-        (K == 0 && !gicp ? nb * 2 * kOrderDims * 4 : 0),   // 23 obounds
+        (K == 0 || gicp ? 3 * n * 4 : 0),                  // 21 evaluation order: order, ocell, orank
+        (K == 0 || gicp ? (size_t)kOrderCells * 4 : 0),    // 22 ocount
+        (K == 0 || gicp ? nb * 2 * kOrderDims * 4 : 0),    // 23 obounds
     };
     Layout L{};
     size_t o = 0;
@@ -834,7 +834,7 @@ mcs_status mcs_session_create(mcs_ctx *ctx, int32_t map_id, int32_t N, int32_t M
     ss->stats = (StepStatsDev *)(b + L.off[14]);
     ss->scan8 = (double4 *)(b + L.off[15]);
     ss->copies = (int32_t *)(b + L.off[16]);
-    if (m->K_cap == 0 && m->kind == kGridMap) {
+    if ((m->K_cap == 0 && m->kind == kGridMap) || m->kind == kVoxelMap) {
         ss->order = (int32_t *)(b + L.off[21]);
         ss->ocell = ss->order + N;
         ss->orank = ss->ocell + N;

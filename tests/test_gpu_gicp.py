@@ -1,7 +1,8 @@
 """GPU parity of the GICP likelihood and Gauss-Newton correction (Eq. 2-7).
 
 Stage-wise against the oracle: neighbours exact; l, b and H within 1e-5 / 1e-4
-of their summation scales; the Gauss-Newton step checked with the oracle fed
+of their summation scales (for b and H the sums of the magnitudes of the
+products each entry is made of, which bound FP32 rounding where they cancel); the Gauss-Newton step checked with the oracle fed
 the GPU's H and b.  Points whose voxel choice is within 1e-9 voxel of a face
 (the only place where the FP64 transforms of the two sides could pick
 different voxels) are counted by the oracle, and particles with any are left
@@ -161,3 +162,20 @@ def test_gicp_frames_raise_the_likelihood(ctx):
     first = gicp_step(ctx, c, p0)
     later = gicp_step(ctx, c, dict(p0, iters=3), frames=2)
     assert np.median(later["loglik"]) > np.median(first["loglik"])
+
+
+def test_gicp_evaluation_order_does_not_change_results(ctx):
+    """A GICP session of >= 4096 particles evaluates them grouped by pose cell:
+    each particle's l, H, b and stepped pose are the same as in sessions too
+    small to be reordered (bit for bit), and the grouped session still matches
+    the oracle."""
+    c = configs.keyframes(N=5000, K=8, kf_points=4096, M_rings=4, seed=57, gicp=True)
+    p = dict(c["params"], iters=2, u=0.5, beta=0.0, resample=abi.RESAMPLE_NEVER)
+    whole = gicp_step(ctx, c, p)
+    parts = [gicp_step(ctx, c, p, poses=c["poses"][a:b], kf=c["kf_poses"][a:b])
+             for a, b in ((0, 4000), (4000, 5000))]
+    for k in ("loglik", "poses", "H", "b", "neighbors"):
+        assert np.array_equal(whole[k], np.concatenate([q[k] for q in parts])), k
+    p1 = dict(p, iters=1)
+    out = gicp_step(ctx, c, p1)
+    check_gicp(c, out, p1)
