@@ -1329,7 +1329,7 @@ __device__ __forceinline__ void gicp_tile(const StepDesc &d, int tile)
                 double y[3];
                 const uint32_t rec = gicp_voxel(Rs, ts, nx, ny, nz, nxy, px, py, pz, y);
                 GicpFetch f;
-                const gf4_ptr vr = vrec + 3 * (size_t)rec;
+                const gf4_ptr vr = vrec + 4 * (size_t)rec;   // 64 B per record
                 f.va = vr[0];
                 f.vb = vr[1];
                 f.vc = vr[2];

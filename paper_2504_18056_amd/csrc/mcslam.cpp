@@ -307,7 +307,7 @@ StepDesc make_desc(const Session *s, const float *scan3_dev, int M, const float 
     StepDesc d{};
     d.cells = m->cells;
     d.grid_stride = (int64_t)align_up((size_t)m->records * (m->kind == kVoxelMap
-                                                                ? kVoxelRecordBytes
+                                                                ? kVoxelDeviceBytes
                                                                 : record_bytes(m->desc.dtype)));
     d.gicp = m->kind == kVoxelMap;
     d.cov6 = cov_dev;
@@ -549,7 +549,7 @@ mcs_status mcs_load_gicp_keyframes(mcs_ctx *ctx, int32_t K, const mcs_voxel_desc
         return fail(MCS_EINVAL, "voxel map rows times columns must stay below 2^24");
     mcs_status s = set_device(ctx);
     if (s != MCS_OK) return s;
-    const size_t map_bytes = (size_t)recs * kVoxelRecordBytes;
+    const size_t map_bytes = (size_t)recs * kVoxelDeviceBytes;
     const size_t occ_stride = align_up((size_t)recs);
     if (occ_stride * (size_t)K >= ((size_t)1 << 32) - 1)
         return fail(MCS_EINVAL, "voxel maps hold 2^32 or more voxels in total");
@@ -578,8 +578,12 @@ mcs_status mcs_load_gicp_keyframes(mcs_ctx *ctx, int32_t K, const mcs_voxel_desc
         m->origins_dev = reinterpret_cast<float *>((char *)m->cells + align_up(map_bytes) * K);
         m->occ_dev = reinterpret_cast<uint8_t *>((char *)m->origins_dev + align_up((size_t)K * 3 * sizeof(float)));
         std::vector<uint8_t> occ(occ_stride, 0);
+        std::vector<unsigned char> padded(map_bytes, 0);
         for (int k = 0; k < K && e == hipSuccess; ++k) {
-            e = hipMemcpy((char *)m->cells + align_up(map_bytes) * k, voxels[k], map_bytes,
+            // Records padded to their device stride on the host, then one copy.
+            for (int64_t v = 0; v < recs; ++v)
+                std::memcpy(&padded[(size_t)v * kVoxelDeviceBytes], &voxels[k][(size_t)v * 12], kVoxelRecordBytes);
+            e = hipMemcpy((char *)m->cells + align_up(map_bytes) * k, padded.data(), map_bytes,
                           hipMemcpyHostToDevice);
             // Occupied: a positive point count (the test the kernel makes on the record).
             for (int64_t v = 0; v < recs; ++v) occ[v] = voxels[k][(size_t)v * 12 + 3] > 0.0f ? 1 : 0;

@@ -29,6 +29,10 @@ inline size_t record_bytes(int dtype) { return dtype == MCS_GRID_FP32 ? 32 : 16;
 
 enum MapKind { kGridMap = 0, kVoxelMap = 1 };
 constexpr size_t kVoxelRecordBytes = 48;   // mean (3), count, covariance (6), 2 unused
+// On the device each voxel record takes 64 B (the 48 B above, then padding), so
+// that a record never straddles a 128 B cache line: a wave's record reads
+// touch one line per distinct voxel.
+constexpr size_t kVoxelDeviceBytes = 64;
 
 struct Map {
     int id = 0;
