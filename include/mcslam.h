@@ -182,14 +182,17 @@ mcs_status mcs_memory_in_use(mcs_ctx *ctx, uint64_t *bytes);
  * values: host FP32, nx*ny*nz samples, x fastest, each a likelihood in
  * [0, 1] (MCS_EINVAL for a sample outside it or not finite).  The device keeps the grid
  * in a cell-major layout holding the 8 corner samples of each cell together,
- * converted to desc->dtype.  Returns the map id in *map_id. */
+ * converted to desc->dtype, (nx+1)(ny+1)(nz+1) records in all (32 B each for
+ * FP32, 16 B for FP16/BF16); MCS_EINVAL for 2^32 records or more, MCS_EBUDGET
+ * when they do not fit the context's budget.  Returns the map id in *map_id. */
 mcs_status mcs_init_map(mcs_ctx *ctx, const mcs_grid_desc *desc, const float *values,
                         int32_t *map_id);
 
 /* Load a keyframe map: K local grids, one per keyframe, each in its own
  * keyframe frame (Sec. III-A, "Particle state"; Fig. 2).  All descs must have
  * the same nx, ny, nz, res and dtype; origins may differ.  values[k] is host
- * FP32 for keyframe k, samples in [0, 1] as for mcs_init_map.  Sessions on such a map hold N*K keyframe poses. */
+ * FP32 for keyframe k, samples in [0, 1] as for mcs_init_map.  Sessions on such a map hold N*K keyframe poses.
+ * Each grid's records must fit 4 GiB and (nx+1)(ny+1) stay below 2^24 (MCS_EINVAL otherwise). */
 mcs_status mcs_load_keyframes(mcs_ctx *ctx, int32_t K, const mcs_grid_desc *descs,
                               const float *const *values, int32_t *map_id);
 

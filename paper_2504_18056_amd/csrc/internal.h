@@ -160,6 +160,9 @@ int eval_tail_tiles(int N, int dtype, bool keyframes);
 // Single-grid evaluation tiles resident on the device at once (0 if unknown).
 int eval_round_tiles(int dtype);
 bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe);
+// A single grid read through 64-bit record addresses (beyond one buffer's
+// range, or with rows or slabs of 2^24 records and more).
+bool grid_is_wide(const StepDesc &d);
 
 // Batched steps of many sessions (the serving path).  Work lists in device
 // memory name (descriptor, block) pairs per stage; every stage kernel is

@@ -352,6 +352,18 @@ __device__ __forceinline__ void grid_layout(const StepDesc &d, GridK &g)
     g.eps = d.eps;
 }
 
+// The records of a single grid: a buffer over them (its range capped at 32
+// bits; grids beyond it are read through 64-bit addresses) and their base.
+template <int DT>
+__device__ __forceinline__ void single_grid_records(const StepDesc &d, GridK &g)
+{
+    const uint64_t bytes = grid_records(d.nx, d.ny, d.nz) << record_shift<DT>();
+    g.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(d.cells), (short)0,
+                                             (int)(uint32_t)(bytes < kMaxRecordBytes ? bytes : kMaxRecordBytes),
+                                             kRsrcWord3);
+    g.gbase = static_cast<const char *>(d.cells);
+}
+
 // Cell fractions and record offset of a transformed point.
 struct Pt {
     float fx, fy, fz;      // position inside the cell
@@ -536,7 +548,10 @@ __device__ __forceinline__ Pt prep_point64(const GridK &g, const GridMap64 &gm, 
     const uint32_t rec = BIG ? (uint32_t)ix + g.cx * (uint32_t)iy + g.cxy * (uint32_t)iz
                              : (uint32_t)ix + __umul24(g.cx, (uint32_t)iy) +
                                    __umul24(g.cxy, (uint32_t)iz);
-    p.off = KF ? gm.base + (rec << record_shift<DT>()) : (rec << record_shift<DT>());
+    if constexpr (BIG && !KF)
+        p.off = rec;   // a record index: the record is read through a 64-bit address
+    else
+        p.off = KF ? gm.base + (rec << record_shift<DT>()) : (rec << record_shift<DT>());
     return p;
 }
 
@@ -588,11 +603,15 @@ template <> __device__ __forceinline__ uint32_t cell_xor<2>(const Cell<2> &c)
 }
 
 // Record of a prepared point: from the buffer or, with GLB, through a 64-bit
-// address (an outside point reads a record of the zero layer either way).
-template <int DT, bool GLB>
+// address; with WIDE (a single grid beyond one buffer's range or with slabs of
+// 2^24 records and more) p.off is the record index and the address is formed
+// in 64 bits.  An outside point reads a record of the zero layer either way.
+template <int DT, bool GLB, bool WIDE = false>
 __device__ __forceinline__ void fetch(const GridK &g, const Pt &p, Cell<DT> &c)
 {
-    if (GLB)
+    if (WIDE)
+        load_cell_g<DT>((uint64_t)g.gbase + ((uint64_t)p.off << record_shift<DT>()), c);
+    else if (GLB)
         load_cell_g<DT>((uint64_t)(g.gbase + p.off), c);
     else
         load_cell<DT>(g.rs, p.off, c);
@@ -625,7 +644,7 @@ __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, sc
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             p[k] = prep_point64<DT, BIG, KF>(g, gm, sq[4 * k], sq[4 * k + 1], sq[4 * k + 2]);
-            fetch<DT, GLB>(g, p[k], c[k]);
+            fetch<DT, GLB, BIG && !KF>(g, p[k], c[k]);
             __builtin_amdgcn_sched_barrier(0);
         }
         __builtin_amdgcn_s_setprio(0);
@@ -642,7 +661,7 @@ __device__ __forceinline__ void eval_range64(const GridK &g, scan64_ptr scan, sc
         const d4v s = scan[j];
         const Pt p = prep_point64<DT, BIG, KF>(g, gm, s.x, s.y, s.z);
         Cell<DT> c;
-        fetch<DT, GLB>(g, p, c);
+        fetch<DT, GLB, BIG && !KF>(g, p, c);
         if constexpr (FLOOR) {
             fl ^= cell_xor<DT>(c);
         } else {
@@ -807,9 +826,7 @@ __device__ __forceinline__ void eval_tile(const StepDesc &d, int tile)
 
     GridK g;
     grid_layout(d, g);
-    g.rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<void *>(d.cells), (short)0,
-        (int)((uint32_t)grid_records(d.nx, d.ny, d.nz) << record_shift<DT>()), kRsrcWord3);
+    single_grid_records<DT>(d, g);
     const int M = d.M;
     const int Q = sub_chunk_len(M);
     constexpr int S = kSubChunks / W;      // sub-chunks per wave
@@ -867,9 +884,7 @@ __device__ __forceinline__ void tail_chunk(const StepDesc &d, int tile0, int pas
     const int i = slot_particle(d, (tile0 + rel) * 64 + lane);
     GridK g;
     grid_layout(d, g);
-    g.rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<void *>(d.cells), (short)0,
-        (int)((uint32_t)grid_records(d.nx, d.ny, d.nz) << record_shift<DT>()), kRsrcWord3);
+    single_grid_records<DT>(d, g);
     const int M = d.M, Q = sub_chunk_len(M);
     float t[3], q[4];
     tail_pose(d, i, pass, t, q);
@@ -2615,18 +2630,28 @@ hipError_t launch_pack_predict(const StepDesc &d, hipStream_t st)
     return hipGetLastError();
 }
 
-static bool big_slab(const StepDesc &d)
+// A single grid whose record indices need full 32-bit products (rows or slabs
+// of 2^24 records and more) or whose records pass one buffer's 32-bit byte
+// range: its kernels take BIG (32-bit products, 64-bit record addresses).
+static bool wide_grid(int nx, int ny, int nz, int dtype)
 {
-    return (uint64_t)(d.nx + 1) >= (1u << 24) || (uint64_t)(d.nx + 1) * (d.ny + 1) >= (1u << 24);
+    const bool slab = (uint64_t)(nx + 1) >= (1u << 24) || (uint64_t)(nx + 1) * (ny + 1) >= (1u << 24);
+    return slab || (grid_records(nx, ny, nz) << (dtype == 0 ? 5 : 4)) > (uint64_t)kMaxRecordBytes;
 }
 
-// One grid's records must fit a 32-bit byte range (kMaxRecordBytes); keyframe
-// grids also take the 24-bit index products.
+bool grid_is_wide(const StepDesc &d) { return d.K == 0 && !d.gicp && wide_grid(d.nx, d.ny, d.nz, d.dtype); }
+
+static bool big_slab(const StepDesc &d) { return wide_grid(d.nx, d.ny, d.nz, d.dtype); }
+
+// A keyframe grid's records must fit a 32-bit byte range (kMaxRecordBytes) and
+// take the 24-bit index products; a single grid's record indices must fit 32
+// bits.
 bool grid_supported(int nx, int ny, int nz, int dtype, bool keyframe)
 {
     const uint64_t n_rec = grid_records(nx, ny, nz);
+    if (!keyframe) return n_rec <= (uint64_t)0xFFFFFFFFu;
     const bool slab = (uint64_t)(nx + 1) >= (1u << 24) || (uint64_t)(nx + 1) * (ny + 1) >= (1u << 24);
-    return (n_rec << (dtype == 0 ? 5 : 4)) <= (uint64_t)kMaxRecordBytes && !(keyframe && slab);
+    return (n_rec << (dtype == 0 ? 5 : 4)) <= (uint64_t)kMaxRecordBytes && !slab;
 }
 
 // Tiles of the evaluation kernel (single grid, or keyframe map) resident on

@@ -500,7 +500,7 @@ mcs_status mcs_init_map(mcs_ctx *ctx, const mcs_grid_desc *desc, const float *va
     mcs_status s = validate_desc(desc);
     if (s != MCS_OK) return s;
     if (!grid_supported(desc->nx, desc->ny, desc->nz, desc->dtype, false))
-        return fail(MCS_EINVAL, "grid records exceed a 32-bit byte range");
+        return fail(MCS_EINVAL, "grid has 2^32 or more records");
     if ((s = set_device(ctx)) != MCS_OK) return s;
     const float *v[1] = {values};
     return build_map(ctx, 0, desc, v, map_id);

@@ -579,8 +579,10 @@ mcs_status mcs_server_submit(mcs_server *s, int32_t sid, const float *scan_dev, 
         return fail(MCS_EINVAL, "out-of-grid rule differs from the server's");
     StepDesc probe = make_desc(ss, scan_dev, M, noise_dev, p);
     if (!eval_supported(probe)) return fail(MCS_EINVAL, "map not supported");
-    const bool big = s->mode == MCS_SERVE_BATCHED && s->big_tiles > 0 &&
-                     particle_tiles(ss->N) >= s->big_tiles;
+    // A wide grid (64-bit record addresses) always takes the large-session
+    // lane, whose kernels are the plain session's.
+    const bool big = s->mode == MCS_SERVE_BATCHED &&
+                     ((s->big_tiles > 0 && particle_tiles(ss->N) >= s->big_tiles) || grid_is_wide(probe));
     if (!big && (particle_tiles(ss->N) > s->max_items || weight_blocks(ss->N) > s->max_items ||
                  scan_blocks(M) > s->max_items))
         return fail(MCS_EINVAL, "session work exceeds the server's per-tick work lists");

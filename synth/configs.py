@@ -667,3 +667,31 @@ def wide_slab(N=33000, M=300, seed=1007, n_xy=4098, h=0.05, sigma=0.1):
     poses = np.concatenate([t, q], axis=1).astype(np.float32)
     return dict(name="wide_slab", grid=grid, dims=(n_xy, n_xy, 3), origin=(0.0, 0.0, 0.0), h=h,
                 sigma=sigma, scan=scan, poses=poses, params=step_params(scan, h, sigma, iters=1))
+
+
+def beyond_4gib(N=33000, M=300, seed=1011, n_xy=2048, n_z=34, h=0.05, sigma=0.1):
+    """A grid whose FP32 records pass one buffer's 32-bit byte range (2049^2 x 35
+    records of 32 B: 4.7 GB), with a smooth field in [0.1, 0.9]; half the
+    particles near the top (cell layer 32, records beyond 4 GiB), half near the
+    bottom (layer 2), level within 0.1 deg, at (60, 70) m; a planar scan of
+    radius <= 5 m."""
+    h = f32(h)
+    rng = np.random.default_rng(seed)
+    i = np.arange(n_xy, dtype=np.float64)
+    fx = np.sin(0.07 * i + 0.3)
+    fy = np.cos(0.05 * i)
+    fz = 0.1 * np.cos(0.4 * np.arange(n_z, dtype=np.float64))
+    grid = (0.5 + 0.3 * fy[None, :, None] * fx[None, None, :] + fz[:, None, None]).astype(np.float32)
+    r = rng.uniform(0.5, 5.0, M)
+    a = rng.uniform(0.0, 2.0 * np.pi, M)
+    scan = np.stack([r * np.cos(a), r * np.sin(a), np.zeros(M)], axis=1).astype(np.float32)
+    layer = np.where(np.arange(N) < N // 2, 32.5, 2.5)
+    t = np.stack([60.0 + rng.normal(0.0, 0.5, N), 70.0 + rng.normal(0.0, 0.5, N),
+                  layer * h + rng.normal(0.0, 0.1 * h, N)], axis=1)
+    phi = rng.normal(0.0, math.radians(0.1), (N, 3))
+    q = geo.quat_mul(np.asarray(geo.quat_yaw(0.7))[None, :], geo.quat_from_axis_angle(phi))
+    q = q / np.linalg.norm(q, axis=-1, keepdims=True)
+    q = np.where(q[:, :1] < 0, -q, q)
+    poses = np.concatenate([t, q], axis=1).astype(np.float32)
+    return dict(name="beyond_4gib", grid=grid, dims=(n_xy, n_xy, n_z), origin=(0.0, 0.0, 0.0), h=h,
+                sigma=sigma, scan=scan, poses=poses, params=step_params(scan, h, sigma, iters=1))

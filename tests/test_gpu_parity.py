@@ -277,6 +277,22 @@ def test_grid_slab_beyond_24_bits(ctx, dtype, oob):
     print("wide slab dtype %d: %s" % (dtype, rep))
 
 
+def test_grid_beyond_4gib(ctx):
+    # FP32 records past one buffer's 32-bit byte range (4.7 GB): record
+    # addresses are formed in 64 bits.  Half the particles read records beyond
+    # 4 GiB, half below; N = 33,000 runs whole rounds and a split tail.
+    c = configs.beyond_4gib()
+    nx, ny, nz = c["dims"]
+    assert (nx + 1) * (ny + 1) * (nz + 1) * 32 > 1 << 32
+    p = dict(c["params"], u=0.29, beta=0.01, resample=abi.RESAMPLE_ALWAYS)
+    print("grid beyond 4 GiB N=%d M=%d" % (c["poses"].shape[0], c["scan"].shape[0]), flush=True)
+    out = one_step(ctx, c, p)
+    rep = {}
+    full_check(c, out, p, report=rep)
+    assert np.all(out["loglik"] > c["scan"].shape[0] * math.log(0.1))   # points inside the grid
+    print("grid beyond 4 GiB: %s" % rep)
+
+
 def test_evaluation_order_does_not_change_results(ctx):
     """Sessions of >= 4096 particles evaluate them grouped by pose cell; each
     particle's l, g and stepped pose are the same as in sessions too small to
