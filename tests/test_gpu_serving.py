@@ -234,3 +234,41 @@ def test_batched_record_types_and_skip_same_alone(ctx, dtype, oob):
         for s in sessions:
             abi.mcs_session_destroy(ctx, s["sid"])
             abi.mcs_release_map(ctx, s["mid"])
+
+
+def test_wide_grid_session_in_the_batched_server(ctx):
+    # A grid whose slabs hold 2^24 records or more needs the BIG kernels, which
+    # the batched tick kernels do not take: such a session runs in the
+    # large-session lane, with the same results as stepped alone, beside a
+    # session that runs in the ticks.
+    frames = 2
+    w = configs.wide_slab(N=1000, M=300)
+    rng = np.random.default_rng(5)
+    mid = abi.mcs_init_map(ctx, abi.grid_desc(w["dims"], w["origin"], w["h"], abi.GRID_FP16), w["grid"])
+    sid = abi.mcs_session_create(ctx, mid, w["poses"], M_max=300)
+    scans = torch.from_numpy(np.stack([w["scan"], w["scan"] + rng.normal(0, 0.01, w["scan"].shape).astype(np.float32)])).to(DEV)
+    noise = torch.from_numpy((rng.normal(size=(frames, 1000, 6)) * 0.005).astype(np.float32)).to(DEV)
+    wide = dict(cfg=w, N=1000, M=300, mid=mid, sid=sid, scans=scans, noise=noise,
+                params=[dict(w["params"], iters=2, u=0.3 + 0.2 * f, beta=0.01, resample=abi.RESAMPLE_ALWAYS)
+                        for f in range(frames)])
+    torch.cuda.synchronize()
+    sessions = [wide] + make_sessions(ctx, [(1000, 8, 64, 221)], dtype=abi.GRID_FP16, frames=frames)
+    try:
+        ref = run_alone(ctx, sessions, frames)
+        for s in sessions:
+            reset(ctx, s)
+        srv = abi.mcs_server_create(ctx, mode=abi.SERVE_BATCHED, dtype=abi.GRID_FP16, max_batch=8)
+        try:
+            for f in range(frames):
+                for s in sessions:
+                    abi.mcs_server_submit(srv, s["sid"], s["scans"][f].data_ptr(), s["M"], s["params"][f],
+                                          noise_dev_ptr=s["noise"][f].data_ptr())
+                abi.mcs_server_drain(srv)
+                for k, s in enumerate(sessions):
+                    assert_same(ref[k][f], snapshot(ctx, s), "session %d frame %d" % (k, f))
+        finally:
+            abi.mcs_server_destroy(srv)
+    finally:
+        for s in sessions:
+            abi.mcs_session_destroy(ctx, s["sid"])
+            abi.mcs_release_map(ctx, s["mid"])
