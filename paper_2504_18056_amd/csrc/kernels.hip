@@ -2277,6 +2277,16 @@ __device__ __forceinline__ void order_coords(const StepDesc &d, int i, float c[k
     c[5] = sg * d.pose[6 * N + i];
 }
 
+// Blocks of k_order_bounds: at most kOrderBoundBlocks, each taking every
+// (blocks x kWeightBlock)-th particle, so that every block of k_order_cell
+// reduces a bounded number of partial ranges whatever N is.
+constexpr int kOrderBoundBlocks = 256;
+__host__ __device__ inline int order_bound_blocks(int N)
+{
+    const int nb = weight_blocks(N);
+    return nb < kOrderBoundBlocks ? nb : kOrderBoundBlocks;
+}
+
 // Per block: the low and high ends of each coordinate over its particles
 // (non-finite values are left out), written as the block's partial range;
 // the blocks also clear the cell counts.
@@ -2285,14 +2295,18 @@ __device__ __forceinline__ void order_bounds_blk(const StepDesc &d, int b)
     constexpr int B = kWeightBlock;
     __shared__ float lo[B], hi[B];
     const int tid = threadIdx.x;
-    const int i = b * B + tid;
-    float c[kOrderDims];
-    const bool ok = i < d.N;
-    if (ok) order_coords(d, i, c);
+    const int stride = order_bound_blocks(d.N) * B;
+    float tlo[kOrderDims], thi[kOrderDims];
+    for (int k = 0; k < kOrderDims; ++k) { tlo[k] = INFINITY; thi[k] = -INFINITY; }
+    for (int i = b * B + tid; i < d.N; i += stride) {
+        float c[kOrderDims];
+        order_coords(d, i, c);
+        for (int k = 0; k < kOrderDims; ++k)
+            if (fabsf(c[k]) <= 1e30f) { tlo[k] = fminf(tlo[k], c[k]); thi[k] = fmaxf(thi[k], c[k]); }
+    }
     for (int k = 0; k < kOrderDims; ++k) {
-        const bool fin = ok && fabsf(c[k]) <= 1e30f;
-        lo[tid] = fin ? c[k] : INFINITY;
-        hi[tid] = fin ? c[k] : -INFINITY;
+        lo[tid] = tlo[k];
+        hi[tid] = thi[k];
         __syncthreads();
         for (int st = B / 2; st > 0; st >>= 1) {
             if (tid < st) {
@@ -2307,7 +2321,6 @@ __device__ __forceinline__ void order_bounds_blk(const StepDesc &d, int b)
         }
         __syncthreads();
     }
-    const int stride = weight_blocks(d.N) * B;
     for (int k = b * B + tid; k < kOrderCells; k += stride) d.ocount[k] = 0;
 }
 
@@ -2320,7 +2333,7 @@ __device__ __forceinline__ void order_cell_blk(const StepDesc &d, int b)
     __shared__ float lo[kOrderDims][B], hi[kOrderDims][B];
     __shared__ float base[kOrderDims], scale[kOrderDims];
     const int tid = threadIdx.x;
-    const int nb = weight_blocks(d.N);
+    const int nb = order_bound_blocks(d.N);
     for (int k = 0; k < kOrderDims; ++k) {
         float l = INFINITY, h = -INFINITY;
         for (int q = tid; q < nb; q += B) {
@@ -2846,7 +2859,7 @@ hipError_t launch_order(const StepDesc &d, hipStream_t st)
 {
     if (!d.order) return hipSuccess;
     const dim3 nb((unsigned)weight_blocks(d.N));
-    hipLaunchKernelGGL(k_order_bounds, nb, dim3(kWeightBlock), 0, st, d);
+    hipLaunchKernelGGL(k_order_bounds, dim3((unsigned)order_bound_blocks(d.N)), dim3(kWeightBlock), 0, st, d);
     hipLaunchKernelGGL(k_order_cell, nb, dim3(kWeightBlock), 0, st, d);
     hipLaunchKernelGGL(k_order_prefix, dim3(1), dim3(kOrderPrefixBlock), 0, st, d);
     hipLaunchKernelGGL(k_order_scatter, nb, dim3(kWeightBlock), 0, st, d);

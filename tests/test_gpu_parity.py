@@ -205,6 +205,28 @@ def test_corridors_full_scale_sampled(ctx):
     check_weights_resample(c["logw"], out["loglik"], 1.0, p["u"], out, abi.RESAMPLE_ESS)
 
 
+def test_corridors_four_million_particles_sampled(ctx):
+    """N = 2^22 + 37 (65,537 tiles, the last one ragged) on the corridors map:
+    sampled particles vs the oracle, and the weights and resampling of all of
+    them; the evaluation order's bounds reduce over at most 256 partial ranges
+    at any N."""
+    N = (1 << 22) + 37
+    c = configs.corridors(N=N, n_frames=2)
+    p = dict(c["params"], iters=1, u=float(c["u"][0]), beta=1.0, resample=abi.RESAMPLE_ESS)
+    print("corridors N=%d M=%d" % (N, c["scan"].shape[0]), flush=True)
+    out = one_step(ctx, c, p)
+    rng = np.random.default_rng(1)
+    idx = np.union1d(np.union1d(rng.choice(N, 256, replace=False), np.arange(N - 101, N)), np.arange(64))
+    ref = oracle.evaluate(c["grid"], c["dims"], c["origin"], c["h"], p["eps"], c["scan"],
+                          c["poses"][idx], delta=DELTA)
+    rep = {}
+    check_eval(out["loglik"][idx], out["grad"][idx], ref, idx=np.arange(idx.size), report=rep)
+    print("corridors 4M sampled:", rep)
+    anc = out["parents"]
+    check_step(c["poses"][anc], out["grad"][anc], out["poses"], p)
+    check_weights_resample(c["logw"], out["loglik"], 1.0, p["u"], out, abi.RESAMPLE_ESS)
+
+
 def test_rejects_samples_outside_unit_range_and_tiny_eps(ctx, box_room):
     """Samples are likelihoods in [0, 1] and eps lies in [1e-5, 1]: the point loop
     multiplies up to four factors G + eps, which must stay normal FP32 numbers."""
